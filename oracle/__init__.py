@@ -1,0 +1,214 @@
+"""CPU oracle for the ENSEI secure-convolution hot path: ctypes wrapper.
+
+TEST INFRASTRUCTURE ONLY. Only ``tests/``, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package. It shares no code
+with the GPU library (``paper_2003_05328_amd``) and never imports it; the
+product path fails loudly rather than falling back here.
+
+Every function takes and returns numpy arrays and follows the plain
+definitions written out in ``ensei_oracle.c`` (see that file's header for the
+conventions and the paper passages they restate).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libensei_oracle.so")
+
+u64, i64, i32, vp = C.c_uint64, C.c_int64, C.c_int, C.c_void_p
+
+_SIG = {
+    "or_is_prime": (C.c_int, [u64]),
+    "or_primitive_root": (u64, [u64]),
+    "or_root_of_unity": (u64, [u64, u64, C.c_int]),
+    "or_inverse": (u64, [u64, u64]),
+    "or_dft2d_direct": (None, [u64, i64, i32, i32, vp, vp, C.c_int]),
+    "or_ntt2d": (None, [u64, i64, i32, i32, vp, vp, C.c_int]),
+    "or_weight_prep": (None, [u64, i32, i32, i32, i32, i32, i32, vp, vp]),
+    "or_cyclic_conv": (None, [u64, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp]),
+    "or_splitmix64": (u64, [u64, u64]),
+    "or_delta": (u64, [u64]),
+    "or_encrypt": (None, [u64, i64, i32, vp, vp, vp, u64, u64, vp]),
+    "or_phase": (u64, [i32, vp, vp]),
+    "or_decrypt": (None, [u64, i64, i32, vp, vp, vp]),
+    "or_homconv": (None, [u64, i32, i32, i32, i64, i32, vp, vp, vp, vp]),
+    "or_homconv_select": (None, [u64, i32, i32, i32, i64, i32, vp, vp, vp, i64, vp, vp]),
+    "or_server_share": (None, [u64, i64, i32, i32, vp, vp]),
+    "or_set_threads": (C.c_int, [C.c_int]),
+}
+
+
+def _c(a: np.ndarray, dtype) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Oracle:
+    """The oracle functions bound to one build of ``ensei_oracle.c``."""
+
+    def __init__(self, lib_path: str = _LIB_PATH):
+        if lib_path == _LIB_PATH and not os.path.exists(lib_path):
+            from . import build as _b
+
+            _b.build()
+        lib = C.CDLL(lib_path)
+        for name, (res, args) in _SIG.items():
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        self.lib = lib
+        self.path = lib_path
+
+    def set_threads(self, k: int) -> int:
+        """Thread count for the oracle's OpenMP loops; returns the count in effect."""
+        return self.lib.or_set_threads(int(k))
+
+    def is_prime(self, p: int) -> bool:
+        return bool(self.lib.or_is_prime(p))
+
+    def primitive_root(self, p: int) -> int:
+        return int(self.lib.or_primitive_root(p))
+
+    def root_of_unity(self, p: int, N: int, inverse: bool = False) -> int:
+        return int(self.lib.or_root_of_unity(p, N, int(inverse)))
+
+    def inverse(self, a: int, p: int) -> int:
+        return int(self.lib.or_inverse(a, p))
+
+    def delta(self, p: int) -> int:
+        return int(self.lib.or_delta(p))
+
+    def splitmix64(self, seed: int, k: int) -> int:
+        return int(self.lib.or_splitmix64(seed % 2**64, k % 2**64))
+
+    def dft2d_direct(self, x: np.ndarray, p: int, inverse: bool = False) -> np.ndarray:
+        """O(F^2) double-sum 2D DFT over Z_p of x[..., H, W] (uint32)."""
+        x = _c(x, np.uint32)
+        H, W = x.shape[-2:]
+        out = np.empty_like(x)
+        self.lib.or_dft2d_direct(p, x.size // (H * W), H, W, _p(x), _p(out), int(inverse))
+        return out
+
+    def ntt2d(self, x: np.ndarray, p: int, inverse: bool = False) -> np.ndarray:
+        """2D transform of x[..., H, W] evaluated axis by axis (plain 1D sums)."""
+        x = _c(x, np.uint32)
+        H, W = x.shape[-2:]
+        out = np.empty_like(x)
+        self.lib.or_ntt2d(p, x.size // (H * W), H, W, _p(x), _p(out), int(inverse))
+        return out
+
+    def weight_prep(self, w: np.ndarray, H: int, W: int, p: int) -> np.ndarray:
+        """w[Cout][Cin][kh][kw] int32 -> W^ [Cout][Cin][H*W] uint32."""
+        w = _c(w, np.int32)
+        Cout, Cin, kh, kw = w.shape
+        out = np.empty((Cout, Cin, H * W), dtype=np.uint32)
+        self.lib.or_weight_prep(p, Cout, Cin, kh, kw, H, W, _p(w), _p(out))
+        return out
+
+    def cyclic_conv(self, x: np.ndarray, w: np.ndarray, p: int) -> np.ndarray:
+        """x[B][Cin][H][W] residues, w[Cout][Cin][kh][kw] ints -> y[B][Cout][H][W] mod p."""
+        x = _c(x, np.uint32)
+        w = _c(w, np.int32)
+        B, Cin, H, W = x.shape
+        Cout, Cin2, kh, kw = w.shape
+        assert Cin == Cin2
+        y = np.empty((B, Cout, H, W), dtype=np.uint32)
+        self.lib.or_cyclic_conv(p, B, Cin, Cout, H, W, kh, kw, _p(x), _p(w), _p(y))
+        return y
+
+    def encrypt(self, m, s, e, seed_a: int, p: int, ct_index0: int = 0) -> np.ndarray:
+        """m[N] in [0,p), s[n] ternary, e[N] -> ct[N][n+1] uint64."""
+        m = _c(m, np.uint32).reshape(-1)
+        e = _c(e, np.int32).reshape(-1)
+        s = _c(s, np.int8)
+        n = s.shape[0]
+        ct = np.empty((m.shape[0], n + 1), dtype=np.uint64)
+        self.lib.or_encrypt(p, m.shape[0], n, _p(m), _p(s), _p(e), seed_a % 2**64, ct_index0 % 2**64, _p(ct))
+        return ct
+
+    def phase(self, ct_row: np.ndarray, s: np.ndarray) -> int:
+        row = _c(ct_row, np.uint64)
+        s = _c(s, np.int8)
+        return int(self.lib.or_phase(s.shape[0], _p(row), _p(s)))
+
+    def decrypt(self, ct: np.ndarray, s: np.ndarray, p: int) -> np.ndarray:
+        """ct[N][n+1] -> m[N] uint32."""
+        s = _c(s, np.int8)
+        n = s.shape[0]
+        ct = _c(ct, np.uint64).reshape(-1, n + 1)
+        m = np.empty(ct.shape[0], dtype=np.uint32)
+        self.lib.or_decrypt(p, ct.shape[0], n, _p(ct), _p(s), _p(m))
+        return m
+
+    def homconv(self, ct_in, w_hat, r, p: int) -> np.ndarray:
+        """ct_in[B][Cin][F][n+1], w_hat[Cout][Cin][F], r[B][Cout][F] -> ct_out[B][Cout][F][n+1]."""
+        ct_in = _c(ct_in, np.uint64)
+        w_hat = _c(w_hat, np.uint32)
+        r = _c(r, np.uint32)
+        B, Cin, F, n1 = ct_in.shape
+        Cout = w_hat.shape[0]
+        assert w_hat.shape == (Cout, Cin, F) and r.shape == (B, Cout, F)
+        out = np.empty((B, Cout, F, n1), dtype=np.uint64)
+        self.lib.or_homconv(p, B, Cin, Cout, F, n1 - 1, _p(ct_in), _p(w_hat), _p(r), _p(out))
+        return out
+
+    def homconv_select(self, ct_in, w_hat, r, sel, p: int) -> np.ndarray:
+        """Output rows for the (b, o, f) triples in sel[k] -> [k][n+1]."""
+        ct_in = _c(ct_in, np.uint64)
+        w_hat = _c(w_hat, np.uint32)
+        r = _c(r, np.uint32)
+        sel = _c(sel, np.int64).reshape(-1, 3)
+        B, Cin, F, n1 = ct_in.shape
+        Cout = w_hat.shape[0]
+        out = np.empty((sel.shape[0], n1), dtype=np.uint64)
+        self.lib.or_homconv_select(p, B, Cin, Cout, F, n1 - 1, _p(ct_in), _p(w_hat), _p(r), sel.shape[0], _p(sel), _p(out))
+        return out
+
+    def server_share(self, r, H: int, W: int, p: int) -> np.ndarray:
+        """r[..., F] -> s_B[..., H, W] = INTT2D(-r mod p)."""
+        r = _c(r, np.uint32)
+        batch = r.size // (H * W)
+        out = np.empty(r.shape[:-1] + (H, W), dtype=np.uint32)
+        self.lib.or_server_share(p, batch, H, W, _p(r), _p(out))
+        return out
+
+    def fdsc_round0(self, inp, p: int):
+        """The whole secure convolution of one layer (Fig. 2, round 0) on the CPU.
+
+        Returns a dict with every intermediate: x_hat, w_hat, ct_in, ct_out, m,
+        s_a (the client's spatial share) and s_b (the server's spatial share).
+        """
+        S = inp.shape
+        x_hat = self.ntt2d(inp.x, p).reshape(S.B, S.Cin, S.F)
+        w_hat = self.weight_prep(inp.w, S.H, S.W, p)
+        ct_in = self.encrypt(x_hat, inp.s, inp.e, inp.seed_a, p).reshape(S.B, S.Cin, S.F, S.n + 1)
+        ct_out = self.homconv(ct_in, w_hat, inp.r, p)
+        m = self.decrypt(ct_out, inp.s, p).reshape(S.B, S.Cout, S.F)
+        s_a = self.ntt2d(m.reshape(S.B, S.Cout, S.H, S.W), p, inverse=True)
+        s_b = self.server_share(inp.r, S.H, S.W, p)
+        return dict(x_hat=x_hat, w_hat=w_hat, ct_in=ct_in, ct_out=ct_out, m=m, s_a=s_a, s_b=s_b)
+
+
+_default: Oracle | None = None
+
+
+def default() -> Oracle:
+    """The oracle built from the committed source (built on first use)."""
+    global _default
+    if _default is None:
+        _default = Oracle()
+    return _default
+
+
+def __getattr__(name):
+    # module-level access (oracle.ntt2d, ...) forwards to the default build
+    if name.startswith("_"):
+        raise AttributeError(name)
+    return getattr(default(), name)

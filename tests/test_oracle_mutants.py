@@ -1,0 +1,72 @@
+"""Planted mistakes in the CPU oracle are caught by its pins (no GPU).
+
+Each mutant is a copy of ``oracle/ensei_oracle.c`` with one plausible bug
+(a dropped term, a wrong sign, a wrong index, a transposed operand, a missing
+reduction) compiled into a temporary library. The test asserts that at least
+one pin of ``tests/pins.py`` fails on it, so the pins constrain every part of
+the oracle rather than only its own restatement.
+"""
+import os
+import subprocess
+
+import pytest
+
+import oracle
+from tests import pins
+
+SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "ensei_oracle.c")
+
+MUTANTS = {
+    "root_not_inverted": ("return inverse ? powmod(w, p - 2, p) : w;", "return w;"),
+    "primitive_root_unchecked": ("if (ok) return g;", "return g;"),
+    "intt_missing_scale": (
+        "    uint64_t scale = inverse ? or_inverse((uint64_t)H * (uint64_t)W % p, p) : 1;\n    int64_t F = (int64_t)H * W;\n    uint64_t *powH",
+        "    uint64_t scale = 1;\n    int64_t F = (int64_t)H * W;\n    uint64_t *powH",
+    ),
+    "row_uses_column_root": ("powW[(int64_t)i2 * k2 % W]", "powH[(int64_t)i2 * k2 % H]"),
+    "direct_dft_wrong_index": ("powmod(wH, (uint64_t)i1 * k1, p)", "powmod(wH, (uint64_t)i1 * k2, p)"),
+    "conv_correlation_not_convolution": ("int r1 = ((m1 - j1) % H + H) % H", "int r1 = ((m1 + j1) % H + H) % H"),
+    "conv_weight_not_reduced": ("if (wv < 0) wv += (int64_t)p;\n                                int r1", "int r1"),
+    "filter_transposed_in_grid": ("w_hat[t * F + a * W + b] = (uint32_t)v;", "w_hat[t * F + b * W + a] = (uint32_t)v;"),
+    "splitmix_wrong_shift": ("z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;", "z = (z ^ (z >> 29)) * 0x94d049bb133111ebULL;"),
+    "enc_counter_off_by_one": ("gidx * (uint64_t)n + (uint64_t)j + 1)", "gidx * (uint64_t)n + (uint64_t)j)"),
+    "enc_dropped_error": ("row[n] = dot + (uint64_t)(int64_t)e[c] + delta * (uint64_t)m[c];", "row[n] = dot + delta * (uint64_t)m[c];"),
+    "enc_wrong_key_sign": (
+        "            if (s[j] == 1) dot += a;\n            else if (s[j] == -1) dot -= a;",
+        "            if (s[j] == 1) dot += a;\n            else if (s[j] == -1) dot += a;",
+    ),
+    "delta_rounded_up": ("return (uint64_t)((((u128)1) << 64) / p);", "return (uint64_t)((((u128)1) << 64) / p + 1);"),
+    "dec_truncates_not_rounds": ("u128 t = (u128)phi * p + (((u128)1) << 63);", "u128 t = (u128)phi * p;"),
+    "dec_missing_final_mod": ("m[c] = (uint32_t)(v % p);", "m[c] = (uint32_t)v;"),
+    "dec_phase_sign": ("return row[n] - dot;", "return row[n] + dot;"),
+    "homconv_mask_on_word0": ("out_row[n] += or_delta(p)", "out_row[0] += or_delta(p)"),
+    "homconv_weight_transposed": ("w_hat[(o * Cin + i) * F + f]", "w_hat[(i * Cout + o) * F + f]"),
+    "homconv_mask_missing_delta": ("out_row[n] += or_delta(p) * (uint64_t)r", "out_row[n] += (uint64_t)r"),
+    "server_share_not_negated": ("s_b[k] = (uint32_t)((p - r[k] % p) % p);", "s_b[k] = (uint32_t)(r[k] % p);"),
+}
+
+
+def _build(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, f"mutation site for {name} not found"
+    mutated = src.replace(old, new)
+    assert mutated != src
+    c_path = tmp_path / f"{name}.c"
+    so_path = tmp_path / f"lib_{name}.so"
+    c_path.write_text(mutated)
+    subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-fopenmp", str(c_path), "-o", str(so_path)], check=True)
+    return oracle.Oracle(str(so_path))
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    orc = _build(tmp_path, name, old, new)
+    caught_by = None
+    for check in pins.ALL_CHECKS:
+        try:
+            check(orc)
+        except (AssertionError, ValueError, IndexError, OverflowError):
+            caught_by = check.__name__
+            break
+    assert caught_by, f"planted mistake {name!r} passed every pin"
