@@ -1,0 +1,185 @@
+/*
+ * ensei.h — C ABI of the MI355X (gfx950) library for the data-parallel hot
+ * path of ENSEI's frequency-domain secure convolution (Bian et al., "ENSEI:
+ * Efficient Secure Inference via Frequency-Domain Homomorphic Convolution for
+ * Privacy-Preserving Visual Recognition", CVPR 2020).
+ *
+ * One secure convolution (Fig. 2, round 0) is, with p one prime used as NTT,
+ * share and plaintext modulus and q = 2^64 the ciphertext modulus:
+ *   client:  x^ = NTT2D(x)                 ensei_ntt2d      (Fig. 2 line 1)
+ *            ct_in = Enc(x^, s)            ensei_encrypt    (Fig. 2 line 2)
+ *   server:  W^ = NTT2D(pad(w))            ensei_weight_prep + ensei_pack_weights (setup)
+ *            ct_out = sum_i W^ ct_in + Delta r   ensei_homconv (lines 3-4)
+ *   client:  m = Dec(ct_out, s)            ensei_decrypt    (line 5)
+ *            s_A = INTT2D(m)               ensei_intt2d     (line 6)
+ *   server:  s_B = INTT2D(-r)              ensei_server_share (line 6)
+ * and s_A + s_B = x (*) w mod p (Sec. 4.1.1, Appendix A).
+ *
+ * Common rules for every call below:
+ *   - every array pointer is a DEVICE pointer on the context's device, owned
+ *     by the caller, who keeps it alive until the work queued on `stream`
+ *     has finished; the library never frees, retains or allocates on a call;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *     every call only enqueues work on it and returns without synchronising;
+ *   - arrays are dense, row-major, with the shapes stated per call;
+ *   - argument checks run on the host before any launch; a call that returns
+ *     an error has enqueued nothing. Errors raised later by the device are
+ *     not reported by these calls (a HIP launch failure is, as ENSEI_ERR_HIP);
+ *   - the current HIP device must be the context's device (ENSEI_ERR_DEVICE);
+ *   - unless stated, outputs must not overlap inputs (ENSEI_ERR_OVERLAP).
+ */
+#ifndef ENSEI_H
+#define ENSEI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum ensei_status {
+    ENSEI_OK = 0,
+    ENSEI_ERR_ARG = -1,     /* null pointer, non-positive size, bad flag */
+    ENSEI_ERR_SHAPE = -2,   /* H or W not a power of two in [2, 128], or not dividing p-1 */
+    ENSEI_ERR_MODULUS = -3, /* p not prime, or outside [3, 2^22) */
+    ENSEI_ERR_ALIGN = -4,   /* pointer not aligned to its element size */
+    ENSEI_ERR_OVERLAP = -5, /* output range overlaps an input range */
+    ENSEI_ERR_LIMIT = -6,   /* size beyond the supported range (see each call) */
+    ENSEI_ERR_DEVICE = -7,  /* current HIP device is not the context's device */
+    ENSEI_ERR_HIP = -8      /* HIP runtime error (allocation at create, launch failure) */
+};
+
+/* Largest supported sizes. */
+#define ENSEI_MAX_DIM 128        /* H and W */
+#define ENSEI_MAX_LWE_N 16384    /* LWE dimension n */
+#define ENSEI_MAX_CIN 32768      /* input channels of HomConv (keeps i32 limb sums exact) */
+#define ENSEI_MAX_COUT 65536     /* output channels of HomConv */
+
+typedef struct ensei_ctx ensei_ctx;
+
+/* Creates a context for prime modulus p on HIP device `device`: checks that
+ * p is prime with 3 <= p < 2^22 (the bound keeps every lazily reduced residue
+ * below 2^24, the width of the 24-bit multipliers the transforms use), finds
+ * the smallest primitive root g, and uploads the twiddle tables
+ * omega_L^j = g^((p-1)/L * j) for every power-of-two L <= 128 dividing p-1
+ * (Eq. (ntt_transform_eq)). Delta = floor(2^64 / p) (Eq. (bfv_enc), q = 2^64).
+ * Allocates a few KB of device memory; this is the only allocating call.
+ * On error *out is set to NULL. */
+int ensei_ctx_create(ensei_ctx **out, uint32_t p, int device);
+
+/* Frees the context (NULL is a no-op). The caller must have finished all
+ * work that uses it. */
+int ensei_ctx_destroy(ensei_ctx *ctx);
+
+/* Static human-readable text for a status code. */
+const char *ensei_status_str(int status);
+
+/* The context's p, Delta = floor(2^64/p) and largest usable transform size. */
+uint32_t ensei_ctx_modulus(const ensei_ctx *ctx);
+uint64_t ensei_ctx_delta(const ensei_ctx *ctx);
+int ensei_ctx_max_dim(const ensei_ctx *ctx);
+
+/* ----------------------------------------------------------- transforms --
+ * Cyclic 2D NTT over Z_p of `batch` channels, each an H x W grid
+ * (Sec. 4.1, "Line 1-3": 2D DFT of the padded input; Eq. (ntt_transform_eq)
+ * along both axes):
+ *   out[t][k1*W + k2] = sum_{i1<H, i2<W} in[t][i1*W + i2]
+ *                       * omega_H^(i1*k1) * omega_W^(i2*k2)  mod p,
+ * with omega_N = g^((p-1)/N). in: uint32 [batch][H][W], every value < p;
+ * out: uint32 [batch][H*W], flattened row-major (f = k1*W + k2), values in
+ * [0, p). H, W: powers of two in [2, min(128, ctx max dim)].
+ * In-place (in == out) is allowed; other overlap is not. */
+int ensei_ntt2d(ensei_ctx *ctx, const uint32_t *in, uint32_t *out, int64_t batch, int H, int W,
+                void *stream);
+
+/* The inverse (Sec. 4.1, "Line 4-6"): omega^-1 and a final factor (H W)^-1:
+ *   out[t][i1][i2] = (HW)^-1 sum_{k1,k2} in[t][k1*W + k2]
+ *                    * omega_H^(-i1*k1) * omega_W^(-i2*k2)  mod p.
+ * Same layouts and rules as ensei_ntt2d (in: [batch][H*W] values < p;
+ * out: [batch][H][W]). */
+int ensei_intt2d(ensei_ctx *ctx, const uint32_t *in, uint32_t *out, int64_t batch, int H, int W,
+                 void *stream);
+
+/* The server's spatial share s_B = INTT2D(-r mod p) of HomShare
+ * (Eq. (homshare); Sec. 4.1, "Line 4-6"), for masks r: uint32 [batch][H*W]
+ * with values < p; s_b: uint32 [batch][H][W]. The client's share
+ * s_A = INTT2D(Dec(ct_out)) then satisfies s_A + s_B = x (*) w mod p.
+ * In-place allowed. */
+int ensei_server_share(ensei_ctx *ctx, const uint32_t *r, uint32_t *s_b, int64_t batch, int H, int W,
+                       void *stream);
+
+/* ---------------------------------------------------------- weight prep --
+ * Server setup (Sec. 4.1, "Line 3-4"): each filter w[o][i] (kh x kw signed
+ * integers) is reduced mod p, zero-padded into the top-left kh x kw corner
+ * of the H x W grid, and transformed by NTT2D:
+ *   w_hat[o][i][f] = NTT2D(pad(w[o][i] mod p))[f].
+ * w: int32 [Cout][Cin][kh][kw]; w_hat: uint32 [Cout][Cin][H*W] in [0, p).
+ * 1 <= kh <= H, 1 <= kw <= W. */
+int ensei_weight_prep(ensei_ctx *ctx, const int32_t *w, int Cout, int Cin, int kh, int kw, int H, int W,
+                      uint32_t *w_hat, void *stream);
+
+/* Bytes of the packed-weight buffer ensei_pack_weights writes:
+ * F * ceil(Cin/16) * roundup(Cout,16) * 48. Returns 0 for invalid sizes. */
+size_t ensei_wpack_bytes(int Cout, int Cin, int64_t F);
+
+/* Packs transformed weights for ensei_homconv: every W^[o][i][f] (the
+ * integer in [0, p), p < 2^22) is written as three signed bytes
+ * d0 + 2^8 d1 + 2^16 d2 with d0, d1, d2 in [-128, 127] (balanced base-256
+ * digits), grouped per frequency as
+ *   w_pack[f][i/16][o][d][i%16]   (int8; channels and rows zero-padded),
+ * the operand layout of the i8 matrix-core contraction in ensei_homconv.
+ * w_hat: uint32 [Cout][Cin][F]; w_pack: ensei_wpack_bytes(Cout, Cin, F)
+ * bytes, 16-byte aligned. */
+int ensei_pack_weights(ensei_ctx *ctx, const uint32_t *w_hat, int Cout, int Cin, int64_t F, int8_t *w_pack,
+                       void *stream);
+
+/* ------------------------------------------------------------------ Enc --
+ * LWE encryption of num_ct plaintexts m[c] < p under the ternary key s
+ * (Eq. (bfv_enc) with one coefficient per ciphertext; q = 2^64):
+ *   a_j = SplitMix64 output number (ct_index0 + c)*n + j + 1 of the
+ *         generator seeded with seed_a, for j < n (the uniform "encryption
+ *         constants" the paper generates offline, Sec. 5.1);
+ *   b   = sum_j s_j a_j + e[c] + Delta * m[c]  mod 2^64;
+ *   ct[c] = [a_0, ..., a_{n-1}, b].
+ * m: uint32 [num_ct]; s: int8 [n] in {-1, 0, 1}; e: int32 [num_ct];
+ * ct: uint64 [num_ct][n+1] (8-byte aligned). 1 <= n <= ENSEI_MAX_LWE_N.
+ * Encrypting a slice with ct_index0 = its first global index reproduces the
+ * same words as one call over the whole range. */
+int ensei_encrypt(ensei_ctx *ctx, const uint32_t *m, const int8_t *s, const int32_t *e, int64_t num_ct, int n,
+                  uint64_t seed_a, uint64_t ct_index0, uint64_t *ct, void *stream);
+
+/* -------------------------------------------------------------- HomConv --
+ * Server-side homomorphic convolution in the frequency domain: the
+ * homomorphic Hadamard product with the transformed filters, summed over
+ * input channels, then HomShare's mask (Fig. 2 lines 3-4; Eq. (homshare)):
+ *   ct_out[b][o][f][j] = sum_i W^[o][i][f] * ct_in[b][i][f][j]  mod 2^64,  j <= n
+ *   ct_out[b][o][f][n] += Delta * r[b][o][f]                     mod 2^64
+ * so Dec(ct_out[b][o][f]) = (sum_i W^ x^ + r) mod p and the server keeps -r.
+ * ct_in: uint64 [batch][Cin][F][n+1]; w_pack: from ensei_pack_weights for
+ * (Cout, Cin, F); r: uint32 [batch][Cout][F] (< p); ct_out: uint64
+ * [batch][Cout][F][n+1]. 1 <= Cin <= ENSEI_MAX_CIN, 1 <= Cout <= ENSEI_MAX_COUT,
+ * 1 <= n <= ENSEI_MAX_LWE_N. Runs on the i8 matrix cores (signed-byte limbs
+ * of both operands, exact i32 sums, recombined mod 2^64). */
+int ensei_homconv(ensei_ctx *ctx, const uint64_t *ct_in, const int8_t *w_pack, const uint32_t *r, int64_t batch,
+                  int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, void *stream);
+
+/* The same HomConv computed with 64-bit vector-ALU multiply-adds straight
+ * from w_hat: uint32 [Cout][Cin][F] (values < p). Bit-identical results;
+ * kept as the vector-ALU comparison point for the matrix-core kernel. */
+int ensei_homconv_valu(ensei_ctx *ctx, const uint64_t *ct_in, const uint32_t *w_hat, const uint32_t *r,
+                       int64_t batch, int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, void *stream);
+
+/* ------------------------------------------------------------------ Dec --
+ * Decryption with round-half-up (Sec. 3.1, "round off the fractions"):
+ *   phi  = b - sum_j s_j a_j  mod 2^64,
+ *   m[c] = floor((phi * p + 2^63) / 2^64) mod p   (exact 81-bit arithmetic).
+ * ct: uint64 [num_ct][n+1]; s: int8 [n]; m: uint32 [num_ct]. */
+int ensei_decrypt(ensei_ctx *ctx, const uint64_t *ct, const int8_t *s, int64_t num_ct, int n, uint32_t *m,
+                  void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ENSEI_H */

@@ -1,0 +1,63 @@
+// Internal declarations shared by the HIP sources of libensei.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ensei.h"
+
+struct ensei_ctx {
+    int device;
+    uint32_t p;         // prime modulus, 3 <= p < 2^22
+    uint32_t g;         // smallest primitive root of p
+    uint64_t delta;     // floor(2^64 / p)
+    int max_log;        // largest log2(L) with L | p-1, capped at 7
+    // Device twiddle tables: for direction d (0 forward, 1 inverse) and each
+    // length L = 2^l (1 <= l <= 7), L/2 entries (omega_L^j, floor(omega_L^j 2^24 / p))
+    // starting at entry d * 127 + (L/2 - 1).
+    uint2 *d_tw;
+};
+
+namespace ensei {
+
+constexpr int kTwPerDir = 127;
+
+// Host-side checks shared by the entry points.
+int check_ctx(const ensei_ctx *ctx);
+bool overlaps(const void *a, size_t an, const void *b, size_t bn);
+int launch_status();
+int ilog2_pow2(int v);  // log2(v) if v is a power of two >= 2, else -1
+
+// ------------------------------------------------------- Z_p on the VALU --
+// Residues live in [0, 2p) between butterfly stages ("lazy" reduction);
+// p < 2^22 keeps every operand of a 24-bit multiply below 2^24.
+
+// Low 32 bits of a 24 x 24-bit product (v_mul_u32_u24, full rate).
+__device__ __forceinline__ uint32_t mul24(uint32_t a, uint32_t b) { return (a & 0xffffffu) * (b & 0xffffffu); }
+
+// The same product, kept as one instruction: without the asm the compiler
+// may reassociate q1*p + q2*p into (q1+q2)*p, whose operand no longer fits
+// 24 bits, and fall back to the quarter-rate 32-bit multiply.
+__device__ __forceinline__ uint32_t mul24_pinned(uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// a * w mod p, lazily reduced to [0, 2p), for a < 2^24, w < p and
+// wq = floor(w * 2^24 / p) (Shoup's precomputed quotient with a 2^24 scale).
+// q = floor(a * wq / 2^24) is floor(a w / p) or one less, so
+// a w - q p lies in [0, 2p) and is exact modulo 2^32. Six full-rate ops.
+__device__ __forceinline__ uint32_t mulmod_lazy(uint32_t a, uint32_t w, uint32_t wq, uint32_t p) {
+    uint64_t prod = (uint64_t)(a & 0xffffffu) * (wq & 0xffffffu);
+    uint32_t q = (uint32_t)(prod >> 24);
+    return mul24(a, w) - mul24_pinned(q, p);
+}
+
+// x in [0, 2m) -> [0, m): unsigned min picks x when x < m (x - m wraps high).
+__device__ __forceinline__ uint32_t reduce_once(uint32_t x, uint32_t m) {
+    uint32_t y = x - m;
+    return y < x ? y : x;  // y < x exactly when x >= m
+}
+
+}  // namespace ensei

@@ -1,0 +1,268 @@
+// Cyclic 2D NTT / INTT over Z_p for H x W grids (H, W powers of two <= 128),
+// the server's share INTT2D(-r), and the filter weight prep (pad + NTT2D).
+//
+// Layout: one workgroup transforms T whole channels. The channels are staged
+// from HBM into LDS with 16-byte loads (rows padded to W+1 words so that
+// both row and column accesses are bank-conflict free); one thread then owns
+// one row, transforms it in registers (radix-2 decimation in frequency, fully
+// unrolled, twiddles read as uniform scalars), and writes it back in natural
+// order; after a barrier one thread owns one column, transforms it, applies
+// the inverse's (HW)^-1 if needed, and stores it straight to HBM, lanes
+// covering consecutive columns so the stores coalesce. HBM traffic is the
+// algorithmic 4 B read + 4 B written per point.
+#include "ensei_internal.hpp"
+
+namespace ensei {
+
+template <int L>
+struct BitRev {
+    static constexpr int apply(int k) {
+        int r = 0;
+        for (int b = 1; b < L; b <<= 1) {
+            r = (r << 1) | (k & 1);
+            k >>= 1;
+        }
+        return r;
+    }
+};
+
+// In-register radix-2 DIF transform of length L. Input residues < 2p in
+// natural order; output residues < 2p in bit-reversed order.
+// tw: this direction's table; entry (m/2 - 1) + j holds omega_m^j.
+template <int L>
+__device__ __forceinline__ void dif_line(uint32_t (&v)[L], const uint2 *__restrict__ tw, uint32_t p) {
+    const uint32_t p2 = 2 * p;
+#pragma unroll
+    for (int m = L; m >= 2; m >>= 1) {
+        const int h = m >> 1;
+#pragma unroll
+        for (int j = 0; j < h; ++j) {
+            uint2 w = make_uint2(1, 0);
+            if (j > 0) w = tw[h - 1 + j];
+#pragma unroll
+            for (int b = 0; b < L; b += m) {
+                const uint32_t u = v[b + j], t = v[b + j + h];
+                const uint32_t s = reduce_once(u + t, p2);
+                uint32_t d = u - t + p2;  // (0, 4p)
+                d = (j == 0) ? reduce_once(d, p2) : mulmod_lazy(d, w.x, w.y, p);
+                v[b + j] = s;
+                v[b + j + h] = d;
+            }
+        }
+    }
+}
+
+template <int LOGH, int LOGW>
+struct NttShape {
+    static constexpr int H = 1 << LOGH, W = 1 << LOGW, F = H * W;
+    static constexpr int LMAX = H > W ? H : W;
+    static constexpr int T = LMAX >= 128 ? 1 : 256 / LMAX;  // channels per workgroup
+    static constexpr int NT = T * LMAX;                       // threads per workgroup
+    static constexpr int STRIDE = W + 1;                      // padded LDS row
+    static constexpr int LDS_WORDS = T * H * STRIDE;
+};
+
+// MODE 0: forward. MODE 1: inverse, output times `scale` (= (HW)^-1 for
+// INTT2D, -(HW)^-1 for the server share).
+template <int LOGH, int LOGW, int MODE>
+__global__ __launch_bounds__((NttShape<LOGH, LOGW>::NT)) void ntt2d_kernel(const uint32_t *in, uint32_t *out,
+                                                                         int64_t batch, const uint2 *__restrict__ tw,
+                                                                         uint32_t p, uint32_t scale, uint32_t scale_q) {
+    using S = NttShape<LOGH, LOGW>;
+    constexpr int H = S::H, W = S::W, F = S::F, T = S::T, NT = S::NT, STR = S::STRIDE;
+    extern __shared__ uint32_t lds[];
+
+    const int tid = threadIdx.x;
+    const int64_t first = (int64_t)blockIdx.x * T;
+    const int nt = (int)((batch - first) < T ? (batch - first) : T);
+    const uint32_t *src = in + first * F;
+
+    // HBM -> LDS, 16-byte loads (channels are 16-byte aligned since F >= 4).
+    constexpr int VEC = W >= 4 ? 4 : W;
+    for (int e = tid * VEC; e < T * F; e += NT * VEC) {
+        const int row = e / W, col = e % W;
+        if (e < nt * F) {
+            if constexpr (VEC == 4) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(src + e);
+                uint32_t *d = lds + row * STR + col;
+                d[0] = q.x;
+                d[1] = q.y;
+                d[2] = q.z;
+                d[3] = q.w;
+            } else {
+                const uint2 q = *reinterpret_cast<const uint2 *>(src + e);
+                lds[row * STR + col] = q.x;
+                lds[row * STR + col + 1] = q.y;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < VEC; ++k) lds[row * STR + col + k] = 0;
+        }
+    }
+    __syncthreads();
+
+    const uint2 *twd = tw + MODE * kTwPerDir;
+    if (tid < T * H) {  // rows
+        uint32_t v[W];
+        uint32_t *rowp = lds + tid * STR;  // channel tid / H, row tid % H
+#pragma unroll
+        for (int k = 0; k < W; ++k) v[k] = rowp[k];
+        dif_line<W>(v, twd, p);
+#pragma unroll
+        for (int k = 0; k < W; ++k) rowp[k] = v[BitRev<W>::apply(k)];
+    }
+    __syncthreads();
+
+    if (tid < T * W) {  // columns
+        const int ch = tid / W, c = tid % W;
+        uint32_t v[H];
+        const uint32_t *colp = lds + ch * H * STR + c;
+#pragma unroll
+        for (int k = 0; k < H; ++k) v[k] = colp[k * STR];
+        dif_line<H>(v, twd, p);
+        if (ch < nt) {
+            uint32_t *dst = out + (first + ch) * F + c;
+#pragma unroll
+            for (int k = 0; k < H; ++k) {
+                uint32_t x = v[BitRev<H>::apply(k)];
+                if (MODE == 1) x = mulmod_lazy(x, scale, scale_q, p);
+                dst[k * W] = reduce_once(x, p);
+            }
+        }
+    }
+}
+
+template <int LOGH, int LOGW, int MODE>
+static int launch_ntt(const uint32_t *in, uint32_t *out, int64_t batch, const ensei_ctx *ctx, uint32_t scale,
+                      hipStream_t st) {
+    using S = NttShape<LOGH, LOGW>;
+    const size_t lds = (size_t)S::LDS_WORDS * 4;
+    auto kern = ntt2d_kernel<LOGH, LOGW, MODE>;
+    static bool attr_set = false;
+    if (!attr_set && lds > 48 * 1024) {
+        if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return ENSEI_ERR_HIP;
+        attr_set = true;
+    }
+    const int64_t blocks = (batch + S::T - 1) / S::T;
+    if (blocks > 0x7fffffff) return ENSEI_ERR_LIMIT;
+    const uint32_t scale_q = (uint32_t)(((uint64_t)scale << 24) / ctx->p);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(S::NT), lds, st, in, out, batch, ctx->d_tw, ctx->p, scale,
+                       scale_q);
+    return launch_status();
+}
+
+using LaunchFn = int (*)(const uint32_t *, uint32_t *, int64_t, const ensei_ctx *, uint32_t, hipStream_t);
+
+template <int MODE>
+struct NttTable {
+    template <int LH, int LW>
+    static constexpr LaunchFn entry() {
+        return &launch_ntt<LH, LW, MODE>;
+    }
+#define ENSEI_ROW(LH) \
+    entry<LH, 1>(), entry<LH, 2>(), entry<LH, 3>(), entry<LH, 4>(), entry<LH, 5>(), entry<LH, 6>(), entry<LH, 7>()
+    static constexpr LaunchFn table[7][7] = {{ENSEI_ROW(1)}, {ENSEI_ROW(2)}, {ENSEI_ROW(3)}, {ENSEI_ROW(4)},
+                                             {ENSEI_ROW(5)}, {ENSEI_ROW(6)}, {ENSEI_ROW(7)}};
+#undef ENSEI_ROW
+};
+
+static uint64_t host_powmod32(uint64_t a, uint64_t e, uint64_t p) {
+    uint64_t r = 1 % p;
+    a %= p;
+    for (; e; e >>= 1) {
+        if (e & 1) r = r * a % p;
+        a = a * a % p;
+    }
+    return r;
+}
+
+// Validates a transform call; on success fills lh, lw.
+static int check_ntt(const ensei_ctx *ctx, const void *in, const void *out, int64_t batch, int H, int W, int *lh,
+                     int *lw) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!in || !out || batch <= 0) return ENSEI_ERR_ARG;
+    *lh = ilog2_pow2(H);
+    *lw = ilog2_pow2(W);
+    if (*lh < 1 || *lw < 1 || *lh > ctx->max_log || *lw > ctx->max_log) return ENSEI_ERR_SHAPE;
+    if (((uintptr_t)in & 15) || ((uintptr_t)out & 15)) return ENSEI_ERR_ALIGN;
+    const size_t bytes = (size_t)batch * H * W * 4;
+    if (in != out && overlaps(in, bytes, out, bytes)) return ENSEI_ERR_OVERLAP;
+    return ENSEI_OK;
+}
+
+static int run_ntt(const ensei_ctx *ctx, const uint32_t *in, uint32_t *out, int64_t batch, int H, int W, int mode,
+                   bool negate, void *stream) {
+    int lh, lw;
+    int st = check_ntt(ctx, in, out, batch, H, W, &lh, &lw);
+    if (st) return st;
+    uint32_t scale = 1;
+    if (mode == 1) {
+        scale = (uint32_t)host_powmod32((uint64_t)H * W % ctx->p, ctx->p - 2, ctx->p);
+        if (negate) scale = (ctx->p - scale) % ctx->p;
+    }
+    LaunchFn fn = mode == 0 ? NttTable<0>::table[lh - 1][lw - 1] : NttTable<1>::table[lh - 1][lw - 1];
+    return fn(in, out, batch, ctx, scale, (hipStream_t)stream);
+}
+
+// Filter reduced mod p and zero-padded into the top-left of the H x W grid.
+__global__ void pad_filters_kernel(const int32_t *__restrict__ w, int64_t nfilt, int kh, int kw, int H, int W,
+                                   int32_t p, uint32_t *__restrict__ out) {
+    const int64_t F = (int64_t)H * W;
+    const int64_t total = nfilt * F;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = idx / F;
+        const int f = (int)(idx - t * F);
+        const int r = f / W, c = f % W;
+        uint32_t v = 0;
+        if (r < kh && c < kw) {
+            int32_t x = w[(t * kh + r) * kw + c] % p;
+            v = (uint32_t)(x < 0 ? x + p : x);
+        }
+        out[idx] = v;
+    }
+}
+
+}  // namespace ensei
+
+using namespace ensei;
+
+extern "C" {
+
+int ensei_ntt2d(ensei_ctx *ctx, const uint32_t *in, uint32_t *out, int64_t batch, int H, int W, void *stream) {
+    return run_ntt(ctx, in, out, batch, H, W, 0, false, stream);
+}
+
+int ensei_intt2d(ensei_ctx *ctx, const uint32_t *in, uint32_t *out, int64_t batch, int H, int W, void *stream) {
+    return run_ntt(ctx, in, out, batch, H, W, 1, false, stream);
+}
+
+int ensei_server_share(ensei_ctx *ctx, const uint32_t *r, uint32_t *s_b, int64_t batch, int H, int W,
+                       void *stream) {
+    return run_ntt(ctx, r, s_b, batch, H, W, 1, true, stream);
+}
+
+int ensei_weight_prep(ensei_ctx *ctx, const int32_t *w, int Cout, int Cin, int kh, int kw, int H, int W,
+                      uint32_t *w_hat, void *stream) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!w || !w_hat || Cout <= 0 || Cin <= 0 || kh <= 0 || kw <= 0) return ENSEI_ERR_ARG;
+    int lh = ilog2_pow2(H), lw = ilog2_pow2(W);
+    if (lh < 1 || lw < 1 || lh > ctx->max_log || lw > ctx->max_log) return ENSEI_ERR_SHAPE;
+    if (kh > H || kw > W) return ENSEI_ERR_SHAPE;
+    if (((uintptr_t)w & 3) || ((uintptr_t)w_hat & 15)) return ENSEI_ERR_ALIGN;
+    const int64_t nfilt = (int64_t)Cout * Cin;
+    if (overlaps(w, (size_t)nfilt * kh * kw * 4, w_hat, (size_t)nfilt * H * W * 4)) return ENSEI_ERR_OVERLAP;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t total = nfilt * H * W;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(pad_filters_kernel, dim3((unsigned)blocks), dim3(256), 0, s, w, nfilt, kh, kw, H, W,
+                       (int32_t)ctx->p, w_hat);
+    if ((st = launch_status())) return st;
+    return run_ntt(ctx, w_hat, w_hat, nfilt, H, W, 0, false, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,244 @@
+"""Thin Python binding of libensei.so (argument marshalling only).
+
+Every operation runs in the HIP kernels behind the C ABI declared in
+``include/ensei.h``; this module only checks tensor dtypes, shapes and
+devices, passes ``data_ptr()`` values and the current HIP stream, and turns
+status codes into exceptions. PyTorch provides device memory and streams.
+There is no CPU path: without the built library or a GPU every call raises.
+
+Names follow the C ABI: ``ensei_ntt2d`` -> ``Context.ntt2d`` and so on; the
+raw ctypes functions are available as ``lib().ensei_ntt2d`` etc.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libensei.so")
+
+ENSEI_OK = 0
+STATUS = {
+    -1: "ENSEI_ERR_ARG",
+    -2: "ENSEI_ERR_SHAPE",
+    -3: "ENSEI_ERR_MODULUS",
+    -4: "ENSEI_ERR_ALIGN",
+    -5: "ENSEI_ERR_OVERLAP",
+    -6: "ENSEI_ERR_LIMIT",
+    -7: "ENSEI_ERR_DEVICE",
+    -8: "ENSEI_ERR_HIP",
+}
+
+_vp, _i32, _i64, _u32, _u64 = C.c_void_p, C.c_int, C.c_int64, C.c_uint32, C.c_uint64
+
+# name -> (restype, argtypes); the same table drives the symbol-export test.
+SIGNATURES = {
+    "ensei_ctx_create": (_i32, [C.POINTER(_vp), _u32, _i32]),
+    "ensei_ctx_destroy": (_i32, [_vp]),
+    "ensei_status_str": (C.c_char_p, [_i32]),
+    "ensei_ctx_modulus": (_u32, [_vp]),
+    "ensei_ctx_delta": (_u64, [_vp]),
+    "ensei_ctx_max_dim": (_i32, [_vp]),
+    "ensei_ntt2d": (_i32, [_vp, _vp, _vp, _i64, _i32, _i32, _vp]),
+    "ensei_intt2d": (_i32, [_vp, _vp, _vp, _i64, _i32, _i32, _vp]),
+    "ensei_server_share": (_i32, [_vp, _vp, _vp, _i64, _i32, _i32, _vp]),
+    "ensei_weight_prep": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp]),
+    "ensei_wpack_bytes": (C.c_size_t, [_i32, _i32, _i64]),
+    "ensei_pack_weights": (_i32, [_vp, _vp, _i32, _i32, _i64, _vp, _vp]),
+    "ensei_encrypt": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _u64, _u64, _vp, _vp]),
+    "ensei_homconv": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
+    "ensei_homconv_valu": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
+    "ensei_decrypt": (_i32, [_vp, _vp, _vp, _i64, _i32, _vp, _vp]),
+}
+
+
+class EnseiError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        name = STATUS.get(status, str(status))
+        msg = _lib.ensei_status_str(status).decode() if _lib is not None else ""
+        super().__init__(f"{where}: {name} ({msg})")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_2003_05328_amd.build` "
+                "(there is no CPU fallback)"
+            )
+        l = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(l, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = l
+    return _lib
+
+
+def _check(status: int, where: str):
+    if status != ENSEI_OK:
+        raise EnseiError(status, where)
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context for prime p on one GPU (``ensei_ctx``)."""
+
+    def __init__(self, p: int = 65537, device: int | None = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the ENSEI kernels run only on the GPU")
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib().ensei_ctx_create(C.byref(h), p, self.device), "ensei_ctx_create")
+        self._h = h
+        self.p = int(lib().ensei_ctx_modulus(h))
+        self.delta = int(lib().ensei_ctx_delta(h))
+        self.max_dim = int(lib().ensei_ctx_max_dim(h))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self.device)
+            lib().ensei_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ------------------------------------------------------------
+    def _stream(self):
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _dev(self, t: torch.Tensor, name: str, dtype):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device.type != "cuda" or t.device.index != self.device:
+            raise ValueError(f"{name} must live on cuda:{self.device}")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def _empty(self, shape, dtype):
+        return torch.empty(shape, dtype=dtype, device=f"cuda:{self.device}")
+
+    def _call(self, name, *args):
+        with torch.cuda.device(self.device):
+            _check(getattr(lib(), name)(self._h, *args, self._stream()), name)
+
+    # -- transforms ---------------------------------------------------------
+    def ntt2d(self, x: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """x uint32 [..., H, W] -> out uint32 [..., H*W] (ensei_ntt2d)."""
+        self._dev(x, "x", torch.uint32)
+        H, W = x.shape[-2:]
+        batch = x.numel() // (H * W)
+        out = self._empty(x.shape[:-2] + (H * W,), torch.uint32) if out is None else self._dev(out, "out", torch.uint32)
+        self._call("ensei_ntt2d", _ptr(x), _ptr(out), batch, H, W)
+        return out
+
+    def intt2d(self, X: torch.Tensor, H: int, W: int, out: torch.Tensor | None = None) -> torch.Tensor:
+        """X uint32 [..., H*W] -> out uint32 [..., H, W] (ensei_intt2d)."""
+        self._dev(X, "X", torch.uint32)
+        batch = X.numel() // (H * W)
+        out = self._empty(X.shape[:-1] + (H, W), torch.uint32) if out is None else self._dev(out, "out", torch.uint32)
+        self._call("ensei_intt2d", _ptr(X), _ptr(out), batch, H, W)
+        return out
+
+    def server_share(self, r: torch.Tensor, H: int, W: int, out: torch.Tensor | None = None) -> torch.Tensor:
+        """r uint32 [..., H*W] -> s_B = INTT2D(-r) uint32 [..., H, W] (ensei_server_share)."""
+        self._dev(r, "r", torch.uint32)
+        batch = r.numel() // (H * W)
+        out = self._empty(r.shape[:-1] + (H, W), torch.uint32) if out is None else self._dev(out, "out", torch.uint32)
+        self._call("ensei_server_share", _ptr(r), _ptr(out), batch, H, W)
+        return out
+
+    # -- weights -------------------------------------------------------------
+    def weight_prep(self, w: torch.Tensor, H: int, W: int, out: torch.Tensor | None = None) -> torch.Tensor:
+        """w int32 [Cout][Cin][kh][kw] -> W^ uint32 [Cout][Cin][H*W] (ensei_weight_prep)."""
+        self._dev(w, "w", torch.int32)
+        Cout, Cin, kh, kw = w.shape
+        out = self._empty((Cout, Cin, H * W), torch.uint32) if out is None else self._dev(out, "out", torch.uint32)
+        self._call("ensei_weight_prep", _ptr(w), Cout, Cin, kh, kw, H, W, _ptr(out))
+        return out
+
+    def pack_weights(self, w_hat: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """W^ uint32 [Cout][Cin][F] -> packed int8 limbs (ensei_pack_weights)."""
+        self._dev(w_hat, "w_hat", torch.uint32)
+        Cout, Cin, F = w_hat.shape
+        nb = int(lib().ensei_wpack_bytes(Cout, Cin, F))
+        out = self._empty((nb,), torch.int8) if out is None else self._dev(out, "out", torch.int8)
+        if out.numel() < nb:
+            raise ValueError(f"packed-weight buffer needs {nb} bytes")
+        self._call("ensei_pack_weights", _ptr(w_hat), Cout, Cin, F, _ptr(out))
+        return out
+
+    # -- LWE -----------------------------------------------------------------
+    def encrypt(self, m, s, e, seed_a: int, ct_index0: int = 0, out=None) -> torch.Tensor:
+        """m uint32 [...], s int8 [n], e int32 [...] -> ct uint64 [..., n+1] (ensei_encrypt)."""
+        self._dev(m, "m", torch.uint32)
+        self._dev(s, "s", torch.int8)
+        self._dev(e, "e", torch.int32)
+        if e.numel() != m.numel():
+            raise ValueError("e must have one error per plaintext")
+        n = s.numel()
+        out = self._empty(m.shape + (n + 1,), torch.uint64) if out is None else self._dev(out, "out", torch.uint64)
+        self._call("ensei_encrypt", _ptr(m), _ptr(s), _ptr(e), m.numel(), n, seed_a % 2**64, ct_index0 % 2**64, _ptr(out))
+        return out
+
+    def decrypt(self, ct, s, out=None) -> torch.Tensor:
+        """ct uint64 [..., n+1], s int8 [n] -> m uint32 [...] (ensei_decrypt)."""
+        self._dev(ct, "ct", torch.uint64)
+        self._dev(s, "s", torch.int8)
+        n = s.numel()
+        if ct.shape[-1] != n + 1:
+            raise ValueError("ct rows must have n+1 words")
+        out = self._empty(ct.shape[:-1], torch.uint32) if out is None else self._dev(out, "out", torch.uint32)
+        self._call("ensei_decrypt", _ptr(ct), _ptr(s), ct.numel() // (n + 1), n, _ptr(out))
+        return out
+
+    # -- HomConv ---------------------------------------------------------------
+    def _hc_shapes(self, ct_in, Cout, r):
+        B, Cin, F, n1 = ct_in.shape
+        if tuple(r.shape) != (B, Cout, F):
+            raise ValueError(f"r must be [B][Cout][F] = {(B, Cout, F)}")
+        return B, Cin, F, n1 - 1
+
+    def homconv(self, ct_in, w_pack, r, Cout: int, out=None) -> torch.Tensor:
+        """ct_in uint64 [B][Cin][F][n+1], packed W^, r uint32 [B][Cout][F] -> ct_out (ensei_homconv)."""
+        self._dev(ct_in, "ct_in", torch.uint64)
+        self._dev(w_pack, "w_pack", torch.int8)
+        self._dev(r, "r", torch.uint32)
+        B, Cin, F, n = self._hc_shapes(ct_in, Cout, r)
+        if w_pack.numel() < int(lib().ensei_wpack_bytes(Cout, Cin, F)):
+            raise ValueError("w_pack is smaller than ensei_wpack_bytes(Cout, Cin, F)")
+        out = self._empty((B, Cout, F, n + 1), torch.uint64) if out is None else self._dev(out, "out", torch.uint64)
+        self._call("ensei_homconv", _ptr(ct_in), _ptr(w_pack), _ptr(r), B, Cin, Cout, F, n, _ptr(out))
+        return out
+
+    def homconv_valu(self, ct_in, w_hat, r, out=None) -> torch.Tensor:
+        """Same contraction from W^ uint32 [Cout][Cin][F] on the vector ALUs (ensei_homconv_valu)."""
+        self._dev(ct_in, "ct_in", torch.uint64)
+        self._dev(w_hat, "w_hat", torch.uint32)
+        self._dev(r, "r", torch.uint32)
+        Cout = w_hat.shape[0]
+        B, Cin, F, n = self._hc_shapes(ct_in, Cout, r)
+        if tuple(w_hat.shape) != (Cout, Cin, F):
+            raise ValueError("w_hat must be [Cout][Cin][F]")
+        out = self._empty((B, Cout, F, n + 1), torch.uint64) if out is None else self._dev(out, "out", torch.uint64)
+        self._call("ensei_homconv_valu", _ptr(ct_in), _ptr(w_hat), _ptr(r), B, Cin, Cout, F, n, _ptr(out))
+        return out

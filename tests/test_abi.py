@@ -1,0 +1,79 @@
+"""The C-ABI library loads and exports every symbol include/ensei.h declares (no GPU)."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2003_05328_amd import ensei
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ensei.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ensei_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_hot_path():
+    names = declared_functions()
+    for core in ("ensei_ntt2d", "ensei_intt2d", "ensei_encrypt", "ensei_homconv", "ensei_decrypt"):
+        assert core in names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ensei.LIB_PATH):
+        from paper_2003_05328_amd import build
+
+        build.build()
+    return ensei.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+        assert name in ensei.SIGNATURES, f"binding lacks {name}"
+    assert set(ensei.SIGNATURES) == set(declared_functions())
+
+
+def test_exports_are_unmangled_c_symbols(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", ensei.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    for name in declared_functions():
+        assert name in exported, name
+
+
+def test_status_strings_and_host_only_calls(lib):
+    for code in list(ensei.STATUS) + [0]:
+        s = lib.ensei_status_str(code)
+        assert isinstance(s, bytes) and len(s) > 0
+    assert lib.ensei_status_str(12345) == b"unknown status"
+    # packed-weight size is pure host arithmetic: F * ceil(Cin/16) * roundup(Cout,16) * 48
+    assert lib.ensei_wpack_bytes(64, 64, 1024) == 1024 * 4 * 64 * 48
+    assert lib.ensei_wpack_bytes(8, 3, 256) == 256 * 1 * 16 * 48
+    assert lib.ensei_wpack_bytes(0, 3, 256) == 0
+    # context accessors tolerate NULL
+    assert lib.ensei_ctx_modulus(None) == 0 and lib.ensei_ctx_delta(None) == 0
+    assert lib.ensei_ctx_destroy(None) == 0
+
+
+def test_entry_points_reject_null_context(lib):
+    # argument checks run on the host before any HIP call touches a device
+    assert lib.ensei_ntt2d(None, None, None, 1, 16, 16, None) < 0
+    assert lib.ensei_homconv(None, None, None, None, 1, 1, 1, 1, 1, None, None) < 0
+    assert lib.ensei_encrypt(None, None, None, None, 1, 1, 0, 0, None, None) < 0
+    assert lib.ensei_decrypt(None, None, None, 1, 1, None, None) < 0
+    h = ctypes.c_void_p()
+    assert lib.ensei_ctx_create(None, 65537, 0) == -1  # ENSEI_ERR_ARG
+
+
+def test_modulus_rejected_before_device_use(lib):
+    h = ctypes.c_void_p()
+    assert lib.ensei_ctx_create(ctypes.byref(h), 65535, 0) == -3  # not prime
+    assert lib.ensei_ctx_create(ctypes.byref(h), 1 << 22 | 1, 0) == -3  # too large
+    assert lib.ensei_ctx_create(ctypes.byref(h), 2, 0) == -3
+    assert h.value is None

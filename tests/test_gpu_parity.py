@@ -1,0 +1,244 @@
+"""GPU parity: every HIP entry point against the CPU oracle, bit for bit.
+
+Small cases span several workgroup tiles and ragged tails and are compared
+element by element; full-size layers are compared on outputs the oracle
+computes one by one (sampled ciphertext rows) and on properties that hold at
+any size (exact decryption, s_A + s_B = x (*) w mod p).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2003_05328_amd import configs, synth
+from paper_2003_05328_amd.ensei import Context, EnseiError
+from tests.gpu_helpers import P, dev, host, oracle_ct_in_rows, oracle_ct_out_row, rows_u64
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [2, 4, 8, 16, 32, 64, 128]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = Context(P, 0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    o = oracle.default()
+    o.set_threads(16)
+    return o
+
+
+def _batch_for(H, W):
+    T = max(1, 256 // max(H, W)) if max(H, W) < 128 else 1
+    return 2 * T + 3  # two full workgroups and a ragged one
+
+
+# ------------------------------------------------------------- transforms ---
+
+
+@pytest.mark.parametrize("H", SIZES)
+@pytest.mark.parametrize("W", SIZES)
+def test_ntt2d_intt2d(ctx, orc, H, W):
+    batch = _batch_for(H, W) if H * W <= 4096 else 3
+    x = synth.uniform_u32(1000 + H * 131 + W, (batch, H, W), P)
+    x[0] = P - 1  # largest residue everywhere
+    X = host(ctx.ntt2d(dev(x)))
+    assert np.array_equal(X.reshape(batch, H, W), orc.ntt2d(x, P))
+    Y = synth.uniform_u32(2000 + H * 131 + W, (batch, H * W), P)
+    y = host(ctx.intt2d(dev(Y), H, W))
+    assert np.array_equal(y, orc.ntt2d(Y.reshape(batch, H, W), P, inverse=True))
+
+
+def test_ntt2d_in_place_and_roundtrip(ctx, orc):
+    x = synth.uniform_u32(7, (37, 32, 32), P)
+    t = dev(x)
+    ctx.ntt2d(t, out=t.view(37, 1024))
+    assert np.array_equal(host(t), orc.ntt2d(x, P))
+    back = ctx.intt2d(t.view(37, 1024), 32, 32)
+    assert np.array_equal(host(back), x)
+
+
+def test_server_share(ctx, orc):
+    r = synth.uniform_u32(8, (5, 3, 256), P)
+    got = host(ctx.server_share(dev(r), 16, 16))
+    assert np.array_equal(got, orc.server_share(r, 16, 16, P))
+
+
+@pytest.mark.parametrize("Cout,Cin,kh,kw,H,W", [(8, 3, 3, 3, 16, 16), (5, 7, 7, 7, 32, 32), (3, 2, 3, 5, 8, 16),
+                                                (2, 2, 1, 1, 128, 128), (4, 3, 4, 4, 4, 4)])
+def test_weight_prep(ctx, orc, Cout, Cin, kh, kw, H, W):
+    g = np.random.default_rng(Cout * 100 + Cin)
+    w = g.integers(-200000, 200000, size=(Cout, Cin, kh, kw)).astype(np.int32)
+    w.flat[0] = -(2**31)
+    w.flat[-1] = 2**31 - 1
+    got = host(ctx.weight_prep(dev(w), H, W))
+    assert np.array_equal(got, orc.weight_prep(w, H, W, P))
+
+
+# -------------------------------------------------------------------- LWE ---
+
+
+@pytest.mark.parametrize("n,num_ct,c0", [(1, 5, 0), (16, 77, 3), (63, 130, 0), (64, 64, 2**40), (65, 257, 11),
+                                         (512, 300, 0), (1024, 1000, 123456)])
+def test_encrypt_decrypt(ctx, orc, n, num_ct, c0):
+    m = synth.uniform_u32(n, num_ct, P)
+    m[:2] = [0, P - 1]
+    s = synth.ternary(n + 1, n)
+    e = synth.rounded_gaussian(n + 2, num_ct)
+    seed_a = 0xC0FFEE ^ n
+    ct = ctx.encrypt(dev(m), dev(s), dev(e), seed_a, ct_index0=c0)
+    ref = orc.encrypt(m, s, e, seed_a, P, ct_index0=c0)
+    assert np.array_equal(host(ct), ref)
+    assert np.array_equal(host(ctx.decrypt(ct, dev(s))), m)
+    # decryption of arbitrary words (not only fresh encryptions)
+    junk = synth.uniform_u64(n + 3, (num_ct, n + 1))
+    assert np.array_equal(host(ctx.decrypt(dev(junk), dev(s))), orc.decrypt(junk, s, P))
+
+
+# ---------------------------------------------------------------- HomConv ---
+
+HOMCONV_CASES = [
+    # B, Cin, Cout, F, n
+    (1, 1, 1, 1, 1),
+    (1, 3, 8, 16, 63),
+    (2, 3, 8, 5, 64),
+    (1, 16, 16, 3, 65),
+    (1, 17, 17, 4, 127),
+    (2, 33, 40, 2, 128),
+    (1, 64, 64, 3, 129),
+    (1, 65, 33, 2, 200),
+    (1, 130, 70, 2, 64),
+    (1, 256, 512, 1, 30),
+]
+
+
+def _homconv_inputs(B, Cin, Cout, F, n, seed):
+    ct = synth.uniform_u64(seed, (B, Cin, F, n + 1))
+    w = synth.uniform_u32(seed + 1, (Cout, Cin, F), P)
+    w.flat[0] = P - 1
+    w.flat[-1] = 0
+    if w.size > 2:
+        w.flat[1] = 65536 % P if P > 65536 else P - 2
+    r = synth.uniform_u32(seed + 2, (B, Cout, F), P)
+    return ct, w, r
+
+
+@pytest.mark.parametrize("B,Cin,Cout,F,n", HOMCONV_CASES)
+def test_homconv_mfma(ctx, orc, B, Cin, Cout, F, n):
+    ct, w, r = _homconv_inputs(B, Cin, Cout, F, n, 31 * Cin + Cout)
+    ref = orc.homconv(ct, w, r, P)
+    pack = ctx.pack_weights(dev(w))
+    got = host(ctx.homconv(dev(ct), pack, dev(r), Cout))
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("B,Cin,Cout,F,n", HOMCONV_CASES)
+def test_homconv_valu(ctx, orc, B, Cin, Cout, F, n):
+    ct, w, r = _homconv_inputs(B, Cin, Cout, F, n, 37 * Cin + Cout)
+    got = host(ctx.homconv_valu(dev(ct), dev(w), dev(r)))
+    assert np.array_equal(got, orc.homconv(ct, w, r, P))
+
+
+def test_homconv_extreme_words(ctx, orc):
+    """All-ones words and W^ = p-1 maximise every limb sum."""
+    B, Cin, Cout, F, n = 1, 70, 20, 2, 66
+    ct = np.full((B, Cin, F, n + 1), 2**64 - 1, dtype=np.uint64)
+    ct[..., ::3] = 2**63
+    w = np.full((Cout, Cin, F), P - 1, dtype=np.uint32)
+    r = np.full((B, Cout, F), P - 1, dtype=np.uint32)
+    ref = orc.homconv(ct, w, r, P)
+    got = host(ctx.homconv(dev(ct), ctx.pack_weights(dev(w)), dev(r), Cout))
+    assert np.array_equal(got, ref)
+
+
+# -------------------------------------------------------- argument checks ---
+
+
+def test_errors_are_reported(ctx):
+    x = torch.zeros((2, 12, 16), dtype=torch.uint32, device="cuda:0")
+    with pytest.raises(EnseiError, match="SHAPE"):
+        ctx.ntt2d(x)
+    big = torch.zeros((1, 4, 1, 9), dtype=torch.uint64, device="cuda:0")
+    w1 = torch.zeros((4, 4, 1), dtype=torch.uint32, device="cuda:0")
+    r1 = torch.zeros((1, 4, 1), dtype=torch.uint32, device="cuda:0")
+    with pytest.raises(EnseiError, match="OVERLAP"):
+        ctx.homconv_valu(big, w1, r1, out=big)
+    s = torch.zeros(20000, dtype=torch.int8, device="cuda:0")
+    m = torch.zeros(3, dtype=torch.uint32, device="cuda:0")
+    e = torch.zeros(3, dtype=torch.int32, device="cuda:0")
+    with pytest.raises(EnseiError, match="LIMIT"):
+        ctx.encrypt(m, s, e, 1)
+
+
+# --------------------------------------------------- whole secure conv ------
+
+
+def _gpu_round0(ctx, inp):
+    S = inp.shape
+    x = dev(inp.x)
+    w = dev(inp.w)
+    s = dev(inp.s)
+    x_hat = ctx.ntt2d(x)  # [B][Cin][F]
+    w_hat = ctx.weight_prep(w, S.H, S.W)
+    pack = ctx.pack_weights(w_hat)
+    ct_in = ctx.encrypt(x_hat, s, dev(inp.e), inp.seed_a)
+    r = dev(inp.r)
+    ct_out = ctx.homconv(ct_in, pack, r, S.Cout)
+    m = ctx.decrypt(ct_out, s)
+    s_a = ctx.intt2d(m, S.H, S.W)
+    s_b = ctx.server_share(r, S.H, S.W)
+    return dict(x_hat=x_hat, w_hat=w_hat, ct_in=ct_in, ct_out=ct_out, m=m, s_a=s_a, s_b=s_b)
+
+
+def test_small_secure_conv_bit_exact(ctx, orc):
+    """16x16 grid, 3 -> 8 channels, n = 512: every intermediate equals the oracle's."""
+    inp = synth.generate(configs.SMALL_16x16_3to8, P, seed=0)
+    ref = orc.fdsc_round0(inp, P)
+    got = _gpu_round0(ctx, inp)
+    for k in ("x_hat", "w_hat", "ct_in", "ct_out", "m", "s_a", "s_b"):
+        assert np.array_equal(host(got[k]), ref[k]), k
+    y = (ref["s_a"].astype(np.int64) + ref["s_b"]) % P
+    assert np.array_equal(y, orc.cyclic_conv(inp.x, inp.w, P))
+
+
+FULL = [
+    "conv32x32_c64to64_k3_n1024",
+    "conv32x32_c64to64_k3_n1024_hidden",
+    "conv128x128_c3to64_k7_n1024",
+    "stack8_L7_4x4_c256to512",
+]
+
+
+@pytest.mark.parametrize("name", FULL)
+def test_full_size_layer(ctx, orc, name):
+    S = configs.WORKLOADS[name]
+    inp = synth.generate(S, P, seed=1)
+    got = _gpu_round0(ctx, inp)
+    # transforms: complete comparison
+    x_hat = orc.ntt2d(inp.x, P).reshape(S.B, S.Cin, S.F)
+    assert np.array_equal(host(got["x_hat"]), x_hat)
+    w_hat = orc.weight_prep(inp.w, S.H, S.W, P)
+    assert np.array_equal(host(got["w_hat"]), w_hat)
+    # sampled ciphertext rows, each recomputed by the oracle from its own inputs
+    g = np.random.default_rng(5)
+    for _ in range(6):
+        b, f = int(g.integers(S.B)), int(g.integers(S.F))
+        cin = oracle_ct_in_rows(orc, x_hat, inp, b, f)
+        flat_in = [(b * S.Cin + i) * S.F + f for i in range(S.Cin)]
+        assert np.array_equal(rows_u64(got["ct_in"], flat_in), cin)
+        for o in {0, S.Cout - 1, int(g.integers(S.Cout))}:
+            ref_row = oracle_ct_out_row(orc, cin, w_hat, inp, b, o, f)
+            assert np.array_equal(rows_u64(got["ct_out"], [(b * S.Cout + o) * S.F + f]), ref_row[None])
+            assert int(host(got["m"])[b, o, f]) == int(orc.decrypt(ref_row[None], inp.s, P)[0])
+    # exact decryption everywhere: m = (sum_i W^ x^ + r) mod p
+    # (products < 2^34, sums over Cin <= 512 stay below 2^43: exact in int64)
+    exp_m = (np.einsum("oif,bif->bof", w_hat.astype(np.int64), x_hat.astype(np.int64)) + inp.r) % P
+    assert np.array_equal(host(got["m"]).astype(np.int64), exp_m)
+    # the two shares reconstruct the cyclic convolution
+    y = (host(got["s_a"]).astype(np.int64) + host(got["s_b"])) % P
+    assert np.array_equal(y, orc.cyclic_conv(inp.x, inp.w, P))
