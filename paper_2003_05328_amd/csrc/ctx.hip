@@ -108,6 +108,9 @@ int ensei_ctx_create(ensei_ctx **out, uint32_t p, int device) {
     int lg = 0;
     while (lg < 7 && (p - 1) % (1u << (lg + 1)) == 0) ++lg;
     c->max_log = lg;
+    if (hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        c->num_cus <= 0)
+        c->num_cus = 256;
 
     // Twiddles omega_L^j (and their 2^24-scaled quotients) per direction and length.
     uint2 tw[2 * kTwPerDir];

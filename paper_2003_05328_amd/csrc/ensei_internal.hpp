@@ -12,6 +12,7 @@ struct ensei_ctx {
     uint32_t g;         // smallest primitive root of p
     uint64_t delta;     // floor(2^64 / p)
     int max_log;        // largest log2(L) with L | p-1, capped at 7
+    int num_cus;        // compute units of the device (persistent-kernel grids)
     // Device twiddle tables: for direction d (0 forward, 1 inverse) and each
     // length L = 2^l (1 <= l <= 7), L/2 entries (omega_L^j, floor(omega_L^j 2^24 / p))
     // starting at entry d * 127 + (L/2 - 1).

@@ -88,11 +88,20 @@ __global__ __launch_bounds__(256) void decrypt_kernel(const uint64_t *__restrict
     const int64_t rowlen = (int64_t)n + 1;
     for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); c < num_ct; c += stride) {
         const uint64_t *row = ct + c * rowlen;
+        const uint64_t bword = row[n];  // same address in every lane: one transaction, issued first
         uint64_t acc = 0;
-#pragma unroll 8
-        for (int j = lane; j < n; j += 64) acc += ternary_times(key[j], row[j]);
+        int j = lane;
+        // 16 words per lane in flight at once
+        for (; j + 64 * 15 < n; j += 64 * 16) {
+            uint64_t w[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) w[k] = row[j + 64 * k];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) acc += ternary_times(key[j + 64 * k], w[k]);
+        }
+        for (; j < n; j += 64) acc += ternary_times(key[j], row[j]);
         acc = wave_sum_u64(acc);
-        if (lane == 0) m[c] = decode(row[n] - acc, p);
+        if (lane == 0) m[c] = decode(bword - acc, p);
     }
 }
 

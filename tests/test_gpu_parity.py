@@ -114,6 +114,9 @@ HOMCONV_CASES = [
     (1, 65, 33, 2, 200),
     (1, 130, 70, 2, 64),
     (1, 256, 512, 1, 30),
+    # more tiles than resident workgroups: every block walks many (tile, K step) units
+    (1, 70, 64, 300, 130),
+    (2, 130, 20, 150, 64),
 ]
 
 
