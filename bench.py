@@ -140,8 +140,8 @@ def main():
     w_hat = torch.empty((S.Cout, S.Cin, S.F), dtype=torch.uint32, device=dv)
     pack = torch.empty((pack_bytes,), dtype=torch.int8, device=dv)
     x_hat = torch.empty((S.B, S.Cin, S.F), dtype=torch.uint32, device=dv)
-    ct_in = torch.empty((S.B, S.Cin, S.F, S.n + 1), dtype=torch.uint64, device=dv)
-    ct_out = torch.empty((S.B, S.Cout, S.F, S.n + 1), dtype=torch.uint64, device=dv)
+    ct_in = torch.empty((S.B, S.F, S.n + 1, S.Cin), dtype=torch.uint64, device=dv)  # word-major
+    ct_out = torch.empty((S.B, S.F, S.n + 1, S.Cout), dtype=torch.uint64, device=dv)
     m = torch.empty((S.B, S.Cout, S.F), dtype=torch.uint32, device=dv)
     s_a = torch.empty((S.B, S.Cout, S.H, S.W), dtype=torch.uint32, device=dv)
     s_b = torch.empty((S.B, S.Cout, S.H, S.W), dtype=torch.uint32, device=dv)

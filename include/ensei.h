@@ -120,47 +120,61 @@ int ensei_weight_prep(ensei_ctx *ctx, const int32_t *w, int Cout, int Cin, int k
                       uint32_t *w_hat, void *stream);
 
 /* Bytes of the packed-weight buffer ensei_pack_weights writes:
- * F * ceil(Cin/16) * roundup(Cout,16) * 48. Returns 0 for invalid sizes. */
+ * F * (ceil(Cin/64) * 4) * roundup(Cout,16) * 48. Returns 0 for invalid sizes. */
 size_t ensei_wpack_bytes(int Cout, int Cin, int64_t F);
 
 /* Packs transformed weights for ensei_homconv: every W^[o][i][f] (the
  * integer in [0, p), p < 2^22) is written as three signed bytes
  * d0 + 2^8 d1 + 2^16 d2 with d0, d1, d2 in [-128, 127] (balanced base-256
  * digits), grouped per frequency as
- *   w_pack[f][i/16][o][d][i%16]   (int8; channels and rows zero-padded),
+ *   w_pack[f][i/16][o][d][i%16]   (int8; rows zero-padded to a multiple of 16,
+ *                                  channel groups of 16 to a multiple of 4),
  * the operand layout of the i8 matrix-core contraction in ensei_homconv.
  * w_hat: uint32 [Cout][Cin][F]; w_pack: ensei_wpack_bytes(Cout, Cin, F)
  * bytes, 16-byte aligned. */
 int ensei_pack_weights(ensei_ctx *ctx, const uint32_t *w_hat, int Cout, int Cin, int64_t F, int8_t *w_pack,
                        void *stream);
 
+/* ------------------------------------------------- ciphertext storage --
+ * LWE ciphertexts (one per frequency coefficient) are stored WORD-MAJOR:
+ * for B images, C channels and F frequencies, ct is uint64 [B][F][n+1][C]
+ * and ciphertext (b, c, f) keeps its word j (j < n: a_j, j = n: b) at
+ * ct[b][f][j][c]. Its ciphertext index is q = (b*F + f)*C + c. For one
+ * (b, f) the C ciphertexts form a contiguous (n+1) x C matrix, the operand
+ * HomConv contracts; with C = 1 the layout is a plain list of rows [N][n+1].
+ * Plaintexts, errors, decryptions and masks use the spectra's channel-major
+ * layout [B][C][F] (what ensei_ntt2d produces and ensei_intt2d consumes).
+ */
+
 /* ------------------------------------------------------------------ Enc --
- * LWE encryption of num_ct plaintexts m[c] < p under the ternary key s
- * (Eq. (bfv_enc) with one coefficient per ciphertext; q = 2^64):
- *   a_j = SplitMix64 output number (ct_index0 + c)*n + j + 1 of the
+ * LWE encryption of the B*C*F plaintexts m[b][c][f] < p under the ternary
+ * key s (Eq. (bfv_enc) with one coefficient per ciphertext; q = 2^64):
+ *   a_j = SplitMix64 output number (ct_index0 + q)*n + j + 1 of the
  *         generator seeded with seed_a, for j < n (the uniform "encryption
  *         constants" the paper generates offline, Sec. 5.1);
- *   b   = sum_j s_j a_j + e[c] + Delta * m[c]  mod 2^64;
- *   ct[c] = [a_0, ..., a_{n-1}, b].
- * m: uint32 [num_ct]; s: int8 [n] in {-1, 0, 1}; e: int32 [num_ct];
- * ct: uint64 [num_ct][n+1] (8-byte aligned). 1 <= n <= ENSEI_MAX_LWE_N.
- * Encrypting a slice with ct_index0 = its first global index reproduces the
- * same words as one call over the whole range. */
-int ensei_encrypt(ensei_ctx *ctx, const uint32_t *m, const int8_t *s, const int32_t *e, int64_t num_ct, int n,
-                  uint64_t seed_a, uint64_t ct_index0, uint64_t *ct, void *stream);
+ *   b   = sum_j s_j a_j + e[b][c][f] + Delta * m[b][c][f]  mod 2^64.
+ * m: uint32 [B][C][F]; s: int8 [n] in {-1, 0, 1}; e: int32 [B][C][F];
+ * ct: uint64 [B][F][n+1][C] (word-major, above; 8-byte aligned).
+ * 1 <= n <= ENSEI_MAX_LWE_N. Encrypting a slice with ct_index0 = the index of
+ * its first ciphertext reproduces the same words as one call over the whole
+ * range (C = 1 slices of a list). */
+int ensei_encrypt(ensei_ctx *ctx, const uint32_t *m, const int8_t *s, const int32_t *e, int64_t batch, int C,
+                  int64_t F, int n, uint64_t seed_a, uint64_t ct_index0, uint64_t *ct, void *stream);
 
 /* -------------------------------------------------------------- HomConv --
  * Server-side homomorphic convolution in the frequency domain: the
  * homomorphic Hadamard product with the transformed filters, summed over
  * input channels, then HomShare's mask (Fig. 2 lines 3-4; Eq. (homshare)):
- *   ct_out[b][o][f][j] = sum_i W^[o][i][f] * ct_in[b][i][f][j]  mod 2^64,  j <= n
- *   ct_out[b][o][f][n] += Delta * r[b][o][f]                     mod 2^64
- * so Dec(ct_out[b][o][f]) = (sum_i W^ x^ + r) mod p and the server keeps -r.
- * ct_in: uint64 [batch][Cin][F][n+1]; w_pack: from ensei_pack_weights for
- * (Cout, Cin, F); r: uint32 [batch][Cout][F] (< p); ct_out: uint64
- * [batch][Cout][F][n+1]. 1 <= Cin <= ENSEI_MAX_CIN, 1 <= Cout <= ENSEI_MAX_COUT,
- * 1 <= n <= ENSEI_MAX_LWE_N. Runs on the i8 matrix cores (signed-byte limbs
- * of both operands, exact i32 sums, recombined mod 2^64). */
+ *   ct_out(b, o, f)[j] = sum_i W^[o][i][f] * ct_in(b, i, f)[j]  mod 2^64,  j <= n
+ *   ct_out(b, o, f)[n] += Delta * r[b][o][f]                      mod 2^64
+ * so Dec(ct_out(b, o, f)) = (sum_i W^ x^ + r) mod p and the server keeps -r.
+ * ct_in: uint64 [batch][F][n+1][Cin] (word-major); w_pack: from
+ * ensei_pack_weights for (Cout, Cin, F); r: uint32 [batch][Cout][F] (< p);
+ * ct_out: uint64 [batch][F][n+1][Cout] (word-major). 1 <= Cin <= ENSEI_MAX_CIN,
+ * 1 <= Cout <= ENSEI_MAX_COUT, 1 <= n <= ENSEI_MAX_LWE_N, and one (b, f) block
+ * of either side below 2^31 bytes ((n+1) * max(Cin, Cout) * 8). Runs on the
+ * i8 matrix cores (signed-byte limbs of both operands, exact i32 sums,
+ * recombined mod 2^64). */
 int ensei_homconv(ensei_ctx *ctx, const uint64_t *ct_in, const int8_t *w_pack, const uint32_t *r, int64_t batch,
                   int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, void *stream);
 
@@ -173,10 +187,11 @@ int ensei_homconv_valu(ensei_ctx *ctx, const uint64_t *ct_in, const uint32_t *w_
 /* ------------------------------------------------------------------ Dec --
  * Decryption with round-half-up (Sec. 3.1, "round off the fractions"):
  *   phi  = b - sum_j s_j a_j  mod 2^64,
- *   m[c] = floor((phi * p + 2^63) / 2^64) mod p   (exact 81-bit arithmetic).
- * ct: uint64 [num_ct][n+1]; s: int8 [n]; m: uint32 [num_ct]. */
-int ensei_decrypt(ensei_ctx *ctx, const uint64_t *ct, const int8_t *s, int64_t num_ct, int n, uint32_t *m,
-                  void *stream);
+ *   m[b][c][f] = floor((phi * p + 2^63) / 2^64) mod p   (exact 81-bit arithmetic)
+ * for every ciphertext (b, c, f) of ct: uint64 [B][F][n+1][C] (word-major);
+ * s: int8 [n]; m: uint32 [B][C][F]. */
+int ensei_decrypt(ensei_ctx *ctx, const uint64_t *ct, const int8_t *s, int64_t batch, int C, int64_t F, int n,
+                  uint32_t *m, void *stream);
 
 #ifdef __cplusplus
 }

@@ -32,9 +32,9 @@ _SIG = {
     "or_cyclic_conv": (None, [u64, i32, i32, i32, i32, i32, i32, i32, vp, vp, vp]),
     "or_splitmix64": (u64, [u64, u64]),
     "or_delta": (u64, [u64]),
-    "or_encrypt": (None, [u64, i64, i32, vp, vp, vp, u64, u64, vp]),
-    "or_phase": (u64, [i32, vp, vp]),
-    "or_decrypt": (None, [u64, i64, i32, vp, vp, vp]),
+    "or_encrypt": (None, [u64, i64, i32, i64, i32, vp, vp, vp, u64, u64, vp]),
+    "or_phase": (u64, [i32, vp, i64, vp]),
+    "or_decrypt": (None, [u64, i64, i32, i64, i32, vp, vp, vp]),
     "or_homconv": (None, [u64, i32, i32, i32, i64, i32, vp, vp, vp, vp]),
     "or_homconv_select": (None, [u64, i32, i32, i32, i64, i32, vp, vp, vp, i64, vp, vp]),
     "or_server_share": (None, [u64, i64, i32, i32, vp, vp]),
@@ -124,48 +124,58 @@ class Oracle:
         return y
 
     def encrypt(self, m, s, e, seed_a: int, p: int, ct_index0: int = 0) -> np.ndarray:
-        """m[N] in [0,p), s[n] ternary, e[N] -> ct[N][n+1] uint64."""
-        m = _c(m, np.uint32).reshape(-1)
-        e = _c(e, np.int32).reshape(-1)
+        """Encrypt plaintexts m[B][C][F] (errors e of the same shape) into the
+        word-major ciphertexts ct[B][F][n+1][C] (word j of ciphertext (b, c, f)
+        at ct[b][f][j][c]). A 1-D m is a plain list: B = C = 1, F = N, and the
+        result is returned as rows [N][n+1]."""
+        m = _c(m, np.uint32)
+        e = _c(e, np.int32)
         s = _c(s, np.int8)
         n = s.shape[0]
-        ct = np.empty((m.shape[0], n + 1), dtype=np.uint64)
-        self.lib.or_encrypt(p, m.shape[0], n, _p(m), _p(s), _p(e), seed_a % 2**64, ct_index0 % 2**64, _p(ct))
-        return ct
+        flat = m.ndim == 1
+        B, C, F = (1, 1, m.shape[0]) if flat else m.shape
+        assert e.size == m.size
+        ct = np.empty((B, F, n + 1, C), dtype=np.uint64)
+        self.lib.or_encrypt(p, B, C, F, n, _p(m), _p(s), _p(e), seed_a % 2**64, ct_index0 % 2**64, _p(ct))
+        return ct.reshape(F, n + 1) if flat else ct
 
     def phase(self, ct_row: np.ndarray, s: np.ndarray) -> int:
+        """phi = b - <a, s> of one ciphertext given as its n+1 words."""
         row = _c(ct_row, np.uint64)
         s = _c(s, np.int8)
-        return int(self.lib.or_phase(s.shape[0], _p(row), _p(s)))
+        return int(self.lib.or_phase(s.shape[0], _p(row), 1, _p(s)))
 
     def decrypt(self, ct: np.ndarray, s: np.ndarray, p: int) -> np.ndarray:
-        """ct[N][n+1] -> m[N] uint32."""
+        """ct[B][F][n+1][C] -> m[B][C][F]; a 2-D ct[N][n+1] is a plain list -> m[N]."""
         s = _c(s, np.int8)
         n = s.shape[0]
-        ct = _c(ct, np.uint64).reshape(-1, n + 1)
-        m = np.empty(ct.shape[0], dtype=np.uint32)
-        self.lib.or_decrypt(p, ct.shape[0], n, _p(ct), _p(s), _p(m))
-        return m
+        ct = _c(ct, np.uint64)
+        flat = ct.ndim == 2
+        B, F, n1, C = (1, ct.shape[0], ct.shape[1], 1) if flat else ct.shape
+        assert n1 == n + 1
+        m = np.empty((B, C, F), dtype=np.uint32)
+        self.lib.or_decrypt(p, B, C, F, n, _p(ct), _p(s), _p(m))
+        return m.reshape(F) if flat else m
 
     def homconv(self, ct_in, w_hat, r, p: int) -> np.ndarray:
-        """ct_in[B][Cin][F][n+1], w_hat[Cout][Cin][F], r[B][Cout][F] -> ct_out[B][Cout][F][n+1]."""
+        """ct_in[B][F][n+1][Cin], w_hat[Cout][Cin][F], r[B][Cout][F] -> ct_out[B][F][n+1][Cout]."""
         ct_in = _c(ct_in, np.uint64)
         w_hat = _c(w_hat, np.uint32)
         r = _c(r, np.uint32)
-        B, Cin, F, n1 = ct_in.shape
+        B, F, n1, Cin = ct_in.shape
         Cout = w_hat.shape[0]
         assert w_hat.shape == (Cout, Cin, F) and r.shape == (B, Cout, F)
-        out = np.empty((B, Cout, F, n1), dtype=np.uint64)
+        out = np.empty((B, F, n1, Cout), dtype=np.uint64)
         self.lib.or_homconv(p, B, Cin, Cout, F, n1 - 1, _p(ct_in), _p(w_hat), _p(r), _p(out))
         return out
 
     def homconv_select(self, ct_in, w_hat, r, sel, p: int) -> np.ndarray:
-        """Output rows for the (b, o, f) triples in sel[k] -> [k][n+1]."""
+        """Output ciphertexts for the (b, o, f) triples in sel[k] -> words [k][n+1]."""
         ct_in = _c(ct_in, np.uint64)
         w_hat = _c(w_hat, np.uint32)
         r = _c(r, np.uint32)
         sel = _c(sel, np.int64).reshape(-1, 3)
-        B, Cin, F, n1 = ct_in.shape
+        B, F, n1, Cin = ct_in.shape
         Cout = w_hat.shape[0]
         out = np.empty((sel.shape[0], n1), dtype=np.uint64)
         self.lib.or_homconv_select(p, B, Cin, Cout, F, n1 - 1, _p(ct_in), _p(w_hat), _p(r), sel.shape[0], _p(sel), _p(out))
@@ -188,9 +198,9 @@ class Oracle:
         S = inp.shape
         x_hat = self.ntt2d(inp.x, p).reshape(S.B, S.Cin, S.F)
         w_hat = self.weight_prep(inp.w, S.H, S.W, p)
-        ct_in = self.encrypt(x_hat, inp.s, inp.e, inp.seed_a, p).reshape(S.B, S.Cin, S.F, S.n + 1)
-        ct_out = self.homconv(ct_in, w_hat, inp.r, p)
-        m = self.decrypt(ct_out, inp.s, p).reshape(S.B, S.Cout, S.F)
+        ct_in = self.encrypt(x_hat, inp.s, inp.e, inp.seed_a, p)  # [B][F][n+1][Cin]
+        ct_out = self.homconv(ct_in, w_hat, inp.r, p)  # [B][F][n+1][Cout]
+        m = self.decrypt(ct_out, inp.s, p)  # [B][Cout][F]
         s_a = self.ntt2d(m.reshape(S.B, S.Cout, S.H, S.W), p, inverse=True)
         s_b = self.server_share(inp.r, S.H, S.W, p)
         return dict(x_hat=x_hat, w_hat=w_hat, ct_in=ct_in, ct_out=ct_out, m=m, s_a=s_a, s_b=s_b)

@@ -22,9 +22,13 @@
  *     [a_0 .. a_{n-1}, b] with b = <a, s> + Delta * m + e mod 2^64, which is
  *     the paper's (c0, c1) = (-a, a t + (q/p) u + e0) of Eq. (bfv_enc) with one
  *     coefficient per ciphertext; Delta = floor(2^64 / p);
+ *   - storage (a layout the paper leaves open): the ciphertexts of channel c,
+ *     frequency f, image b are stored word-major, word j at
+ *     ct[b][f][j][c] (C channels innermost); ciphertext index
+ *     q = (b F + f) C + c. With C = 1 this is a plain list of rows [N][n+1];
  *   - the a-words come from the SplitMix64 generator (Steele, Lea and Flood,
- *     OOPSLA 2014): word j of global ciphertext c is output number
- *     c * n + j + 1 of the generator seeded with seed_a;
+ *     OOPSLA 2014): word j of ciphertext q is output number
+ *     (q0 + q) n + j + 1 of the generator seeded with seed_a;
  *   - HomConv: for every frequency f, ct_out[o,f] = sum_i W^[o,i,f] ct_in[i,f]
  *     mod 2^64 (the homomorphic Hadamard product with a plaintext, summed over
  *     input channels), then Delta * r[o,f] is added to the b word (HomShare,
@@ -220,86 +224,95 @@ uint64_t or_splitmix64(uint64_t seed, uint64_t k) {
 
 uint64_t or_delta(uint64_t p) { return (uint64_t)((((u128)1) << 64) / p); }
 
-/* Enc of num_ct plaintexts m[c] in [0,p) under ternary key s (Eq. (bfv_enc),
- * one coefficient per ciphertext). ct is [num_ct][n+1]. */
-void or_encrypt(uint64_t p, int64_t num_ct, int n, const uint32_t *m, const int8_t *s, const int32_t *e,
-                uint64_t seed_a, uint64_t ct_index0, uint64_t *ct) {
+/* Enc of the B*C*F plaintexts m[b][c][f] in [0,p) under ternary key s
+ * (Eq. (bfv_enc), one coefficient per ciphertext), e[b][c][f] the errors.
+ * ct is [B][F][n+1][C]: ciphertext (b, c, f) has word j at ct[b][f][j][c]. */
+void or_encrypt(uint64_t p, int64_t B, int C, int64_t F, int n, const uint32_t *m, const int8_t *s,
+                const int32_t *e, uint64_t seed_a, uint64_t ct_index0, uint64_t *ct) {
     uint64_t delta = or_delta(p);
-#pragma omp parallel for schedule(static)
-    for (int64_t c = 0; c < num_ct; ++c) {
-        uint64_t gidx = ct_index0 + (uint64_t)c, dot = 0;
-        uint64_t *row = ct + c * (int64_t)(n + 1);
-        for (int j = 0; j < n; ++j) {
-            uint64_t a = or_splitmix64(seed_a, gidx * (uint64_t)n + (uint64_t)j + 1);
-            row[j] = a;
-            if (s[j] == 1) dot += a;
-            else if (s[j] == -1) dot -= a;
-        }
-        row[n] = dot + (uint64_t)(int64_t)e[c] + delta * (uint64_t)m[c];
-    }
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t b = 0; b < B; ++b)
+        for (int64_t f = 0; f < F; ++f)
+            for (int c = 0; c < C; ++c) {
+                uint64_t q = (uint64_t)((b * F + f) * C + c), dot = 0;
+                uint64_t *w = ct + (b * F + f) * (int64_t)(n + 1) * C + c; /* word j at w[j * C] */
+                for (int j = 0; j < n; ++j) {
+                    uint64_t a = or_splitmix64(seed_a, (ct_index0 + q) * (uint64_t)n + (uint64_t)j + 1);
+                    w[(int64_t)j * C] = a;
+                    if (s[j] == 1) dot += a;
+                    else if (s[j] == -1) dot -= a;
+                }
+                int64_t mi = (b * C + c) * F + f;
+                w[(int64_t)n * C] = dot + (uint64_t)(int64_t)e[mi] + delta * (uint64_t)m[mi];
+            }
 }
 
-/* Decryption phase phi = b - <a, s> mod 2^64 of one ciphertext row. */
-uint64_t or_phase(int n, const uint64_t *row, const int8_t *s) {
+/* Decryption phase phi = b - <a, s> mod 2^64 of one ciphertext whose word j
+ * is at w[j * stride]. */
+uint64_t or_phase(int n, const uint64_t *w, int64_t stride, const int8_t *s) {
     uint64_t dot = 0;
     for (int j = 0; j < n; ++j) {
-        if (s[j] == 1) dot += row[j];
-        else if (s[j] == -1) dot -= row[j];
+        if (s[j] == 1) dot += w[j * stride];
+        else if (s[j] == -1) dot -= w[j * stride];
     }
-    return row[n] - dot;
+    return w[(int64_t)n * stride] - dot;
 }
 
-/* Dec: m = floor((phi * p + 2^63) / 2^64) mod p, in exact 128-bit arithmetic. */
-void or_decrypt(uint64_t p, int64_t num_ct, int n, const uint64_t *ct, const int8_t *s, uint32_t *m) {
-#pragma omp parallel for schedule(static)
-    for (int64_t c = 0; c < num_ct; ++c) {
-        uint64_t phi = or_phase(n, ct + c * (int64_t)(n + 1), s);
-        u128 t = (u128)phi * p + (((u128)1) << 63);
-        uint64_t v = (uint64_t)(t >> 64);
-        m[c] = (uint32_t)(v % p);
-    }
+/* Dec of ct [B][F][n+1][C] into m[b][c][f]:
+ * m = floor((phi * p + 2^63) / 2^64) mod p, in exact 128-bit arithmetic. */
+void or_decrypt(uint64_t p, int64_t B, int C, int64_t F, int n, const uint64_t *ct, const int8_t *s,
+                uint32_t *m) {
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t b = 0; b < B; ++b)
+        for (int64_t f = 0; f < F; ++f)
+            for (int c = 0; c < C; ++c) {
+                uint64_t phi = or_phase(n, ct + (b * F + f) * (int64_t)(n + 1) * C + c, C, s);
+                u128 t = (u128)phi * p + (((u128)1) << 63);
+                uint64_t v = (uint64_t)(t >> 64);
+                m[(b * C + c) * F + f] = (uint32_t)(v % p);
+            }
 }
 
 /* --------------------------------------------------------- HomConv --- */
 
-/* One output ciphertext row of HomConv for (image b, output channel o,
- * frequency f): sum_i W^[o,i,f] * ct_in[b,i,f,:] mod 2^64, then
- * + Delta * r[b,o,f] on the b word. ct_in [B][Cin][F][n+1],
- * w_hat [Cout][Cin][F] (integers in [0,p)), r [B][Cout][F]. */
-static void homconv_row(uint64_t p, int Cin, int Cout, int64_t F, int n, const uint64_t *ct_in,
+/* One output ciphertext of HomConv for (image b, output channel o,
+ * frequency f): sum_i W^[o,i,f] * ct_in(b, i, f) mod 2^64 word by word, then
+ * + Delta * r[b,o,f] on the b word. ct_in [B][F][n+1][Cin],
+ * w_hat [Cout][Cin][F] (integers in [0,p)), r [B][Cout][F]; the result's
+ * word j goes to out[j * ostride]. */
+static void homconv_one(uint64_t p, int Cin, int Cout, int64_t F, int n, const uint64_t *ct_in,
                         const uint32_t *w_hat, const uint32_t *r, int64_t b, int64_t o, int64_t f,
-                        uint64_t *out_row) {
-    int64_t row = n + 1;
+                        uint64_t *out, int64_t ostride) {
+    const uint64_t *blk = ct_in + (b * F + f) * (int64_t)(n + 1) * Cin;
     for (int j = 0; j <= n; ++j) {
         uint64_t acc = 0;
         for (int i = 0; i < Cin; ++i)
-            acc += (uint64_t)w_hat[(o * Cin + i) * F + f] * ct_in[((b * Cin + i) * F + f) * row + j];
-        out_row[j] = acc;
+            acc += (uint64_t)w_hat[(o * Cin + i) * F + f] * blk[(int64_t)j * Cin + i];
+        out[j * ostride] = acc;
     }
-    out_row[n] += or_delta(p) * (uint64_t)r[(b * Cout + o) * F + f];
+    out[n * ostride] += or_delta(p) * (uint64_t)r[(b * Cout + o) * F + f];
 }
 
 void or_homconv(uint64_t p, int B, int Cin, int Cout, int64_t F, int n, const uint64_t *ct_in,
                 const uint32_t *w_hat, const uint32_t *r, uint64_t *ct_out) {
-    int64_t row = n + 1;
 #pragma omp parallel for collapse(3) schedule(static)
     for (int64_t b = 0; b < B; ++b)
-        for (int64_t o = 0; o < Cout; ++o)
-            for (int64_t f = 0; f < F; ++f)
-                homconv_row(p, Cin, Cout, F, n, ct_in, w_hat, r, b, o, f,
-                            ct_out + ((b * Cout + o) * F + f) * row);
+        for (int64_t f = 0; f < F; ++f)
+            for (int64_t o = 0; o < Cout; ++o)
+                homconv_one(p, Cin, Cout, F, n, ct_in, w_hat, r, b, o, f,
+                            ct_out + (b * F + f) * (int64_t)(n + 1) * Cout + o, Cout);
 }
 
-/* HomConv restricted to the listed output rows: sel holds nsel triples
- * (b, o, f); out is [nsel][n+1]. */
+/* HomConv restricted to the listed outputs: sel holds nsel triples
+ * (b, o, f); out is [nsel][n+1] (one ciphertext's words per row). */
 void or_homconv_select(uint64_t p, int B, int Cin, int Cout, int64_t F, int n, const uint64_t *ct_in,
                        const uint32_t *w_hat, const uint32_t *r, int64_t nsel, const int64_t *sel,
                        uint64_t *out) {
     (void)B;
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < nsel; ++k)
-        homconv_row(p, Cin, Cout, F, n, ct_in, w_hat, r, sel[3 * k], sel[3 * k + 1], sel[3 * k + 2],
-                    out + k * (int64_t)(n + 1));
+        homconv_one(p, Cin, Cout, F, n, ct_in, w_hat, r, sel[3 * k], sel[3 * k + 1], sel[3 * k + 2],
+                    out + k * (int64_t)(n + 1), 1);
 }
 
 /* The server's spatial share s_B = INTT2D(-r mod p) (Sec. 4.1, "Line 4-6"). */

@@ -1,13 +1,17 @@
 // LWE encryption and decryption over q = 2^64 (one ciphertext per frequency
-// coefficient): streaming, HBM-bound matrix-vector kernels.
+// coefficient): streaming, HBM-bound matrix-vector kernels over the
+// word-major ciphertext layout ct[b][f][j][c].
 //
-// One wave owns one ciphertext row of n+1 words at a time: lane l touches
-// words l, l+64, ... so every wave instruction moves 512 contiguous bytes.
-// The key s (n ternary bytes) sits in LDS; the row's inner product <a, s>
-// is accumulated per lane and summed across the wave with DPP/ds_swizzle
-// shuffles. Encryption generates the uniform a-words on the fly with a
-// counter-based SplitMix64, so its only HBM traffic is the ciphertext
-// written (plus 8 bytes of m and e per row).
+// A workgroup owns a group of up to 64 ciphertexts that sit side by side in
+// memory: 64 channels of one (b, f) when C >= 64, else floor(64 / C)
+// consecutive frequencies of all C channels. Lane = ciphertext, so every
+// wave instruction moves the group's word j of all its ciphertexts - one
+// contiguous 512-byte run when C >= 64. The four waves split the word range
+// [0, n) into quarters; the key byte s_j is the same for every lane (read from
+// LDS as a broadcast), each lane accumulates its own <a, s> and the four
+// partial sums meet in LDS. Encryption generates the uniform a-words on the
+// fly with a counter-based SplitMix64, so its only HBM traffic is the
+// ciphertexts written (plus 8 bytes of m and e per ciphertext).
 #include "ensei_internal.hpp"
 
 namespace ensei {
@@ -22,49 +26,106 @@ __device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const uint32_t lo = __shfl_xor((uint32_t)v, off, 64);
-        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), off, 64);
-        v += ((uint64_t)hi << 32) | lo;
-    }
-    return v;
+// Group geometry shared by Enc and Dec.
+struct LweGroups {
+    int lanes_per_f;  // min(C, 64)
+    int f_per_group;  // 64 / lanes_per_f (1 when C >= 64)
+    int c_blocks;     // ceil(C / 64) (1 when C < 64)
+    int64_t f_groups; // ceil(F / f_per_group)
+};
+
+__host__ __device__ inline LweGroups lwe_groups(int C, int64_t F) {
+    LweGroups g;
+    g.lanes_per_f = C < 64 ? C : 64;
+    g.f_per_group = 64 / g.lanes_per_f;
+    g.c_blocks = (C + 63) / 64;
+    g.f_groups = (F + g.f_per_group - 1) / g.f_per_group;
+    return g;
 }
 
-// s_j * a mod 2^64 for s_j in {-1, 0, 1}.
-__device__ __forceinline__ uint64_t ternary_times(int8_t sj, uint64_t a) {
-    const uint64_t nz = sj != 0 ? ~0ull : 0ull;
-    const uint64_t neg = sj < 0 ? ~0ull : 0ull;
-    return ((a & nz) ^ neg) - neg;  // (x ^ -1) + 1 = -x
+// Position of this lane's ciphertext: (b, f, c), and whether it exists.
+struct LweLane {
+    int64_t b, f;
+    int c;
+    bool ok;
+};
+
+__device__ __forceinline__ LweLane lwe_lane(const LweGroups &G, int C, int64_t F, int64_t group, int lane) {
+    LweLane L;
+    const int cb = (int)(group % G.c_blocks);
+    const int64_t rest = group / G.c_blocks;
+    const int64_t fg = rest % G.f_groups;
+    L.b = rest / G.f_groups;
+    const int fl = lane / G.lanes_per_f;
+    L.c = cb * 64 + lane % G.lanes_per_f;
+    L.f = fg * G.f_per_group + fl;
+    L.ok = fl < G.f_per_group && L.f < F && L.c < C;
+    return L;
 }
 
-constexpr int kWavesPerBlock = 4;
+constexpr int kWaves = 4;
+
+// Key bytes s_j .. s_j+3 (the same for every lane) from the LDS copy of the
+// key, moved to a scalar register; j is a multiple of 4.
+__device__ __forceinline__ uint32_t key4(const int8_t *key, int j) {
+    return __builtin_amdgcn_readfirstlane(*reinterpret_cast<const uint32_t *>(key + j));
+}
+
+// All-ones when the key byte k of `k4` is +1 (pos) / -1 (neg), else zero.
+__device__ __forceinline__ uint64_t key_mask(uint32_t k4, int k, int sign) {
+    const int sj = (int)(int8_t)(k4 >> (8 * k));
+    return sj == sign ? ~0ull : 0ull;
+}
 
 __global__ __launch_bounds__(256) void encrypt_kernel(const uint32_t *__restrict__ m, const int8_t *__restrict__ s,
-                                                      const int32_t *__restrict__ e, int64_t num_ct, int n,
+                                                      const int32_t *__restrict__ e, int C, int64_t F, int n,
                                                       uint64_t seed_a, uint64_t ct_index0, uint64_t delta,
-                                                      uint64_t *__restrict__ ct) {
-    extern __shared__ int8_t key[];
+                                                      uint64_t *__restrict__ ct, LweGroups G) {
+    extern __shared__ uint8_t smem[];  // key bytes (n, padded to 8) then kWaves x 64 partial sums
+    int8_t *key = reinterpret_cast<int8_t *>(smem);
+    uint64_t *part = reinterpret_cast<uint64_t *>(smem + ((n + 7) & ~7));
     for (int i = threadIdx.x; i < n; i += blockDim.x) key[i] = s[i];
     __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
-    const uint64_t step = kGamma * 64;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const LweLane L = lwe_lane(G, C, F, blockIdx.x, lane);
     const int64_t rowlen = (int64_t)n + 1;
-    for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); c < num_ct; c += stride) {
-        uint64_t *row = ct + c * rowlen;
-        uint64_t z = seed_a + ((ct_index0 + (uint64_t)c) * (uint64_t)n + (uint64_t)lane + 1) * kGamma;
-        uint64_t acc = 0;
-#pragma unroll 4
-        for (int j = lane; j < n; j += 64) {
-            const uint64_t a = splitmix_mix(z);
-            row[j] = a;
-            acc += ternary_times(key[j], a);
-            z += step;
+    const int64_t q = (L.b * F + L.f) * C + L.c;                     // ciphertext index
+    uint64_t *w = ct + (L.b * F + L.f) * rowlen * C + L.c;           // word j at w[j * C]
+    // word range of this wave, starting on a multiple of 4 (4-byte key reads)
+    const int per = ((n + 4 * kWaves - 1) / (4 * kWaves)) * 4, j0 = wave * per, j1 = min(n, j0 + per);
+    uint64_t z = seed_a + ((ct_index0 + (uint64_t)q) * (uint64_t)n + (uint64_t)j0 + 1) * kGamma;
+    // <a, s> as (sum over s_j = +1) - (sum over s_j = -1), selected with
+    // wave-uniform masks
+    uint64_t acc_p = 0, acc_n = 0;
+    if (L.ok) {
+        int j = j0;
+        for (; j + 4 <= j1; j += 4) {
+            const uint32_t k4 = key4(key, j);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint64_t a = splitmix_mix(z);
+                z += kGamma;
+                w[(int64_t)(j + k) * C] = a;
+                acc_p += a & key_mask(k4, k, 1);
+                acc_n += a & key_mask(k4, k, -1);
+            }
         }
-        acc = wave_sum_u64(acc);
-        if (lane == 0) row[n] = acc + (uint64_t)(int64_t)e[c] + delta * (uint64_t)m[c];
+        for (; j < j1; ++j) {
+            const uint64_t a = splitmix_mix(z);
+            z += kGamma;
+            w[(int64_t)j * C] = a;
+            const uint32_t k1 = __builtin_amdgcn_readfirstlane((uint32_t)(uint8_t)key[j]);
+            acc_p += a & key_mask(k1, 0, 1);
+            acc_n += a & key_mask(k1, 0, -1);
+        }
+    }
+    part[wave * 64 + lane] = acc_p - acc_n;
+    __syncthreads();
+    if (wave == 0 && L.ok) {
+        const uint64_t dot = part[lane] + part[64 + lane] + part[128 + lane] + part[192 + lane];
+        const int64_t mi = (L.b * C + L.c) * F + L.f;
+        w[(int64_t)n * C] = dot + (uint64_t)(int64_t)e[mi] + delta * (uint64_t)m[mi];
     }
 }
 
@@ -79,36 +140,62 @@ __device__ __forceinline__ uint32_t decode(uint64_t phi, uint32_t p) {
 }
 
 __global__ __launch_bounds__(256) void decrypt_kernel(const uint64_t *__restrict__ ct, const int8_t *__restrict__ s,
-                                                      int64_t num_ct, int n, uint32_t p, uint32_t *__restrict__ m) {
-    extern __shared__ int8_t key[];
+                                                      int C, int64_t F, int n, uint32_t p, uint32_t *__restrict__ m,
+                                                      LweGroups G) {
+    extern __shared__ uint8_t smem[];
+    int8_t *key = reinterpret_cast<int8_t *>(smem);
+    uint64_t *part = reinterpret_cast<uint64_t *>(smem + ((n + 7) & ~7));
     for (int i = threadIdx.x; i < n; i += blockDim.x) key[i] = s[i];
     __syncthreads();
-    const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * kWavesPerBlock;
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const LweLane L = lwe_lane(G, C, F, blockIdx.x, lane);
     const int64_t rowlen = (int64_t)n + 1;
-    for (int64_t c = (int64_t)blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); c < num_ct; c += stride) {
-        const uint64_t *row = ct + c * rowlen;
-        const uint64_t bword = row[n];  // same address in every lane: one transaction, issued first
-        uint64_t acc = 0;
-        int j = lane;
+    const uint64_t *w = ct + (L.b * F + L.f) * rowlen * C + L.c;
+    // word range of this wave, starting on a multiple of 4 (4-byte key reads)
+    const int per = ((n + 4 * kWaves - 1) / (4 * kWaves)) * 4, j0 = wave * per, j1 = min(n, j0 + per);
+    uint64_t acc_p = 0, acc_n = 0;
+    if (L.ok) {
+        int j = j0;
         // 16 words per lane in flight at once
-        for (; j + 64 * 15 < n; j += 64 * 16) {
-            uint64_t w[16];
+        for (; j + 16 <= j1; j += 16) {
+            uint64_t x[16];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) w[k] = row[j + 64 * k];
+            for (int k = 0; k < 16; ++k) x[k] = w[(int64_t)(j + k) * C];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) acc += ternary_times(key[j + 64 * k], w[k]);
+            for (int k4i = 0; k4i < 4; ++k4i) {
+                const uint32_t k4 = key4(key, j + 4 * k4i);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    acc_p += x[4 * k4i + k] & key_mask(k4, k, 1);
+                    acc_n += x[4 * k4i + k] & key_mask(k4, k, -1);
+                }
+            }
         }
-        for (; j < n; j += 64) acc += ternary_times(key[j], row[j]);
-        acc = wave_sum_u64(acc);
-        if (lane == 0) m[c] = decode(bword - acc, p);
+        for (; j < j1; ++j) {
+            const uint64_t x = w[(int64_t)j * C];
+            const uint32_t k1 = __builtin_amdgcn_readfirstlane((uint32_t)(uint8_t)key[j]);
+            acc_p += x & key_mask(k1, 0, 1);
+            acc_n += x & key_mask(k1, 0, -1);
+        }
+    }
+    part[wave * 64 + lane] = acc_p - acc_n;
+    __syncthreads();
+    if (wave == 0 && L.ok) {
+        const uint64_t dot = part[lane] + part[64 + lane] + part[128 + lane] + part[192 + lane];
+        m[(L.b * C + L.c) * F + L.f] = decode(w[(int64_t)n * C] - dot, p);
     }
 }
 
-static int64_t lwe_grid(int64_t num_ct) {
-    int64_t blocks = (num_ct + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int64_t cap = 256 * 16;  // CUs x resident blocks: enough waves to keep HBM busy
-    return blocks < cap ? blocks : cap;
+static int check_lwe(const ensei_ctx *ctx, int64_t B, int C, int64_t F, int n, int64_t *groups) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (B <= 0 || C <= 0 || F <= 0 || n <= 0) return ENSEI_ERR_ARG;
+    if (n > ENSEI_MAX_LWE_N) return ENSEI_ERR_LIMIT;
+    const LweGroups G = lwe_groups(C, F);
+    *groups = B * G.f_groups * G.c_blocks;
+    if (*groups > 0x7fffffff) return ENSEI_ERR_LIMIT;
+    return ENSEI_OK;
 }
 
 }  // namespace ensei
@@ -117,34 +204,34 @@ using namespace ensei;
 
 extern "C" {
 
-int ensei_encrypt(ensei_ctx *ctx, const uint32_t *m, const int8_t *s, const int32_t *e, int64_t num_ct, int n,
-                  uint64_t seed_a, uint64_t ct_index0, uint64_t *ct, void *stream) {
-    int st = check_ctx(ctx);
+int ensei_encrypt(ensei_ctx *ctx, const uint32_t *m, const int8_t *s, const int32_t *e, int64_t batch, int C,
+                  int64_t F, int n, uint64_t seed_a, uint64_t ct_index0, uint64_t *ct, void *stream) {
+    int64_t groups;
+    int st = check_lwe(ctx, batch, C, F, n, &groups);
     if (st) return st;
-    if (!m || !s || !e || !ct || num_ct <= 0 || n <= 0) return ENSEI_ERR_ARG;
-    if (n > ENSEI_MAX_LWE_N) return ENSEI_ERR_LIMIT;
+    if (!m || !s || !e || !ct) return ENSEI_ERR_ARG;
     if (((uintptr_t)m & 3) || ((uintptr_t)e & 3) || ((uintptr_t)ct & 7)) return ENSEI_ERR_ALIGN;
-    const size_t ctb = (size_t)num_ct * (n + 1) * 8;
-    if (overlaps(ct, ctb, m, (size_t)num_ct * 4) || overlaps(ct, ctb, e, (size_t)num_ct * 4) ||
-        overlaps(ct, ctb, s, (size_t)n))
+    const size_t num = (size_t)batch * C * F, ctb = num * (n + 1) * 8;
+    if (overlaps(ct, ctb, m, num * 4) || overlaps(ct, ctb, e, num * 4) || overlaps(ct, ctb, s, (size_t)n))
         return ENSEI_ERR_OVERLAP;
-    hipLaunchKernelGGL(encrypt_kernel, dim3((unsigned)lwe_grid(num_ct)), dim3(256), (size_t)n, (hipStream_t)stream, m,
-                       s, e, num_ct, n, seed_a, ct_index0, ctx->delta, ct);
+    const size_t smem = ((n + 7) & ~7) + kWaves * 64 * 8;
+    hipLaunchKernelGGL(encrypt_kernel, dim3((unsigned)groups), dim3(256), smem, (hipStream_t)stream, m, s, e, C, F, n,
+                       seed_a, ct_index0, ctx->delta, ct, lwe_groups(C, F));
     return launch_status();
 }
 
-int ensei_decrypt(ensei_ctx *ctx, const uint64_t *ct, const int8_t *s, int64_t num_ct, int n, uint32_t *m,
-                  void *stream) {
-    int st = check_ctx(ctx);
+int ensei_decrypt(ensei_ctx *ctx, const uint64_t *ct, const int8_t *s, int64_t batch, int C, int64_t F, int n,
+                  uint32_t *m, void *stream) {
+    int64_t groups;
+    int st = check_lwe(ctx, batch, C, F, n, &groups);
     if (st) return st;
-    if (!m || !s || !ct || num_ct <= 0 || n <= 0) return ENSEI_ERR_ARG;
-    if (n > ENSEI_MAX_LWE_N) return ENSEI_ERR_LIMIT;
+    if (!m || !s || !ct) return ENSEI_ERR_ARG;
     if (((uintptr_t)m & 3) || ((uintptr_t)ct & 7)) return ENSEI_ERR_ALIGN;
-    const size_t ctb = (size_t)num_ct * (n + 1) * 8;
-    if (overlaps(m, (size_t)num_ct * 4, ct, ctb) || overlaps(m, (size_t)num_ct * 4, s, (size_t)n))
-        return ENSEI_ERR_OVERLAP;
-    hipLaunchKernelGGL(decrypt_kernel, dim3((unsigned)lwe_grid(num_ct)), dim3(256), (size_t)n, (hipStream_t)stream, ct,
-                       s, num_ct, n, ctx->p, m);
+    const size_t num = (size_t)batch * C * F, ctb = num * (n + 1) * 8;
+    if (overlaps(m, num * 4, ct, ctb) || overlaps(m, num * 4, s, (size_t)n)) return ENSEI_ERR_OVERLAP;
+    const size_t smem = ((n + 7) & ~7) + kWaves * 64 * 8;
+    hipLaunchKernelGGL(decrypt_kernel, dim3((unsigned)groups), dim3(256), smem, (hipStream_t)stream, ct, s, C, F, n,
+                       ctx->p, m, lwe_groups(C, F));
     return launch_status();
 }
 

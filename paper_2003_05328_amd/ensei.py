@@ -47,10 +47,10 @@ SIGNATURES = {
     "ensei_weight_prep": (_i32, [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp, _vp]),
     "ensei_wpack_bytes": (C.c_size_t, [_i32, _i32, _i64]),
     "ensei_pack_weights": (_i32, [_vp, _vp, _i32, _i32, _i64, _vp, _vp]),
-    "ensei_encrypt": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _u64, _u64, _vp, _vp]),
+    "ensei_encrypt": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i64, _i32, _u64, _u64, _vp, _vp]),
     "ensei_homconv": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
     "ensei_homconv_valu": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
-    "ensei_decrypt": (_i32, [_vp, _vp, _vp, _i64, _i32, _vp, _vp]),
+    "ensei_decrypt": (_i32, [_vp, _vp, _vp, _i64, _i32, _i64, _i32, _vp, _vp]),
 }
 
 
@@ -189,44 +189,57 @@ class Context:
 
     # -- LWE -----------------------------------------------------------------
     def encrypt(self, m, s, e, seed_a: int, ct_index0: int = 0, out=None) -> torch.Tensor:
-        """m uint32 [...], s int8 [n], e int32 [...] -> ct uint64 [..., n+1] (ensei_encrypt)."""
+        """m uint32 [B][C][F] (or [N]), s int8 [n], e int32 like m -> word-major
+        ct uint64 [B][F][n+1][C] (or [N][n+1] for a 1-D list) (ensei_encrypt)."""
         self._dev(m, "m", torch.uint32)
         self._dev(s, "s", torch.int8)
         self._dev(e, "e", torch.int32)
         if e.numel() != m.numel():
             raise ValueError("e must have one error per plaintext")
         n = s.numel()
-        out = self._empty(m.shape + (n + 1,), torch.uint64) if out is None else self._dev(out, "out", torch.uint64)
-        self._call("ensei_encrypt", _ptr(m), _ptr(s), _ptr(e), m.numel(), n, seed_a % 2**64, ct_index0 % 2**64, _ptr(out))
+        flat = m.dim() == 1
+        B, C, F = (1, 1, m.shape[0]) if flat else tuple(m.shape)
+        shape = (F, n + 1) if flat else (B, F, n + 1, C)
+        out = self._empty(shape, torch.uint64) if out is None else self._dev(out, "out", torch.uint64)
+        if out.numel() != B * C * F * (n + 1):
+            raise ValueError("ct has the wrong size")
+        self._call("ensei_encrypt", _ptr(m), _ptr(s), _ptr(e), B, C, F, n, seed_a % 2**64, ct_index0 % 2**64, _ptr(out))
         return out
 
     def decrypt(self, ct, s, out=None) -> torch.Tensor:
-        """ct uint64 [..., n+1], s int8 [n] -> m uint32 [...] (ensei_decrypt)."""
+        """Word-major ct uint64 [B][F][n+1][C] (or rows [N][n+1]), s int8 [n] ->
+        m uint32 [B][C][F] (or [N]) (ensei_decrypt)."""
         self._dev(ct, "ct", torch.uint64)
         self._dev(s, "s", torch.int8)
         n = s.numel()
-        if ct.shape[-1] != n + 1:
-            raise ValueError("ct rows must have n+1 words")
-        out = self._empty(ct.shape[:-1], torch.uint32) if out is None else self._dev(out, "out", torch.uint32)
-        self._call("ensei_decrypt", _ptr(ct), _ptr(s), ct.numel() // (n + 1), n, _ptr(out))
+        flat = ct.dim() == 2
+        if flat:
+            B, F, n1, C = 1, ct.shape[0], ct.shape[1], 1
+        else:
+            B, F, n1, C = tuple(ct.shape)
+        if n1 != n + 1:
+            raise ValueError("ciphertexts must have n+1 words")
+        shape = (F,) if flat else (B, C, F)
+        out = self._empty(shape, torch.uint32) if out is None else self._dev(out, "out", torch.uint32)
+        self._call("ensei_decrypt", _ptr(ct), _ptr(s), B, C, F, n, _ptr(out))
         return out
 
     # -- HomConv ---------------------------------------------------------------
     def _hc_shapes(self, ct_in, Cout, r):
-        B, Cin, F, n1 = ct_in.shape
+        B, F, n1, Cin = ct_in.shape  # word-major [B][F][n+1][Cin]
         if tuple(r.shape) != (B, Cout, F):
             raise ValueError(f"r must be [B][Cout][F] = {(B, Cout, F)}")
         return B, Cin, F, n1 - 1
 
     def homconv(self, ct_in, w_pack, r, Cout: int, out=None) -> torch.Tensor:
-        """ct_in uint64 [B][Cin][F][n+1], packed W^, r uint32 [B][Cout][F] -> ct_out (ensei_homconv)."""
+        """ct_in uint64 [B][F][n+1][Cin], packed W^, r uint32 [B][Cout][F] -> ct_out [B][F][n+1][Cout] (ensei_homconv)."""
         self._dev(ct_in, "ct_in", torch.uint64)
         self._dev(w_pack, "w_pack", torch.int8)
         self._dev(r, "r", torch.uint32)
         B, Cin, F, n = self._hc_shapes(ct_in, Cout, r)
         if w_pack.numel() < int(lib().ensei_wpack_bytes(Cout, Cin, F)):
             raise ValueError("w_pack is smaller than ensei_wpack_bytes(Cout, Cin, F)")
-        out = self._empty((B, Cout, F, n + 1), torch.uint64) if out is None else self._dev(out, "out", torch.uint64)
+        out = self._empty((B, F, n + 1, Cout), torch.uint64) if out is None else self._dev(out, "out", torch.uint64)
         self._call("ensei_homconv", _ptr(ct_in), _ptr(w_pack), _ptr(r), B, Cin, Cout, F, n, _ptr(out))
         return out
 
@@ -239,6 +252,6 @@ class Context:
         B, Cin, F, n = self._hc_shapes(ct_in, Cout, r)
         if tuple(w_hat.shape) != (Cout, Cin, F):
             raise ValueError("w_hat must be [Cout][Cin][F]")
-        out = self._empty((B, Cout, F, n + 1), torch.uint64) if out is None else self._dev(out, "out", torch.uint64)
+        out = self._empty((B, F, n + 1, Cout), torch.uint64) if out is None else self._dev(out, "out", torch.uint64)
         self._call("ensei_homconv_valu", _ptr(ct_in), _ptr(w_hat), _ptr(r), B, Cin, Cout, F, n, _ptr(out))
         return out

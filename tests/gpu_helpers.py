@@ -17,31 +17,26 @@ def host(t: torch.Tensor) -> np.ndarray:
     return t.cpu().numpy()
 
 
-def rows_u64(t: torch.Tensor, flat_rows: np.ndarray) -> np.ndarray:
-    """Gather rows of a uint64 [..., n+1] device tensor at flat row indices."""
-    n1 = t.shape[-1]
-    v = t.view(torch.int64).reshape(-1, n1)
-    idx = torch.from_numpy(np.asarray(flat_rows, dtype=np.int64)).to(t.device)
-    return host(v.index_select(0, idx)).view(np.uint64)
+def ct_words(t: torch.Tensor, b: int, f: int, c: int) -> np.ndarray:
+    """The n+1 words of ciphertext (b, c, f) of a word-major [B][F][n+1][C] tensor."""
+    return host(t.view(torch.int64)[b, f, :, c].contiguous()).view(np.uint64)
 
 
 def oracle_ct_in_rows(orc, x_hat: np.ndarray, inp, b: int, f: int) -> np.ndarray:
-    """The oracle's ciphertexts ct_in[b][:, f, :] ([Cin][n+1]) encrypted one by
-    one with their global ciphertext index c = (b*Cin + i)*F + f."""
+    """The oracle's ciphertexts of (b, :, f) ([Cin][n+1]), encrypted one by one
+    with their ciphertext index q = (b*F + f)*Cin + i."""
     S = inp.shape
     out = np.empty((S.Cin, S.n + 1), dtype=np.uint64)
     for i in range(S.Cin):
-        c = (b * S.Cin + i) * S.F + f
-        out[i] = orc.encrypt(
-            x_hat[b, i, f : f + 1], inp.s, inp.e[b, i, f : f + 1], inp.seed_a, P, ct_index0=c
-        )[0]
+        q = (b * S.F + f) * S.Cin + i
+        out[i] = orc.encrypt(x_hat[b, i, f : f + 1], inp.s, inp.e[b, i, f : f + 1], inp.seed_a, P, ct_index0=q)[0]
     return out
 
 
 def oracle_ct_out_row(orc, ct_in_rows: np.ndarray, w_hat: np.ndarray, inp, b: int, o: int, f: int) -> np.ndarray:
-    """The oracle's HomConv output row (b, o, f) from its own ct_in rows."""
+    """The oracle's HomConv output ciphertext (b, o, f) from its own input ciphertexts."""
     S = inp.shape
-    ct = ct_in_rows.reshape(1, S.Cin, 1, S.n + 1)
+    ct = np.ascontiguousarray(ct_in_rows.T).reshape(1, 1, S.n + 1, S.Cin)
     wf = np.ascontiguousarray(w_hat[:, :, f : f + 1])
     rf = np.ascontiguousarray(inp.r[b : b + 1, :, f : f + 1])
     return orc.homconv_select(ct, wf, rf, np.array([[0, o, 0]]), P)[0]

@@ -221,6 +221,23 @@ def check_encrypt(orc):
     # encrypting a slice with its global index gives the same words
     part = orc.encrypt(m[7:], s, e[7:], seed_a, P, ct_index0=c0 + 7)
     assert np.array_equal(part, ct[7:])
+    # word-major storage of B x C x F plaintexts: ciphertext (b, c, f) is number
+    # q = (b F + f) C + c, its word j sits at ct[b][f][j][c]
+    B, C, F = 2, 3, 5
+    m3 = g.integers(0, P, size=(B, C, F)).astype(np.uint32)
+    e3 = synth.rounded_gaussian(9, (B, C, F))
+    ct3 = orc.encrypt(m3, s, e3, seed_a, P)
+    assert ct3.shape == (B, F, n + 1, C)
+    stream = bf.splitmix64_stream(seed_a, B * C * F * n)
+    for b in range(B):
+        for c in range(C):
+            for f in range(F):
+                q = (b * F + f) * C + c
+                a = [int(v) for v in ct3[b, f, :n, c]]
+                assert a == stream[q * n : (q + 1) * n]
+                dot = sum(int(s[j]) * a[j] for j in range(n))
+                assert (int(ct3[b, f, n, c]) - dot - D * int(m3[b, c, f]) - int(e3[b, c, f])) % M64 == 0
+    assert np.array_equal(orc.decrypt(ct3, s, P), m3)
 
 
 def check_decrypt_exhaustive(orc):
@@ -261,33 +278,34 @@ def check_decode_rounding(orc):
 def check_homconv_numpy(orc):
     g = _rng(12)
     B, Cin, Cout, F, n = 2, 5, 3, 8, 7
-    ct = g.integers(0, 2**64, size=(B, Cin, F, n + 1), dtype=np.uint64)
+    ct = g.integers(0, 2**64, size=(B, F, n + 1, Cin), dtype=np.uint64)
     w = g.integers(0, P, size=(Cout, Cin, F)).astype(np.uint32)
     w[0, 0, 0] = P - 1
     r = g.integers(0, P, size=(B, Cout, F)).astype(np.uint32)
     out = orc.homconv(ct, w, r, P)
+    assert out.shape == (B, F, n + 1, Cout)
     D = np.uint64(bf.brute_delta(P))
     for b in range(B):
         for f in range(F):
-            ref = w[:, :, f].astype(np.uint64) @ ct[b, :, f, :]  # uint64 matmul wraps mod 2^64
-            ref[:, n] += D * r[b, :, f].astype(np.uint64)
-            assert np.array_equal(out[b, :, f, :], ref), (b, f)
+            ref = ct[b, f] @ w[:, :, f].T.astype(np.uint64)  # [n+1][Cout], uint64 matmul wraps mod 2^64
+            ref[n, :] += D * r[b, :, f].astype(np.uint64)
+            assert np.array_equal(out[b, f], ref), (b, f)
     sel = np.array([[1, 2, 7], [0, 0, 0], [1, 0, 3]])
     rows = orc.homconv_select(ct, w, r, sel, P)
     for k, (b, o, f) in enumerate(sel):
-        assert np.array_equal(rows[k], out[b, o, f])
+        assert np.array_equal(rows[k], out[b, f, :, o])
 
 
 def check_homconv_special(orc):
     g = _rng(13)
-    ct = g.integers(0, 2**64, size=(1, 1, 4, 9), dtype=np.uint64)
+    ct = g.integers(0, 2**64, size=(1, 4, 9, 1), dtype=np.uint64)
     one = np.ones((1, 1, 4), dtype=np.uint32)
     zero_r = np.zeros((1, 1, 4), dtype=np.uint32)
     assert np.array_equal(orc.homconv(ct, one, zero_r, P), ct)
     r = g.integers(0, P, size=(1, 2, 4)).astype(np.uint32)
     out = orc.homconv(ct, np.zeros((2, 1, 4), dtype=np.uint32), r, P)
-    assert np.all(out[..., :8] == 0)
-    assert np.array_equal(out[..., 8], (np.uint64(bf.brute_delta(P)) * r.astype(np.uint64)))
+    assert np.all(out[:, :, :8, :] == 0)
+    assert np.array_equal(out[0, :, 8, :], (np.uint64(bf.brute_delta(P)) * r[0].T.astype(np.uint64)))
 
 
 def _small_layer(seed, H=8, W=8, Cin=3, Cout=2, k=3, n=32, B=1, hidden=False):
@@ -311,7 +329,7 @@ def check_noise_identity(orc):
                 Mi = sum(wh[o, i, f] * xh[b, i, f] for i in range(S.Cin)) + int(inp.r[b, o, f])
                 mo = Mi % P
                 E = sum(wh[o, i, f] * e[b, i, f] for i in range(S.Cin)) - Mi // P
-                phi = orc.phase(out["ct_out"][b, o, f], inp.s)
+                phi = orc.phase(out["ct_out"][b, f, :, o], inp.s)
                 assert (phi - D * mo - E) % M64 == 0
                 assert int(out["m"][b, o, f]) == mo
                 assert abs(E * P - mo) < 2**63

@@ -52,9 +52,10 @@ def test_status_strings_and_host_only_calls(lib):
         s = lib.ensei_status_str(code)
         assert isinstance(s, bytes) and len(s) > 0
     assert lib.ensei_status_str(12345) == b"unknown status"
-    # packed-weight size is pure host arithmetic: F * ceil(Cin/16) * roundup(Cout,16) * 48
+    # packed-weight size is pure host arithmetic: F * ceil(Cin/64)*4 * roundup(Cout,16) * 48
     assert lib.ensei_wpack_bytes(64, 64, 1024) == 1024 * 4 * 64 * 48
-    assert lib.ensei_wpack_bytes(8, 3, 256) == 256 * 1 * 16 * 48
+    assert lib.ensei_wpack_bytes(8, 3, 256) == 256 * 4 * 16 * 48
+    assert lib.ensei_wpack_bytes(40, 130, 16) == 16 * 12 * 48 * 48
     assert lib.ensei_wpack_bytes(0, 3, 256) == 0
     # context accessors tolerate NULL
     assert lib.ensei_ctx_modulus(None) == 0 and lib.ensei_ctx_delta(None) == 0
@@ -65,8 +66,8 @@ def test_entry_points_reject_null_context(lib):
     # argument checks run on the host before any HIP call touches a device
     assert lib.ensei_ntt2d(None, None, None, 1, 16, 16, None) < 0
     assert lib.ensei_homconv(None, None, None, None, 1, 1, 1, 1, 1, None, None) < 0
-    assert lib.ensei_encrypt(None, None, None, None, 1, 1, 0, 0, None, None) < 0
-    assert lib.ensei_decrypt(None, None, None, 1, 1, None, None) < 0
+    assert lib.ensei_encrypt(None, None, None, None, 1, 1, 1, 1, 0, 0, None, None) < 0
+    assert lib.ensei_decrypt(None, None, None, 1, 1, 1, 1, None, None) < 0
     h = ctypes.c_void_p()
     assert lib.ensei_ctx_create(None, 65537, 0) == -1  # ENSEI_ERR_ARG
 

@@ -12,7 +12,7 @@ import torch
 import oracle
 from paper_2003_05328_amd import configs, synth
 from paper_2003_05328_amd.ensei import Context, EnseiError
-from tests.gpu_helpers import P, dev, host, oracle_ct_in_rows, oracle_ct_out_row, rows_u64
+from tests.gpu_helpers import P, ct_words, dev, host, oracle_ct_in_rows, oracle_ct_out_row
 
 pytestmark = pytest.mark.gpu
 
@@ -100,6 +100,22 @@ def test_encrypt_decrypt(ctx, orc, n, num_ct, c0):
     assert np.array_equal(host(ctx.decrypt(dev(junk), dev(s))), orc.decrypt(junk, s, P))
 
 
+@pytest.mark.parametrize("B,C,F,n", [(2, 3, 50, 64), (1, 64, 17, 100), (2, 70, 5, 33), (1, 130, 3, 1024),
+                                     (1, 1, 700, 16), (3, 21, 7, 1)])
+def test_encrypt_decrypt_word_major(ctx, orc, B, C, F, n):
+    """Channel groups of one frequency, several frequencies per group (C < 64),
+    partial channel blocks (C > 64) and ragged word ranges."""
+    m = synth.uniform_u32(B * C, (B, C, F), P)
+    s = synth.ternary(C + 1, n)
+    e = synth.rounded_gaussian(C + 2, (B, C, F))
+    ct = ctx.encrypt(dev(m), dev(s), dev(e), 77, ct_index0=5)
+    ref = orc.encrypt(m, s, e, 77, P, ct_index0=5)
+    assert np.array_equal(host(ct), ref)
+    assert np.array_equal(host(ctx.decrypt(ct, dev(s))), m)
+    junk = synth.uniform_u64(C + 3, (B, F, n + 1, C))
+    assert np.array_equal(host(ctx.decrypt(dev(junk), dev(s))), orc.decrypt(junk, s, P))
+
+
 # ---------------------------------------------------------------- HomConv ---
 
 HOMCONV_CASES = [
@@ -121,7 +137,7 @@ HOMCONV_CASES = [
 
 
 def _homconv_inputs(B, Cin, Cout, F, n, seed):
-    ct = synth.uniform_u64(seed, (B, Cin, F, n + 1))
+    ct = synth.uniform_u64(seed, (B, F, n + 1, Cin))
     w = synth.uniform_u32(seed + 1, (Cout, Cin, F), P)
     w.flat[0] = P - 1
     w.flat[-1] = 0
@@ -150,8 +166,8 @@ def test_homconv_valu(ctx, orc, B, Cin, Cout, F, n):
 def test_homconv_extreme_words(ctx, orc):
     """All-ones words and W^ = p-1 maximise every limb sum."""
     B, Cin, Cout, F, n = 1, 70, 20, 2, 66
-    ct = np.full((B, Cin, F, n + 1), 2**64 - 1, dtype=np.uint64)
-    ct[..., ::3] = 2**63
+    ct = np.full((B, F, n + 1, Cin), 2**64 - 1, dtype=np.uint64)
+    ct[:, :, ::3, :] = 2**63
     w = np.full((Cout, Cin, F), P - 1, dtype=np.uint32)
     r = np.full((B, Cout, F), P - 1, dtype=np.uint32)
     ref = orc.homconv(ct, w, r, P)
@@ -166,7 +182,7 @@ def test_errors_are_reported(ctx):
     x = torch.zeros((2, 12, 16), dtype=torch.uint32, device="cuda:0")
     with pytest.raises(EnseiError, match="SHAPE"):
         ctx.ntt2d(x)
-    big = torch.zeros((1, 4, 1, 9), dtype=torch.uint64, device="cuda:0")
+    big = torch.zeros((1, 1, 9, 4), dtype=torch.uint64, device="cuda:0")
     w1 = torch.zeros((4, 4, 1), dtype=torch.uint32, device="cuda:0")
     r1 = torch.zeros((1, 4, 1), dtype=torch.uint32, device="cuda:0")
     with pytest.raises(EnseiError, match="OVERLAP"):
@@ -189,7 +205,7 @@ def _gpu_round0(ctx, inp):
     x_hat = ctx.ntt2d(x)  # [B][Cin][F]
     w_hat = ctx.weight_prep(w, S.H, S.W)
     pack = ctx.pack_weights(w_hat)
-    ct_in = ctx.encrypt(x_hat, s, dev(inp.e), inp.seed_a)
+    ct_in = ctx.encrypt(x_hat, s, dev(inp.e), inp.seed_a)  # [B][F][n+1][Cin]
     r = dev(inp.r)
     ct_out = ctx.homconv(ct_in, pack, r, S.Cout)
     m = ctx.decrypt(ct_out, s)
@@ -232,11 +248,11 @@ def test_full_size_layer(ctx, orc, name):
     for _ in range(6):
         b, f = int(g.integers(S.B)), int(g.integers(S.F))
         cin = oracle_ct_in_rows(orc, x_hat, inp, b, f)
-        flat_in = [(b * S.Cin + i) * S.F + f for i in range(S.Cin)]
-        assert np.array_equal(rows_u64(got["ct_in"], flat_in), cin)
+        for i in range(S.Cin):
+            assert np.array_equal(ct_words(got["ct_in"], b, f, i), cin[i])
         for o in {0, S.Cout - 1, int(g.integers(S.Cout))}:
             ref_row = oracle_ct_out_row(orc, cin, w_hat, inp, b, o, f)
-            assert np.array_equal(rows_u64(got["ct_out"], [(b * S.Cout + o) * S.F + f]), ref_row[None])
+            assert np.array_equal(ct_words(got["ct_out"], b, f, o), ref_row)
             assert int(host(got["m"])[b, o, f]) == int(orc.decrypt(ref_row[None], inp.s, P)[0])
     # exact decryption everywhere: m = (sum_i W^ x^ + r) mod p
     # (products < 2^34, sums over Cin <= 512 stay below 2^43: exact in int64)

@@ -29,19 +29,21 @@ MUTANTS = {
     "conv_weight_not_reduced": ("if (wv < 0) wv += (int64_t)p;\n                                int r1", "int r1"),
     "filter_transposed_in_grid": ("w_hat[t * F + a * W + b] = (uint32_t)v;", "w_hat[t * F + b * W + a] = (uint32_t)v;"),
     "splitmix_wrong_shift": ("z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;", "z = (z ^ (z >> 29)) * 0x94d049bb133111ebULL;"),
-    "enc_counter_off_by_one": ("gidx * (uint64_t)n + (uint64_t)j + 1)", "gidx * (uint64_t)n + (uint64_t)j)"),
-    "enc_dropped_error": ("row[n] = dot + (uint64_t)(int64_t)e[c] + delta * (uint64_t)m[c];", "row[n] = dot + delta * (uint64_t)m[c];"),
+    "enc_counter_off_by_one": ("(ct_index0 + q) * (uint64_t)n + (uint64_t)j + 1)", "(ct_index0 + q) * (uint64_t)n + (uint64_t)j)"),
+    "enc_counter_channel_major": ("uint64_t q = (uint64_t)((b * F + f) * C + c)", "uint64_t q = (uint64_t)((b * C + c) * F + f)"),
+    "enc_dropped_error": ("dot + (uint64_t)(int64_t)e[mi] + delta * (uint64_t)m[mi];", "dot + delta * (uint64_t)m[mi];"),
     "enc_wrong_key_sign": (
-        "            if (s[j] == 1) dot += a;\n            else if (s[j] == -1) dot -= a;",
-        "            if (s[j] == 1) dot += a;\n            else if (s[j] == -1) dot += a;",
+        "                    if (s[j] == 1) dot += a;\n                    else if (s[j] == -1) dot -= a;",
+        "                    if (s[j] == 1) dot += a;\n                    else if (s[j] == -1) dot += a;",
     ),
     "delta_rounded_up": ("return (uint64_t)((((u128)1) << 64) / p);", "return (uint64_t)((((u128)1) << 64) / p + 1);"),
     "dec_truncates_not_rounds": ("u128 t = (u128)phi * p + (((u128)1) << 63);", "u128 t = (u128)phi * p;"),
-    "dec_missing_final_mod": ("m[c] = (uint32_t)(v % p);", "m[c] = (uint32_t)v;"),
-    "dec_phase_sign": ("return row[n] - dot;", "return row[n] + dot;"),
-    "homconv_mask_on_word0": ("out_row[n] += or_delta(p)", "out_row[0] += or_delta(p)"),
+    "dec_missing_final_mod": ("m[(b * C + c) * F + f] = (uint32_t)(v % p);", "m[(b * C + c) * F + f] = (uint32_t)v;"),
+    "dec_phase_sign": ("return w[(int64_t)n * stride] - dot;", "return w[(int64_t)n * stride] + dot;"),
+    "homconv_mask_on_word0": ("out[n * ostride] += or_delta(p)", "out[0] += or_delta(p)"),
     "homconv_weight_transposed": ("w_hat[(o * Cin + i) * F + f]", "w_hat[(i * Cout + o) * F + f]"),
-    "homconv_mask_missing_delta": ("out_row[n] += or_delta(p) * (uint64_t)r", "out_row[n] += (uint64_t)r"),
+    "homconv_mask_missing_delta": ("out[n * ostride] += or_delta(p) * (uint64_t)r", "out[n * ostride] += (uint64_t)r"),
+    "homconv_wrong_word_stride": ("blk[(int64_t)j * Cin + i]", "blk[(int64_t)i * (n + 1) + j]"),
     "server_share_not_negated": ("s_b[k] = (uint32_t)((p - r[k] % p) % p);", "s_b[k] = (uint32_t)(r[k] % p);"),
 }
 
