@@ -120,16 +120,18 @@ int ensei_weight_prep(ensei_ctx *ctx, const int32_t *w, int Cout, int Cin, int k
                       uint32_t *w_hat, void *stream);
 
 /* Bytes of the packed-weight buffer ensei_pack_weights writes:
- * F * (ceil(Cin/64) * 4) * roundup(Cout,16) * 48. Returns 0 for invalid sizes. */
+ * F * ceil(Cin/64) * ceil(Cout/64) * U * 16 with U = 768 when Cin >= 48,
+ * else U = 256 * ceil(Cin/16). Returns 0 for invalid sizes. */
 size_t ensei_wpack_bytes(int Cout, int Cin, int64_t F);
 
 /* Packs transformed weights for ensei_homconv: every W^[o][i][f] (the
  * integer in [0, p), p < 2^22) is written as three signed bytes
  * d0 + 2^8 d1 + 2^16 d2 with d0, d1, d2 in [-128, 127] (balanced base-256
- * digits), grouped per frequency as
- *   w_pack[f][i/16][o][d][i%16]   (int8; rows zero-padded to a multiple of 16,
- *                                  channel groups of 16 to a multiple of 4),
- * the operand layout of the i8 matrix-core contraction in ensei_homconv.
+ * digits), arranged as the matrix-core operand fragments ensei_homconv
+ * loads: for every frequency f, 64-channel step and 64-row output tile, U
+ * 16-byte items (one digit of 16 channels for one output row each; rows and
+ * channels past Cout and Cin are zero). The arrangement is private to
+ * ensei_homconv; only the size above is part of the interface.
  * w_hat: uint32 [Cout][Cin][F]; w_pack: ensei_wpack_bytes(Cout, Cin, F)
  * bytes, 16-byte aligned. */
 int ensei_pack_weights(ensei_ctx *ctx, const uint32_t *w_hat, int Cout, int Cin, int64_t F, int8_t *w_pack,
@@ -171,8 +173,9 @@ int ensei_encrypt(ensei_ctx *ctx, const uint32_t *m, const int8_t *s, const int3
  * ct_in: uint64 [batch][F][n+1][Cin] (word-major); w_pack: from
  * ensei_pack_weights for (Cout, Cin, F); r: uint32 [batch][Cout][F] (< p);
  * ct_out: uint64 [batch][F][n+1][Cout] (word-major). 1 <= Cin <= ENSEI_MAX_CIN,
- * 1 <= Cout <= ENSEI_MAX_COUT, 1 <= n <= ENSEI_MAX_LWE_N, and one (b, f) block
- * of either side below 2^31 bytes ((n+1) * max(Cin, Cout) * 8). Runs on the
+ * 1 <= Cout <= ENSEI_MAX_COUT, 1 <= n <= ENSEI_MAX_LWE_N, one (b, f) block
+ * of either side below 2^31 bytes ((n+1) * max(Cin, Cout) * 8) and one
+ * image's masks below 2^31 bytes (Cout * F * 4), else ENSEI_ERR_LIMIT. Runs on the
  * i8 matrix cores (signed-byte limbs of both operands, exact i32 sums,
  * recombined mod 2^64). */
 int ensei_homconv(ensei_ctx *ctx, const uint64_t *ct_in, const int8_t *w_pack, const uint32_t *r, int64_t batch,

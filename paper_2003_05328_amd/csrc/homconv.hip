@@ -1,38 +1,4 @@
 // HomConv: for every (image b, frequency f) an exact integer contraction
-//   ct_out[b][:, f, :] = W^_f (Cout x Cin) . ct_in[b][:, f, :] (Cin x (n+1))  mod 2^64
-// plus Delta * r[b][o][f] on the b word (HomShare).
-//
-// Matrix-core kernel (ensei_homconv). Both operands are split into signed
-// bytes so the i8 MFMA (v_mfma_i32_16x16x64_i8) does the multiplies:
-//   - a ciphertext word c is written in balanced base 256,
-//     c = sum_{k<8} d_k 256^k mod 2^64 with d_k in [-128, 127]; the digits are
-//     the bytes of c + 0x8080...80, each xor 0x80 (the carry out of the top
-//     digit vanishes mod 2^64);
-//   - W^ < 2^22 as w0 + 256 w1 + 65536 w2, the same balanced digits
-//     (ensei_pack_weights).
-//   Then sum_i W^ c = sum_{s<8} 256^s acc_s mod 2^64 with
-//   acc_s = sum_i sum_{l<=2, l<=s} w_l[i] d_{s-l}[i], an exact i32 sum
-//   (|acc_s| <= 3 * Cin * 2^14 < 2^31 for Cin <= 32768). Products with
-//   l + k >= 8 are multiples of 2^64 and are never formed.
-//   One MFMA's 64-long K dimension holds 16 channels x 4 limb slots
-//   (slot l < 3 pairs limb w_l with ciphertext digit plane s - l; slot 3 is
-//   zero), so one instruction per shift s covers all three limbs of 16
-//   channels.
-//
-// Work decomposition: one workgroup (4 waves) per output tile of
-// (b, f, 16*RB rows o, 64 columns j); the b column j = n is simply the last
-// column and gets Delta*r in the epilogue. Per 64 input channels the waves
-// stream the 64 x 64 ciphertext words from HBM (each wave one 16-channel
-// group, lanes along j so every load moves 512 contiguous bytes), convert
-// them to digit planes with byte permutes, and store the planes in LDS as
-// [plane][channel group][column][16 channel bytes], which makes both the
-// 16-byte LDS writes and the MFMA B-operand reads conflict free. Each wave
-// then owns 16 columns x 16*RB rows and keeps the eight shift accumulators
-// in registers; the epilogue recombines them into u64 words and writes
-// ct_out with 128-byte row segments. Tiles are assigned XCD by XCD so tiles
-// that share (b, f) (hence W^_f and, for several row tiles, ct_in) run on
-// the same L2.
-// HomConv: for every (image b, frequency f) an exact integer contraction
 //   ct_out(b, :, f) = W^_f (Cout x Cin) . ct_in(b, :, f) (Cin x (n+1))  mod 2^64
 // plus Delta * r[b][o][f] on the b word (HomShare). Ciphertexts are stored
 // word-major, ct[b][f][j][c]: for one (b, f) the block is a (n+1) x C matrix
@@ -50,10 +16,8 @@
 //   acc_s = sum_i sum_{l<=2, l<=s} w_l[i] d_{s-l}[i], an exact i32 sum
 //   (|acc_s| <= 3 * Cin * 2^14 < 2^31 for Cin <= 32768). Products with
 //   l + k >= 8 are multiples of 2^64 and are never formed.
-//   One MFMA's 64-long K dimension holds 16 channels x 4 limb slots
-//   (slot l < 3 pairs limb w_l with ciphertext digit plane s - l; slot 3 is
-//   zero), so one instruction per shift s covers all three limbs of 16
-//   channels.
+//   The kernel's two K layouts (limbs folded into K, or one limb pair per
+//   instruction) are described at the kernel.
 //
 // Work decomposition: a tile is (b, f, 64 rows o, 64 columns j) and a unit a
 // (tile, 64-channel K step). With C = 64 channels both the unit's input words
@@ -63,8 +27,12 @@
 // (b, f, columns) reuse its input from L2), two units ahead: the next two
 // units' words, weight fragments and masks are in flight while the current
 // unit is converted to digit planes and contracted on the MFMAs. Each wave
-// owns 16 columns x 32 rows and the eight shift accumulators in registers;
-// finished tiles go through LDS and out as contiguous 512-byte column runs.
+// owns 16 columns x 32 rows and the eight shift accumulators in registers.
+// The rows of the MFMA's A operand are permuted so that every lane ends up
+// with 8 consecutive output rows of one column: after the recombination each
+// lane writes one 64-byte run of ct_out straight from its registers.
+#include <type_traits>
+
 #include "ensei_internal.hpp"
 
 namespace ensei {
@@ -143,6 +111,31 @@ struct HcBuf {
 };
 
 constexpr int kHcThreads = 512;
+constexpr int kPairedCin = 48;  // the paired limb scheme from this many input channels on
+
+// 16-byte weight-fragment items per (f, K step, row tile) unit
+__host__ __device__ inline int frag_items(int Cin) { return Cin >= kPairedCin ? 768 : 256 * ((Cin + 15) / 16); }
+
+// Shift accumulators -> one u64 word, mod 2^64:
+//   sum_{s<4} 256^s acc_s exactly (signed), plus 2^32 (sum_{s>=4} 256^(s-4) acc_s mod 2^32).
+// SMALL: Cin <= kSmallCin, so acc_0 + 256 acc_1 and acc_2 + 256 acc_3 are exact i32
+// values (|acc_s| <= 3 Cin 2^14) and the low part needs one 64-bit add.
+constexpr int kSmallCin = 169;
+
+template <bool SMALL>
+__device__ __forceinline__ uint64_t recombine(int a0, int a1, int a2, int a3, int a4, int a5, int a6, int a7) {
+    uint64_t lo;
+    if (SMALL) {
+        const int32_t u = (int32_t)((uint32_t)a0 + ((uint32_t)a1 << 8));
+        const int32_t v = (int32_t)((uint32_t)a2 + ((uint32_t)a3 << 8));
+        lo = (uint64_t)(int64_t)u + ((uint64_t)(int64_t)v << 16);
+    } else {
+        lo = (uint64_t)(int64_t)a0 + ((uint64_t)(int64_t)a1 << 8) + ((uint64_t)(int64_t)a2 << 16) +
+             ((uint64_t)(int64_t)a3 << 24);
+    }
+    const uint32_t h = (uint32_t)a4 + ((uint32_t)a5 << 8) + ((uint32_t)a6 << 16) + ((uint32_t)a7 << 24);
+    return lo + ((uint64_t)h << 32);
+}
 
 // PAIRED = false ("folded" limbs): one MFMA's 64-long K holds 16 channels x
 // 4 limb slots (slot l < 3 pairs weight limb l with digit plane s - l, slot 3
@@ -151,24 +144,26 @@ constexpr int kHcThreads = 512;
 // PAIRED = true: K holds 64 channels of one weight limb l and one digit
 // plane k, one instruction per pair (l, k) with l + k < 8 accumulating into
 // shift l + k: 21 MFMAs per 64 channels and row block and a quarter of the
-// LDS operand reads. Used when Cin >= 64.
-template <bool PAIRED>
+// LDS operand reads. Used when Cin >= 48.
+// WIDE_STORE: Cout is even, so the two words of every 16-byte store are
+// both inside the output row or both outside it.
+template <bool PAIRED, bool WIDE_STORE>
 __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
     const uint64_t *__restrict__ ct_in, const int8_t *__restrict__ w_pack, const uint32_t *__restrict__ r, int Cin,
-    int Cout, int64_t F, int n, uint64_t delta, uint64_t *__restrict__ ct_out, int n_ot, int n_jt, int SC4, int Cout16,
-    int64_t n_tiles, int n_ks) {
+    int Cout, int64_t F, int n, uint64_t delta, uint64_t *__restrict__ ct_out, int n_ot, int n_jt, int n_ks,
+    int n_items, int64_t n_tiles) {
     constexpr int kAItems = PAIRED ? 3 * 4 * 64 : 4 * 4 * 64;  // [limb 3 | sc 4][row block 4][lane 64] x 16 B
     constexpr int kA = kAItems * 16;
     constexpr int kZeroPlanes = PAIRED ? 0 : 2;  // the folded scheme reads planes -2, -1 as zero
-    constexpr int kOutStride = 65;               // u64 per staged output column (64 rows + pad)
-    // digit planes k = -kZeroPlanes..7, then the unit's weight fragments, its
-    // 64 masks, and the finished tile [col][row]
-    __shared__ __attribute__((aligned(16)))
-    uint8_t lds[(8 + kZeroPlanes) * kPlaneBytes + kA + 64 * 4 + 64 * kOutStride * 8];
-    uint8_t *planes = lds + kZeroPlanes * kPlaneBytes;  // plane k at planes + k * kPlaneBytes
-    uint8_t *lds_a = lds + (8 + kZeroPlanes) * kPlaneBytes;
-    uint32_t *lds_r = reinterpret_cast<uint32_t *>(lds_a + kA);
-    uint64_t *lds_out = reinterpret_cast<uint64_t *>(lds_a + kA + 64 * 4);
+    // Two LDS buffers, for units of even and odd index, each holding digit
+    // planes k = -kZeroPlanes..7, the unit's weight fragments and its 64 masks.
+    // A unit's operands are written while other waves may still be reading
+    // the previous unit's, so one barrier per unit is enough.
+    constexpr int kLdsBuf = (8 + kZeroPlanes) * kPlaneBytes + kA + 64 * 4;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[2 * kLdsBuf];
+    auto planes = [&](int lb) { return lds + lb * kLdsBuf + kZeroPlanes * kPlaneBytes; };  // plane k at + k * kPlaneBytes
+    auto lds_a = [&](int lb) { return lds + lb * kLdsBuf + (8 + kZeroPlanes) * kPlaneBytes; };
+    auto lds_r = [&](int lb) { return reinterpret_cast<uint32_t *>(lds + lb * kLdsBuf + (8 + kZeroPlanes) * kPlaneBytes + kA); };
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -177,6 +172,7 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
     const int64_t rowlen = (int64_t)n + 1;
     const uint32_t in_block = (uint32_t)(rowlen * Cin * 8);  // bytes of one (b, f) input block
     const uint32_t out_col_bytes = (uint32_t)(Cout * 8);      // one output word index j
+    const bool small = Cin <= kSmallCin;
 
     // this block's contiguous tile range
     const int64_t per = n_tiles / gridDim.x, extra = n_tiles % gridDim.x;
@@ -185,33 +181,18 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
     if (ntile == 0) return;
     const int64_t n_units = ntile * n_ks;
 
-    for (int i = tid; i < kZeroPlanes * kPlaneBytes / 16; i += kHcThreads)
-        reinterpret_cast<uint4 *>(lds)[i] = make_uint4(0, 0, 0, 0);
+    for (int i = tid; i < 2 * kZeroPlanes * kPlaneBytes / 16; i += kHcThreads) {
+        const int lb = i / (kZeroPlanes * kPlaneBytes / 16), k = i % (kZeroPlanes * kPlaneBytes / 16);
+        reinterpret_cast<uint4 *>(lds + lb * kLdsBuf)[k] = make_uint4(0, 0, 0, 0);
+    }
 
     // load role: column ld_col, channel group ld_sc, half ld_h (8 channels)
     const int ld_col = tid >> 3, ld_sc = (tid >> 1) & 3, ld_h = tid & 1;
-    // weight-fragment items k = tid + 512 j; their first index (sc or limb) and
-    // row block are wave-uniform, the rest is a fixed per-lane offset
-    uint32_t a_lane_off[2];
-    int a_hi[2], a_rb[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const int k = tid + kHcThreads * j;
-        const int ln = k & 63;
-        a_hi[j] = __builtin_amdgcn_readfirstlane(k >> 8);
-        a_rb[j] = __builtin_amdgcn_readfirstlane((k >> 6) & 3);
-        if (PAIRED) {
-            // lane (row ln & 15, channel group g): 16 channels of limb a_hi
-            a_lane_off[j] = (uint32_t)((ln >> 4) * Cout16 * 48 + (ln & 15) * 48);
-        } else {
-            const int slot = (ln >> 4) < 3 ? (ln >> 4) : 2;  // slot 3 meets the zero B plane
-            a_lane_off[j] = (uint32_t)((ln & 15) * 48 + slot * 16);
-        }
-    }
     const int b_col = cg * 16 + l16;  // this lane's B column
     // folded: plane s - g (slot 3: the zero plane); paired: plane k, channel group g
     const int b_base = PAIRED ? plane_slot(b_col, g) * 16 : (g == 3 ? -1 : -g) * kPlaneBytes;
     const int b_step = PAIRED ? kPlaneBytes : (g == 3 ? 0 : kPlaneBytes);
+    const int out_row = 32 * rg + 8 * g;  // first of this lane's 8 output rows in the tile
 
     auto issue = [&](const HcCoord &u, HcBuf &buf) {
         const int col = u.jt * 64 + ld_col;
@@ -222,48 +203,25 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
         const uint32_t off = (uint32_t)(((int64_t)col * Cin + u.ks * 64 + ld_sc * 16 + ld_h * 8) * 8);
 #pragma unroll
         for (int q = 0; q < 4; ++q) buf.w[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16 * q), 0, 0);
+        // the unit's weight fragments: n_items contiguous 16-byte items, item k
+        // read by thread k % 512 (items past n_items read zero, with no traffic)
+        const int64_t unit = ((int64_t)u.f * n_ks + u.ks) * n_ot + u.ot;
+        const __amdgpu_buffer_rsrc_t ra =
+            make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(w_pack) + unit * n_items * 16), (uint32_t)(n_items * 16));
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            // a row block past Cout16 re-reads the last real one (never stored)
-            int row = u.ot * 64 + a_rb[j] * 16;
-            row = row < Cout16 ? row : Cout16 - 16;
-            int64_t base;
-            if (PAIRED) {
-                const int limb = a_hi[j] < 3 ? a_hi[j] : 2;  // item 768.. are spares
-                base = (((int64_t)u.f * SC4 + u.ks * 4) * Cout16 + row) * 48 + limb * 16;
-            } else {
-                const int scg = u.ks * 4 + a_hi[j];
-                base = (((int64_t)u.f * SC4 + scg) * Cout16 + row) * 48;
-            }
-            const uint8_t *wa = uniform_ptr(reinterpret_cast<const uint8_t *>(w_pack) + base);
-            buf.a[j] = load_global<v4i>(wa, a_lane_off[j]);
+            const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(ra, (tid + kHcThreads * j) * 16, 0, 0);
+            buf.a[j] = v4i{(int)v.x, (int)v.y, (int)v.z, (int)v.w};
         }
-        int o = u.ot * 64 + (tid & 63);
-        o = o < Cout ? o : Cout - 1;
-        buf.r = r[(u.b * Cout + o) * F + u.f];
-    };
-
-    v4i acc[8][2];
-    uint64_t res[2][4] = {};
-    bool have_out = false;  // res holds a finished tile not yet stored
-    const uint64_t *out_blk = ct_out;
-    int out_o0 = 0;
-    uint32_t out_nbytes = 0;
-
-    // 8 stores per wave (columns wave + 8k, lane = row), bounded: rows past Cout,
-    // columns past n and iterations without a finished tile are dropped
-    auto store_tile = [&](bool valid) {
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(out_blk)),
-                                                    __builtin_amdgcn_readfirstlane(valid ? out_nbytes : 0u));
-        const bool row_ok = out_o0 + lane < Cout;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int col = wave + 8 * k;
-            const uint64_t v = lds_out[col * kOutStride + lane];
-            const uint32_t off = row_ok ? (uint32_t)(col * out_col_bytes + (out_o0 + lane) * 8) : 0x80000000u;
-            const u32x2 d = {(unsigned)v, (unsigned)(v >> 32)};
-            __builtin_amdgcn_raw_buffer_store_b64(d, rs, (int)off, 0, 0);
-        }
+        // masks are needed only in the column tile holding the b word (j = n),
+        // and only by the first wave: every other load is out of range and
+        // generates no memory traffic
+        const int o = u.ot * 64 + tid;
+        const __amdgpu_buffer_rsrc_t rr =
+            make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(r + u.b * Cout * F + u.f)),
+                      u.jt == n_jt - 1 ? (uint32_t)(((int64_t)(Cout - 1) * F + 1) * 4) : 0u);
+        buf.r = __builtin_amdgcn_raw_buffer_load_b32(rr, (int)(tid < 64 && o < Cout ? (uint32_t)(o * F * 4) : 0x80000000u),
+                                                     0, 0);
     };
 
     HcCoord cur, nx;
@@ -277,20 +235,127 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
         cur.f = t % F;
         cur.b = t / F;
     }
-    // two units in flight from the start; the entry issues the same store/load
-    // sequence as every iteration (stores fully out of bounds) so the waits at
-    // the loop head see one static count on both incoming paths
+    // 16-channel groups holding channels in the last K step (folded scheme)
+    const int sc_last = (Cin - 64 * (n_ks - 1) + 15) / 16;
+    v4i acc[8][2];
+
+    // MFMA phase of one unit; FRESH: the first product into each shift
+    // accumulator starts from zero (the unit is the tile's first K step)
+    auto contract = [&](auto fresh_tag, int lb) {
+        constexpr bool FRESH = decltype(fresh_tag)::value;
+        const v4i zero = {0, 0, 0, 0};
+        if (PAIRED) {
+            v4i A[3][2];
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb)
+                    A[l][rb] = reinterpret_cast<const v4i *>(lds_a(lb))[(l * 4 + rg * 2 + rb) * 64 + lane];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const v4i B = *reinterpret_cast<const v4i *>(planes(lb) + b_base + k * b_step);
+#pragma unroll
+                for (int l = 0; l < 3; ++l) {
+                    if (k + l >= 8) break;
+                    // in this order shift k + l is first reached at k = 0 or l = 2
+                    const bool first = FRESH && (k == 0 || l == 2);
+#pragma unroll
+                    for (int rb = 0; rb < 2; ++rb)
+                        acc[k + l][rb] =
+                            __builtin_amdgcn_mfma_i32_16x16x64_i8(A[l][rb], B, first ? zero : acc[k + l][rb], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int sc = 0; sc < 4; ++sc) {
+                if (sc >= (cur.ks == n_ks - 1 ? sc_last : 4)) break;  // groups past Cin are zero
+                v4i A[2];
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb)
+                    A[rb] = reinterpret_cast<const v4i *>(lds_a(lb))[(sc * 4 + rg * 2 + rb) * 64 + lane];
+                const uint8_t *bp = planes(lb) + b_base + plane_slot(b_col, sc) * 16;
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const v4i B = *reinterpret_cast<const v4i *>(bp + s * b_step);
+                    const bool first = FRESH && sc == 0;
+#pragma unroll
+                    for (int rb = 0; rb < 2; ++rb)
+                        acc[s][rb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[rb], B, first ? zero : acc[s][rb], 0, 0, 0);
+                }
+            }
+        }
+    };
+
+    // 8 output words of this lane: tile rows out_row + 4 rb + i of column b_col
+    auto store_out = [&](const uint64_t (&res)[2][4], bool valid) {
+        const uint64_t *blk = ct_out + ((cur.b * F + cur.f) * rowlen + cur.jt * 64) * Cout;
+        // columns past n fall outside the block and are dropped
+        const uint32_t nbytes = valid ? (uint32_t)((rowlen - cur.jt * 64) * Cout * 8) : 0u;
+        const __amdgpu_buffer_rsrc_t rs =
+            make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(blk)), __builtin_amdgcn_readfirstlane(nbytes));
+        if (WIDE_STORE) {
+            // 16-byte chunk c of lane row g (lanes 16 g + l16) is X[c]; a 4 x 4
+            // transpose across the lane rows (swap halves, then odd/even rows)
+            // leaves X[q] = chunk g of lane row q, so store q of the four lane
+            // rows of one column covers 64 contiguous bytes
+            uint32_t X[4][4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const uint64_t w0 = res[c >> 1][2 * (c & 1)], w1 = res[c >> 1][2 * (c & 1) + 1];
+                X[c][0] = (uint32_t)w0;
+                X[c][1] = (uint32_t)(w0 >> 32);
+                X[c][2] = (uint32_t)w1;
+                X[c][3] = (uint32_t)(w1 >> 32);
+            }
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const auto t = __builtin_amdgcn_permlane32_swap(X[c][d], X[c + 2][d], false, false);
+                    X[c][d] = t[0];
+                    X[c + 2][d] = t[1];
+                }
+#pragma unroll
+                for (int c = 0; c < 4; c += 2) {
+                    const auto t = __builtin_amdgcn_permlane16_swap(X[c][d], X[c + 1][d], false, false);
+                    X[c][d] = t[0];
+                    X[c + 1][d] = t[1];
+                }
+            }
+            const int o = cur.ot * 64 + 32 * rg + 2 * g;  // + 8 q: rows of store q
+            const uint32_t off = (uint32_t)(b_col * out_col_bytes + o * 8);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const u32x4 d = {X[q][0], X[q][1], X[q][2], X[q][3]};
+                __builtin_amdgcn_raw_buffer_store_b128(d, rs, (int)(o + 8 * q < Cout ? off + 64 * q : 0x80000000u), 0,
+                                                       0);
+            }
+        } else {
+            const int o = cur.ot * 64 + out_row;
+            const uint32_t off = (uint32_t)(b_col * out_col_bytes + o * 8);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint64_t w = res[q >> 2][q & 3];
+                const u32x2 d = {(unsigned)w, (unsigned)(w >> 32)};
+                __builtin_amdgcn_raw_buffer_store_b64(d, rs, (int)(o + q < Cout ? off + 8 * q : 0x80000000u), 0, 0);
+            }
+        }
+    };
+
+    // two units in flight from the start; the entry issues the same load and
+    // store sequence as every iteration (stores fully out of bounds) so the
+    // waits at the loop head see one static count on both incoming paths
     HcBuf buf0, buf1;
+    const uint64_t none[2][4] = {};
     nx = cur;
-    store_tile(false);
     issue(nx, buf0);
+    store_out(none, false);
     if (n_units > 1) nx.advance(n_ot, n_jt, n_ks, F);
-    store_tile(false);
     issue(nx, buf1);
+    store_out(none, false);
     int64_t issued = n_units > 1 ? 2 : 1;
 
-    auto body = [&](HcBuf &buf) {
-        const int o0 = cur.ot * 64, j0 = cur.jt * 64;
+    auto body = [&](HcBuf &buf, int lb) {
         const bool last_ks = cur.ks == n_ks - 1;
 
         // digit planes of this unit's 8 words: 8 bytes of each plane
@@ -314,137 +379,103 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
                            pl[7][d]);
             }
         }
-        __syncthreads();  // previous unit's MFMA reads and staged-tile reads are done
         const int pslot = plane_slot(ld_col, ld_sc) * 16 + ld_h * 8;
 #pragma unroll
         for (int k = 0; k < 8; ++k)
-            *reinterpret_cast<u32x2 *>(planes + k * kPlaneBytes + pslot) =
+            *reinterpret_cast<u32x2 *>(planes(lb) + k * kPlaneBytes + pslot) =
                 u32x2{pl[k][0] ^ 0x80808080u, pl[k][1] ^ 0x80808080u};
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-            if (tid + kHcThreads * j < kAItems) reinterpret_cast<v4i *>(lds_a)[tid + kHcThreads * j] = buf.a[j];
-        if (tid < 64) lds_r[tid] = buf.r;
-        // the finished previous tile: lane holds rows 32 rg + 16 rb + 4 g + i of column 16 cg + l16
-#pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) lds_out[b_col * kOutStride + rg * 32 + rb * 16 + 4 * g + i] = res[rb][i];
+            if (tid + kHcThreads * j < kAItems) reinterpret_cast<v4i *>(lds_a(lb))[tid + kHcThreads * j] = buf.a[j];
+        if (tid < 64) lds_r(lb)[tid] = buf.r;
         __syncthreads();
 
-        // the finished tile goes out, then the unit two ahead reuses this buffer
-        // (past the end: reissue the last one, keeping the load count static);
-        // stores issued before the loads are never waited for with them
-        store_tile(have_out);
-        have_out = false;
+        // the unit two ahead reuses this buffer (past the end: reissue the
+        // last one, keeping the load count static)
         if (issued < n_units) {
             nx.advance(n_ot, n_jt, n_ks, F);
             ++issued;
         }
         issue(nx, buf);
 
-        if (cur.ks == 0) {
-#pragma unroll
-            for (int s = 0; s < 8; ++s)
-#pragma unroll
-                for (int rb = 0; rb < 2; ++rb) acc[s][rb] = v4i{0, 0, 0, 0};
-        }
-        if (PAIRED) {
-            v4i A[3][2];
-#pragma unroll
-            for (int l = 0; l < 3; ++l)
-#pragma unroll
-                for (int rb = 0; rb < 2; ++rb)
-                    A[l][rb] = reinterpret_cast<const v4i *>(lds_a)[(l * 4 + rg * 2 + rb) * 64 + lane];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const v4i B = *reinterpret_cast<const v4i *>(planes + b_base + k * b_step);
-#pragma unroll
-                for (int l = 0; l < 3; ++l) {
-                    if (k + l >= 8) break;
-#pragma unroll
-                    for (int rb = 0; rb < 2; ++rb)
-                        acc[k + l][rb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[l][rb], B, acc[k + l][rb], 0, 0, 0);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int sc = 0; sc < 4; ++sc) {
-                if (cur.ks * 4 + sc >= SC4) break;
-                v4i A[2];
-#pragma unroll
-                for (int rb = 0; rb < 2; ++rb)
-                    A[rb] = reinterpret_cast<const v4i *>(lds_a)[(sc * 4 + rg * 2 + rb) * 64 + lane];
-                const uint8_t *bp = planes + b_base + plane_slot(b_col, sc) * 16;
-#pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    const v4i B = *reinterpret_cast<const v4i *>(bp + s * b_step);
-#pragma unroll
-                    for (int rb = 0; rb < 2; ++rb)
-                        acc[s][rb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[rb], B, acc[s][rb], 0, 0, 0);
-                }
-            }
-        }
+        if (cur.ks == 0)
+            contract(std::true_type{}, lb);
+        else
+            contract(std::false_type{}, lb);
 
-        if (last_ks) {
-            const int jc = j0 + b_col;
+        // epilogue: recombine the shift accumulators (in every unit, so the
+        // store count stays static; only the tile's last K step stores)
+        uint64_t res[2][4];
+        auto recombine_all = [&](auto small_tag) {
+            constexpr bool SMALL = decltype(small_tag)::value;
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int64_t lo64 = (int64_t)acc[0][rb][i] + (int64_t)acc[1][rb][i] * 256 +
-                                         (int64_t)acc[2][rb][i] * 65536 + (int64_t)acc[3][rb][i] * 16777216;
-                    const uint32_t hi32 = (uint32_t)acc[4][rb][i] + ((uint32_t)acc[5][rb][i] << 8) +
-                                          ((uint32_t)acc[6][rb][i] << 16) + ((uint32_t)acc[7][rb][i] << 24);
-                    uint64_t v = (uint64_t)lo64 + ((uint64_t)hi32 << 32);
-                    if (jc == n) v += delta * (uint64_t)lds_r[rg * 32 + rb * 16 + 4 * g + i];
-                    res[rb][i] = v;
-                }
-            have_out = true;
-            out_o0 = o0;
-            out_blk = ct_out + ((cur.b * F + cur.f) * rowlen + j0) * Cout;
-            out_nbytes = (uint32_t)((rowlen - j0) * Cout * 8);
+                for (int i = 0; i < 4; ++i)
+                    res[rb][i] = recombine<SMALL>(acc[0][rb][i], acc[1][rb][i], acc[2][rb][i], acc[3][rb][i],
+                                                  acc[4][rb][i], acc[5][rb][i], acc[6][rb][i], acc[7][rb][i]);
+        };
+        if (small)
+            recombine_all(std::true_type{});
+        else
+            recombine_all(std::false_type{});
+        // HomShare: Delta * r on the b word (column n)
+        if (cur.jt * 64 + 64 > n && cur.jt * 64 + b_col == n) {
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) res[rb][i] += delta * (uint64_t)lds_r(lb)[out_row + 4 * rb + i];
         }
+        store_out(res, last_ks);
         cur.advance(n_ot, n_jt, n_ks, F);
     };
 
     for (int64_t it = 0; it < n_units / 2; ++it) {
-        body(buf0);
-        body(buf1);
+        body(buf0, 0);
+        body(buf1, 1);
     }
-    if (n_units & 1) body(buf0);
-    // the last finished tile
-    __syncthreads();
-#pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) lds_out[b_col * kOutStride + rg * 32 + rb * 16 + 4 * g + i] = res[rb][i];
-    __syncthreads();
-    store_tile(have_out);
+    if (n_units & 1) body(buf0, 0);
 }
 
-// w_hat [Cout][Cin][F] -> w_pack [F][SC4][Cout16][3][16]: balanced base-256 digits
-// (SC4 = ceil(Cin/16) rounded up to a multiple of 4; padding is zero).
-__global__ void pack_weights_kernel(const uint32_t *__restrict__ w_hat, int Cout, int Cin, int64_t F, int SC4,
-                                    int Cout16, int8_t *__restrict__ w_pack) {
-    const int64_t total = F * SC4 * Cout16;
+// Weight-fragment item k (16 bytes) of the unit (f, ks, ot): the operand one
+// lane of the matrix-core kernel hands the MFMA, in the order its threads load
+// and its waves read them.
+//   paired (Cin >= 48): 768 items [limb 3][row block 4][lane 64];
+//   folded (Cin < 48):  256 * ceil(Cin/16) items [channel group][row block 4][lane 64].
+// Lane ln of row block rbg covers tile row 32 (rbg / 2) + 8 (m / 4) + 4 (rbg % 2) + m % 4
+// (m = ln % 16), so that after the contraction each output lane holds 8
+// consecutive rows; its 16 bytes are one limb of 16 channels: channel group
+// 4 ks + ln / 16 and limb `limb` (paired), or channel group sc and limb
+// ln / 16 (folded; limb 3 is zero). Digits are the balanced base-256 digits
+// of W^ (bytes of W^ + 0x808080, each xor 0x80).
+__device__ __forceinline__ int frag_row(int rbg, int m) { return 32 * (rbg >> 1) + 8 * (m >> 2) + 4 * (rbg & 1) + (m & 3); }
+
+__global__ void pack_weights_kernel(const uint32_t *__restrict__ w_hat, int Cout, int Cin, int64_t F, int n_ks,
+                                    int n_ot, int n_items, int paired, int8_t *__restrict__ w_pack) {
+    const int64_t total = F * n_ks * n_ot * n_items;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
+        // f fastest: neighbouring threads read neighbouring W^ words
         const int64_t f = idx % F;
-        const int64_t rest = idx / F;
-        const int o = (int)(rest % Cout16), sc = (int)(rest / Cout16);
-        uint32_t dig[3][4] = {};
+        int64_t rest = idx / F;
+        const int k = (int)(rest % n_items);
+        rest /= n_items;
+        const int ot = (int)(rest % n_ot), ks = (int)(rest / n_ot);
+        const int ln = k & 63, rbg = (k >> 6) & 3, hi = k >> 8;
+        const int row = ot * 64 + frag_row(rbg, ln & 15);
+        const int group = paired ? ks * 4 + (ln >> 4) : hi;
+        const int limb = paired ? hi : (ln >> 4);
+        uint32_t dig[4] = {0, 0, 0, 0};
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-            const int i = sc * 16 + c;
+            const int i = group * 16 + c;
             uint32_t w = 0;
-            if (o < Cout && i < Cin) w = w_hat[((int64_t)o * Cin + i) * F + f];
-            const uint32_t u = (w + 0x808080u) ^ 0x808080u;  // balanced digits as bytes
-#pragma unroll
-            for (int l = 0; l < 3; ++l) dig[l][c >> 2] |= ((u >> (8 * l)) & 0xffu) << (8 * (c & 3));
+            if (row < Cout && i < Cin) w = w_hat[((int64_t)row * Cin + i) * F + f];
+            const uint32_t u = (w + 0x808080u) ^ 0x808080u;  // balanced digits as bytes (byte 3 is 0)
+            dig[c >> 2] |= ((u >> (8 * limb)) & 0xffu) << (8 * (c & 3));
         }
-        uint4 *dst = reinterpret_cast<uint4 *>(w_pack + (((f * SC4 + sc) * Cout16 + o) * 3) * 16);
-#pragma unroll
-        for (int l = 0; l < 3; ++l) dst[l] = make_uint4(dig[l][0], dig[l][1], dig[l][2], dig[l][3]);
+        const int64_t unit = ((int64_t)f * n_ks + ks) * n_ot + ot;
+        reinterpret_cast<uint4 *>(w_pack)[unit * n_items + k] = make_uint4(dig[0], dig[1], dig[2], dig[3]);
     }
 }
 
@@ -501,6 +532,7 @@ static int check_homconv(const ensei_ctx *ctx, const void *ct_in, const void *w,
     if (Cin > ENSEI_MAX_CIN || Cout > ENSEI_MAX_COUT || n > ENSEI_MAX_LWE_N || F > (1 << 20)) return ENSEI_ERR_LIMIT;
     // one (b, f) block of either side is addressed with 32-bit byte offsets
     if ((int64_t)(n + 1) * (Cin > Cout ? Cin : Cout) * 8 > 0x7fffffff) return ENSEI_ERR_LIMIT;
+    if ((int64_t)Cout * F * 4 > 0x7fffffff) return ENSEI_ERR_LIMIT;  // one image's masks, likewise
     if (((uintptr_t)ct_in & 7) || ((uintptr_t)ct_out & 7) || ((uintptr_t)r & 3)) return ENSEI_ERR_ALIGN;
     const size_t inb = (size_t)batch * Cin * F * (n + 1) * 8, outb = (size_t)batch * Cout * F * (n + 1) * 8;
     if (overlaps(ct_out, outb, ct_in, inb) || overlaps(ct_out, outb, w, wbytes) ||
@@ -517,7 +549,7 @@ extern "C" {
 
 size_t ensei_wpack_bytes(int Cout, int Cin, int64_t F) {
     if (Cout <= 0 || Cin <= 0 || F <= 0) return 0;
-    return (size_t)F * ((Cin + 63) / 64 * 4) * ((Cout + 15) / 16 * 16) * 48;
+    return (size_t)F * ((Cin + 63) / 64) * ((Cout + 63) / 64) * frag_items(Cin) * 16;
 }
 
 int ensei_pack_weights(ensei_ctx *ctx, const uint32_t *w_hat, int Cout, int Cin, int64_t F, int8_t *w_pack,
@@ -528,12 +560,12 @@ int ensei_pack_weights(ensei_ctx *ctx, const uint32_t *w_hat, int Cout, int Cin,
     if (Cin > ENSEI_MAX_CIN || Cout > ENSEI_MAX_COUT || F > (1 << 20)) return ENSEI_ERR_LIMIT;
     if (((uintptr_t)w_hat & 3) || ((uintptr_t)w_pack & 15)) return ENSEI_ERR_ALIGN;
     if (overlaps(w_pack, ensei_wpack_bytes(Cout, Cin, F), w_hat, (size_t)Cout * Cin * F * 4)) return ENSEI_ERR_OVERLAP;
-    const int SC4 = (Cin + 63) / 64 * 4, Cout16 = (Cout + 15) / 16 * 16;
-    const int64_t total = F * SC4 * Cout16;
+    const int n_ks = (Cin + 63) / 64, n_ot = (Cout + 63) / 64, n_items = frag_items(Cin);
+    const int64_t total = F * n_ks * n_ot * n_items;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(pack_weights_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, w_hat, Cout,
-                       Cin, F, SC4, Cout16, w_pack);
+                       Cin, F, n_ks, n_ot, n_items, (int)(Cin >= kPairedCin), w_pack);
     return launch_status();
 }
 
@@ -542,7 +574,6 @@ int ensei_homconv(ensei_ctx *ctx, const uint64_t *ct_in, const int8_t *w_pack, c
     int st = check_homconv(ctx, ct_in, w_pack, r, batch, Cin, Cout, F, n, ct_out, ensei_wpack_bytes(Cout, Cin, F));
     if (st) return st;
     if ((uintptr_t)w_pack & 15) return ENSEI_ERR_ALIGN;
-    const int SC4 = (Cin + 63) / 64 * 4, Cout16 = (Cout + 15) / 16 * 16;
     const int n_ot = (Cout + 63) / 64;
     const int n_jt = (n + 1 + 63) / 64;
     const int n_ks = (Cin + 63) / 64;
@@ -552,13 +583,11 @@ int ensei_homconv(ensei_ctx *ctx, const uint64_t *ct_in, const int8_t *w_pack, c
     if (n_tiles < blocks) blocks = n_tiles;
     // one limb pair per MFMA once the 64-channel K steps are full enough;
     // limbs folded into K for narrow inputs
-    if (Cin >= 48)
-        hipLaunchKernelGGL(homconv_mfma_kernel<true>, dim3((unsigned)blocks), dim3(kHcThreads), 0, (hipStream_t)stream,
-                           ct_in, w_pack, r, Cin, Cout, F, n, ctx->delta, ct_out, n_ot, n_jt, SC4, Cout16, n_tiles, n_ks);
-    else
-        hipLaunchKernelGGL(homconv_mfma_kernel<false>, dim3((unsigned)blocks), dim3(kHcThreads), 0,
-                           (hipStream_t)stream, ct_in, w_pack, r, Cin, Cout, F, n, ctx->delta, ct_out, n_ot, n_jt, SC4,
-                           Cout16, n_tiles, n_ks);
+    auto kernel = Cin >= kPairedCin
+                      ? (Cout % 2 == 0 ? homconv_mfma_kernel<true, true> : homconv_mfma_kernel<true, false>)
+                      : (Cout % 2 == 0 ? homconv_mfma_kernel<false, true> : homconv_mfma_kernel<false, false>);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kHcThreads), 0, (hipStream_t)stream, ct_in, w_pack, r, Cin,
+                       Cout, F, n, ctx->delta, ct_out, n_ot, n_jt, n_ks, frag_items(Cin), n_tiles);
     return launch_status();
 }
 

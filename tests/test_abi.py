@@ -53,9 +53,12 @@ def test_status_strings_and_host_only_calls(lib):
         assert isinstance(s, bytes) and len(s) > 0
     assert lib.ensei_status_str(12345) == b"unknown status"
     # packed-weight size is pure host arithmetic: F * ceil(Cin/64)*4 * roundup(Cout,16) * 48
-    assert lib.ensei_wpack_bytes(64, 64, 1024) == 1024 * 4 * 64 * 48
-    assert lib.ensei_wpack_bytes(8, 3, 256) == 256 * 4 * 16 * 48
-    assert lib.ensei_wpack_bytes(40, 130, 16) == 16 * 12 * 48 * 48
+    # F * ceil(Cin/64) * ceil(Cout/64) * U * 16, U = 768 (Cin >= 48) or 256 * ceil(Cin/16)
+    assert lib.ensei_wpack_bytes(64, 64, 1024) == 1024 * 1 * 1 * 768 * 16
+    assert lib.ensei_wpack_bytes(8, 3, 256) == 256 * 1 * 1 * 256 * 16
+    assert lib.ensei_wpack_bytes(40, 130, 16) == 16 * 3 * 1 * 768 * 16
+    assert lib.ensei_wpack_bytes(130, 33, 5) == 5 * 1 * 3 * 768 * 16
+    assert lib.ensei_wpack_bytes(512, 256, 16) == 16 * 4 * 8 * 768 * 16
     assert lib.ensei_wpack_bytes(0, 3, 256) == 0
     # context accessors tolerate NULL
     assert lib.ensei_ctx_modulus(None) == 0 and lib.ensei_ctx_delta(None) == 0

@@ -175,6 +175,22 @@ def test_homconv_extreme_words(ctx, orc):
     assert np.array_equal(got, ref)
 
 
+@pytest.mark.parametrize("Cin", [169, 170, 300])
+def test_homconv_extreme_digits(ctx, orc, Cin):
+    """Every ciphertext digit -128 and W^ = 0x8080 (limbs -128, -127, 1): the
+    largest same-sign shift sums, on both sides of the kernel's bound for its
+    32-bit partial recombination (Cin <= 169)."""
+    B, Cout, F, n = 1, 6, 2, 70
+    ct = np.full((B, F, n + 1, Cin), 0x7F7F7F7F7F7F7F80, dtype=np.uint64)
+    ct[:, :, 1::2, : Cin // 2] = 0x7F7F7F7F7F7F7F7F  # every digit +127
+    w = np.full((Cout, Cin, F), 0x8080, dtype=np.uint32)
+    w[1] = P - 1
+    r = np.full((B, Cout, F), 12345, dtype=np.uint32)
+    ref = orc.homconv(ct, w, r, P)
+    got = host(ctx.homconv(dev(ct), ctx.pack_weights(dev(w)), dev(r), Cout))
+    assert np.array_equal(got, ref)
+
+
 # -------------------------------------------------------- argument checks ---
 
 
