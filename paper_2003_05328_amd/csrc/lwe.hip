@@ -6,9 +6,10 @@
 // memory: 64 channels of one (b, f) when C >= 64, else floor(64 / C)
 // consecutive frequencies of all C channels. Lane = ciphertext, so every
 // wave instruction moves the group's word j of all its ciphertexts - one
-// contiguous 512-byte run when C >= 64. The four waves split the word range
-// [0, n) into quarters; the key byte s_j is the same for every lane (read from
-// LDS as a broadcast), each lane accumulates its own <a, s> and the four
+// contiguous 512-byte run when C >= 64. The waves of the workgroup (4 for
+// Enc, 16 for Dec) split the word range [0, n) into equal 4-aligned pieces;
+// the key byte s_j is the same for every lane (read from
+// LDS as a broadcast), each lane accumulates its own <a, s> and the waves'
 // partial sums meet in LDS. Encryption generates the uniform a-words on the
 // fly with a counter-based SplitMix64, so its only HBM traffic is the
 // ciphertexts written (plus 8 bytes of m and e per ciphertext).
@@ -63,7 +64,8 @@ __device__ __forceinline__ LweLane lwe_lane(const LweGroups &G, int C, int64_t F
     return L;
 }
 
-constexpr int kWaves = 4;
+constexpr int kWaves = 4;      // Enc: waves per workgroup
+constexpr int kDecWaves = 16;  // Dec: more waves per group keep more loads in flight
 
 // Key bytes s_j .. s_j+3 (the same for every lane) from the LDS copy of the
 // key, moved to a scalar register; j is a multiple of 4.
@@ -139,7 +141,7 @@ __device__ __forceinline__ uint32_t decode(uint64_t phi, uint32_t p) {
     return v >= p ? v - p : v;
 }
 
-__global__ __launch_bounds__(256) void decrypt_kernel(const uint64_t *__restrict__ ct, const int8_t *__restrict__ s,
+__global__ __launch_bounds__(64 * kDecWaves) void decrypt_kernel(const uint64_t *__restrict__ ct, const int8_t *__restrict__ s,
                                                       int C, int64_t F, int n, uint32_t p, uint32_t *__restrict__ m,
                                                       LweGroups G) {
     extern __shared__ uint8_t smem[];
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(256) void decrypt_kernel(const uint64_t *__restrict
     const int64_t rowlen = (int64_t)n + 1;
     const uint64_t *w = ct + (L.b * F + L.f) * rowlen * C + L.c;
     // word range of this wave, starting on a multiple of 4 (4-byte key reads)
-    const int per = ((n + 4 * kWaves - 1) / (4 * kWaves)) * 4, j0 = wave * per, j1 = min(n, j0 + per);
+    const int per = ((n + 4 * kDecWaves - 1) / (4 * kDecWaves)) * 4, j0 = wave * per, j1 = min(n, j0 + per);
     uint64_t acc_p = 0, acc_n = 0;
     if (L.ok) {
         int j = j0;
@@ -182,7 +184,9 @@ __global__ __launch_bounds__(256) void decrypt_kernel(const uint64_t *__restrict
     part[wave * 64 + lane] = acc_p - acc_n;
     __syncthreads();
     if (wave == 0 && L.ok) {
-        const uint64_t dot = part[lane] + part[64 + lane] + part[128 + lane] + part[192 + lane];
+        uint64_t dot = 0;
+#pragma unroll
+        for (int k = 0; k < kDecWaves; ++k) dot += part[k * 64 + lane];
         m[(L.b * C + L.c) * F + L.f] = decode(w[(int64_t)n * C] - dot, p);
     }
 }
@@ -229,8 +233,8 @@ int ensei_decrypt(ensei_ctx *ctx, const uint64_t *ct, const int8_t *s, int64_t b
     if (((uintptr_t)m & 3) || ((uintptr_t)ct & 7)) return ENSEI_ERR_ALIGN;
     const size_t num = (size_t)batch * C * F, ctb = num * (n + 1) * 8;
     if (overlaps(m, num * 4, ct, ctb) || overlaps(m, num * 4, s, (size_t)n)) return ENSEI_ERR_OVERLAP;
-    const size_t smem = ((n + 7) & ~7) + kWaves * 64 * 8;
-    hipLaunchKernelGGL(decrypt_kernel, dim3((unsigned)groups), dim3(256), smem, (hipStream_t)stream, ct, s, C, F, n,
+    const size_t smem = ((n + 7) & ~7) + kDecWaves * 64 * 8;
+    hipLaunchKernelGGL(decrypt_kernel, dim3((unsigned)groups), dim3(64 * kDecWaves), smem, (hipStream_t)stream, ct, s, C, F, n,
                        ctx->p, m, lwe_groups(C, F));
     return launch_status();
 }

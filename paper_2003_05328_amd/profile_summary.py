@@ -1,0 +1,120 @@
+"""Summaries of rocprofv3 output for the profiles/ folder.
+
+    python -m paper_2003_05328_amd.profile_summary --workload NAME \
+        --trace DIR [--fetch DIR --write DIR --copy-fetch DIR --copy-write DIR] \
+        --command "..." [--command "..."] --out profiles/NAME.md [--traffic profiles/homconv_traffic.json]
+
+DIR is a rocprofv3 output directory written with `-o run --output-format csv`
+(run_kernel_stats.csv for --kernel-trace --stats, run_counter_collection.csv
+for --pmc). The HBM counters FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are
+calibrated against a plain copy kernel of known size (the torch elementwise
+kernel of `bench.py --probe-copy`, which reads and writes 1 GiB): the factor
+is true bytes / counted bytes, applied per direction.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+import re
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HOMCONV_SRC = os.path.join(HERE, "csrc", "homconv.hip")
+COPY_BYTES = 1 << 30  # bench.py --probe-copy: 1 GiB read, 1 GiB written per launch
+
+
+def short_name(kernel: str) -> str:
+    name = kernel.split("(")[0]
+    name = re.sub(r"^void ", "", name)
+    return name.replace("ensei::", "")
+
+
+def kernel_stats(trace_dir: str):
+    rows = []
+    with open(os.path.join(trace_dir, "run_kernel_stats.csv")) as fh:
+        for r in csv.DictReader(fh):
+            rows.append((short_name(r["Name"]), int(r["Calls"]), float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3,
+                         float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    return rows
+
+
+def counter_means(pmc_dir: str, counter: str):
+    """Mean counter value per kernel (short name) over its dispatches."""
+    acc = defaultdict(list)
+    with open(os.path.join(pmc_dir, "run_counter_collection.csv")) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] == counter:
+                acc[short_name(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def copy_factor(pmc_dir: str, counter: str) -> float:
+    """True bytes / counted bytes for the copy kernel (largest mean among its dispatches)."""
+    means = counter_means(pmc_dir, counter)
+    kib = max(v for k, v in means.items() if "elementwise" in k)
+    return COPY_BYTES / (kib * 1024.0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-fetch")
+    ap.add_argument("--copy-write")
+    ap.add_argument("--command", action="append", default=[])
+    ap.add_argument("--kernel", default="homconv_mfma_kernel", help="kernel whose HBM bytes are recorded")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--traffic")
+    args = ap.parse_args()
+
+    lines = [f"# Kernel times and HBM traffic: {args.workload}", ""]
+    lines.append("Commands (run from the repository root on one MI355X; OUT is any output directory):")
+    lines.append("")
+    for c in args.command:
+        lines.append(f"    {c}")
+    lines += ["", "## rocprofv3 --kernel-trace --stats", "",
+              "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
+    for name, calls, avg, mn, mx, pct in kernel_stats(args.trace):
+        lines.append(f"| {name} | {calls} | {avg:.1f} | {mn:.1f} | {mx:.1f} | {pct:.1f} |")
+
+    record = None
+    if args.fetch and args.write and args.copy_fetch and args.copy_write:
+        ff, fw = copy_factor(args.copy_fetch, "FETCH_SIZE"), copy_factor(args.copy_write, "WRITE_SIZE")
+        fetch, write = counter_means(args.fetch, "FETCH_SIZE"), counter_means(args.write, "WRITE_SIZE")
+        lines += ["", "## HBM counters (rocprofv3 --pmc, one counter per run)", "",
+                  f"Copy-kernel calibration (1 GiB each way): FETCH_SIZE x {ff:.3f}, WRITE_SIZE x {fw:.3f}.", "",
+                  "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes per launch (calibrated) |", "|---|---|---|---|"]
+        for name in sorted(set(fetch) | set(write)):
+            if "elementwise" in name or "copyBuffer" in name:
+                continue
+            fk, wk = fetch.get(name, 0.0), write.get(name, 0.0)
+            hbm = fk * 1024 * ff + wk * 1024 * fw
+            lines.append(f"| {name} | {fk:.0f} | {wk:.0f} | {hbm / 1e6:.1f} MB |")
+            if args.kernel in name and record is None:
+                record = {
+                    "kernel": name,
+                    "workload": args.workload,
+                    "hbm_bytes_per_launch": int(round(hbm)),
+                    "fetch_kib": fk,
+                    "write_kib": wk,
+                    "fetch_factor": ff,
+                    "write_factor": fw,
+                    "source_sha256": hashlib.sha256(open(HOMCONV_SRC, "rb").read()).hexdigest(),
+                }
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    if args.traffic and record is not None:
+        with open(args.traffic, "w") as fh:
+            json.dump(record, fh, indent=1)
+            fh.write("\n")
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()
