@@ -4,16 +4,17 @@
  * Efficient Secure Inference via Frequency-Domain Homomorphic Convolution for
  * Privacy-Preserving Visual Recognition", CVPR 2020).
  *
- * One secure convolution (Fig. 2, round 0) is, with p one prime used as NTT,
- * share and plaintext modulus and q = 2^64 the ciphertext modulus:
- *   client:  x^ = NTT2D(x)                 ensei_ntt2d      (Fig. 2 line 1)
- *            ct_in = Enc(x^, s)            ensei_encrypt    (Fig. 2 line 2)
+ * One secure convolution (the start round of the protocol in Fig. 2) is,
+ * with p one prime used as NTT, share and plaintext modulus and q = 2^64 the
+ * ciphertext modulus:
+ *   client:  x^ = NTT2D(x)                 ensei_ntt2d      (client transforms its input)
+ *            ct_in = Enc(x^, s)            ensei_encrypt    (and encrypts it)
  *   server:  W^ = NTT2D(pad(w))            ensei_weight_prep + ensei_pack_weights (setup)
- *            ct_out = sum_i W^ ct_in + Delta r   ensei_homconv (lines 3-4)
- *   client:  m = Dec(ct_out, s)            ensei_decrypt    (line 5)
- *            s_A = INTT2D(m)               ensei_intt2d     (line 6)
- *   server:  s_B = INTT2D(-r)              ensei_server_share (line 6)
- * and s_A + s_B = x (*) w mod p (Sec. 4.1.1, Appendix A).
+ *            ct_out = sum_i W^ ct_in + Delta r   ensei_homconv (Hadamard product, HomShare)
+ *   client:  m = Dec(ct_out, s)            ensei_decrypt    (client decrypts)
+ *            s_A = INTT2D(m)               ensei_intt2d     (both parties take the inverse
+ *   server:  s_B = INTT2D(-r)              ensei_server_share  transform of their shares)
+ * and s_A + s_B = x (*) w mod p (Sec. 4.1, Appendix A).
  *
  * Common rules for every call below:
  *   - every array pointer is a DEVICE pointer on the context's device, owned
@@ -166,7 +167,7 @@ int ensei_encrypt(ensei_ctx *ctx, const uint32_t *m, const int8_t *s, const int3
 /* -------------------------------------------------------------- HomConv --
  * Server-side homomorphic convolution in the frequency domain: the
  * homomorphic Hadamard product with the transformed filters, summed over
- * input channels, then HomShare's mask (Fig. 2 lines 3-4; Eq. (homshare)):
+ * input channels, then HomShare's mask (Fig. 2; HomShare in Sec. 3.2):
  *   ct_out(b, o, f)[j] = sum_i W^[o][i][f] * ct_in(b, i, f)[j]  mod 2^64,  j <= n
  *   ct_out(b, o, f)[n] += Delta * r[b][o][f]                      mod 2^64
  * so Dec(ct_out(b, o, f)) = (sum_i W^ x^ + r) mod p and the server keeps -r.
