@@ -197,6 +197,86 @@ int ensei_homconv_valu(ensei_ctx *ctx, const uint64_t *ct_in, const uint32_t *w_
 int ensei_decrypt(ensei_ctx *ctx, const uint64_t *ct, const int8_t *s, int64_t batch, int C, int64_t F, int n,
                   uint32_t *m, void *stream);
 
+/* ------------------------------------------------------ batched plans --
+ * A plan runs a stack of independent secure convolutions (Fig. 2's start
+ * round for each layer; layers of uneven shapes, each over a batch of images
+ * of one client) as one captured HIP graph: per layer NTT2D and Enc, then ONE
+ * persistent matrix-core HomConv launch over the tiles of all layers, then
+ * per layer Dec, INTT2D and the server share. The server's filters are
+ * transformed and packed once, when the plan is created.
+ *
+ * The HomConv tile schedule (persistent workgroups; contiguous tile ranges
+ * or chunks of 1..256 tiles dealt round-robin) is picked by timing the
+ * candidates on the plan's own shapes and buffers at creation. With a
+ * non-NULL tune_cache path the choice is looked up there first, keyed by the
+ * device and the layer shapes, and appended after tuning (a text file, one
+ * line "key blocks chunk [us]" per entry; the last matching line wins and a
+ * line whose key is "*" matches every plan, which pins a schedule). Tuning
+ * and the cache never change results.
+ *
+ * ensei_layer: shape, the server's filters, and the caller's device buffers.
+ * Shapes and layouts are those of the single calls (F = H*W):
+ *   w [Cout][Cin][kh][kw] int32 (read at creation only);
+ *   per run, read:  x [batch][Cin][H][W] residues < p, s [n] ternary int8,
+ *                   e [batch][Cin][F] int32, r [batch][Cout][F] masks < p;
+ *   per run, written: x_hat [batch][Cin][F], ct_in [batch][F][n+1][Cin],
+ *                   ct_out [batch][F][n+1][Cout], m [batch][Cout][F],
+ *                   s_a and s_b [batch][Cout][H][W] (client and server shares).
+ * The plan keeps the pointers: the buffers must stay valid and unmoved until
+ * ensei_plan_destroy, and runs see their current contents. Word j of
+ * ciphertext (b, c, f) of layer l is keyed by seed_a of layer l and
+ * q = (b*F + f)*Cin + c, exactly as ensei_encrypt with ct_index0 = 0. */
+typedef struct ensei_plan ensei_plan;
+
+typedef struct ensei_layer {
+    int H, W, Cin, Cout, kh, kw, n;
+    int64_t batch;
+    uint64_t seed_a;
+    const int32_t *w;
+    const uint32_t *x;
+    const int8_t *s;
+    const int32_t *e;
+    const uint32_t *r;
+    uint32_t *x_hat;
+    uint64_t *ct_in;
+    uint64_t *ct_out;
+    uint32_t *m;
+    uint32_t *s_a;
+    uint32_t *s_b;
+} ensei_layer;
+
+/* The HomConv schedule a plan runs: persistent workgroups, chunk (0 =
+ * contiguous tile ranges), the measured time of its HomConv launch in
+ * microseconds (0 when taken from the cache), and whether it came from the
+ * cache (1) or from tuning (0). */
+typedef struct ensei_schedule {
+    int blocks;
+    int from_cache;
+    int64_t chunk;
+    double homconv_us;
+} ensei_schedule;
+
+/* Creates a plan for nlayers (1..ENSEI_MAX_PLAN_LAYERS) layers. Allocates the
+ * transformed and packed filters and a small launch table on the context's
+ * device (freed by ensei_plan_destroy), runs the filters' preparation, tunes
+ * the schedule, runs the whole stack once eagerly (so every argument check of
+ * the single calls applies and is reported here) and captures the graph.
+ * Synchronous. Errors: those of the single calls, ENSEI_ERR_LIMIT for too
+ * many layers, ENSEI_ERR_HIP for allocation or capture failures. */
+#define ENSEI_MAX_PLAN_LAYERS 64
+int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const char *tune_cache,
+                      ensei_plan **out);
+
+/* Enqueues one run of the captured graph on `stream` (asynchronous). */
+int ensei_plan_run(ensei_plan *plan, void *stream);
+
+/* The schedule the plan runs (see ensei_schedule). */
+int ensei_plan_schedule(const ensei_plan *plan, ensei_schedule *out);
+
+/* Frees the plan's device memory and graph; NULL is accepted. Wait for the
+ * plan's runs to finish first. */
+int ensei_plan_destroy(ensei_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

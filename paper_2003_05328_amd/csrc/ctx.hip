@@ -130,9 +130,9 @@ int ensei_ctx_create(ensei_ctx **out, uint32_t p, int device) {
     if (hipMalloc(&c->d_tw, sizeof(tw)) != hipSuccess ||
         hipMemcpy(c->d_tw, tw, sizeof(tw), hipMemcpyHostToDevice) != hipSuccess)
         st = ENSEI_ERR_HIP;
-    hipSetDevice(prev);
+    (void)hipSetDevice(prev);
     if (st != ENSEI_OK) {
-        if (c->d_tw) hipFree(c->d_tw);
+        if (c->d_tw) (void)hipFree(c->d_tw);
         free(c);
         return st;
     }
@@ -143,10 +143,10 @@ int ensei_ctx_create(ensei_ctx **out, uint32_t p, int device) {
 int ensei_ctx_destroy(ensei_ctx *ctx) {
     if (!ctx) return ENSEI_OK;
     int prev = 0;
-    hipGetDevice(&prev);
-    hipSetDevice(ctx->device);
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(ctx->device);
     hipError_t e = hipFree(ctx->d_tw);
-    hipSetDevice(prev);
+    (void)hipSetDevice(prev);
     free(ctx);
     return e == hipSuccess ? ENSEI_OK : ENSEI_ERR_HIP;
 }

@@ -61,4 +61,40 @@ __device__ __forceinline__ uint32_t reduce_once(uint32_t x, uint32_t m) {
     return y < x ? y : x;  // y < x exactly when x >= m
 }
 
+// ------------------------------------------------------------ HomConv --
+// One HomConv problem of a launch; a multi-problem launch reads an array of
+// these from device memory. tile0 is the problem's first tile in the
+// launch's concatenated tile space (tiles of 64 rows x 64 words per (b, f)).
+struct HcLayer {
+    const uint64_t *ct_in;
+    const int8_t *w_pack;
+    const uint32_t *r;
+    uint64_t *ct_out;
+    int64_t F, B, tile0, n_tiles;
+    int Cin, Cout, n, n_ot, n_jt, n_ks, n_items, pad;
+};
+
+// Tile schedule of a HomConv launch: persistent workgroups, and chunk = 0
+// (one contiguous tile range per workgroup) or the size of the chunks dealt
+// out round-robin.
+struct HcSchedule {
+    int blocks;
+    int64_t chunk;
+};
+
+constexpr int kPairedCin = 48;  // ensei_homconv's paired limb scheme from this many input channels on
+
+// 16-byte weight-fragment items per (f, K step, row tile) unit of each scheme
+inline int frag_items(int Cin, bool paired) { return paired ? 768 : 256 * ((Cin + 15) / 16); }
+size_t wpack_bytes_as(int Cout, int Cin, int64_t F, bool paired);
+int pack_weights_as(const ensei_ctx *ctx, const uint32_t *w_hat, int Cout, int Cin, int64_t F, bool paired,
+                    int8_t *w_pack, hipStream_t stream);
+// Checks one problem's sizes and fills its derived fields (tile0 = 0).
+int homconv_problem(const ensei_ctx *ctx, HcLayer *P, const uint64_t *ct_in, const int8_t *w_pack, const uint32_t *r,
+                    int64_t B, int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, size_t wbytes);
+// Launches the matrix-core HomConv over problems[0..nlayers) (host copies;
+// dev_table holds the same array in device memory when nlayers > 1).
+int homconv_launch(const ensei_ctx *ctx, const HcLayer *problems, const HcLayer *dev_table, int nlayers, bool paired,
+                   HcSchedule sched, hipStream_t stream);
+
 }  // namespace ensei

@@ -86,21 +86,11 @@ __device__ __forceinline__ void transpose4(uint32_t x0, uint32_t x1, uint32_t x2
     y3 = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
 }
 
-// Position of one work unit, advanced in the order units are processed.
+// Position of one work unit: layer L, global tile t, and within the layer's
+// tile the row tile ot, column tile jt, K step ks, frequency f and image b.
 struct HcCoord {
-    int ot, jt, ks;
-    int64_t f, b;
-    __device__ void advance(int n_ot, int n_jt, int n_ks, int64_t F) {
-        if (++ks < n_ks) return;
-        ks = 0;
-        if (++ot < n_ot) return;
-        ot = 0;
-        if (++jt < n_jt) return;
-        jt = 0;
-        if (++f < F) return;
-        f = 0;
-        ++b;
-    }
+    int L, ot, jt, ks;
+    int64_t t, f, b;
 };
 
 // Data of one unit in flight: 8 words per thread, 2 weight-fragment items, 1 mask.
@@ -111,10 +101,6 @@ struct HcBuf {
 };
 
 constexpr int kHcThreads = 512;
-constexpr int kPairedCin = 48;  // the paired limb scheme from this many input channels on
-
-// 16-byte weight-fragment items per (f, K step, row tile) unit
-__host__ __device__ inline int frag_items(int Cin) { return Cin >= kPairedCin ? 768 : 256 * ((Cin + 15) / 16); }
 
 // Shift accumulators -> one u64 word, mod 2^64:
 //   sum_{s<4} 256^s acc_s exactly (signed), plus 2^32 (sum_{s>=4} 256^(s-4) acc_s mod 2^32).
@@ -147,11 +133,16 @@ __device__ __forceinline__ uint64_t recombine(int a0, int a1, int a2, int a3, in
 // LDS operand reads. Used when Cin >= 48.
 // WIDE_STORE: Cout is even, so the two words of every 16-byte store are
 // both inside the output row or both outside it.
-template <bool PAIRED, bool WIDE_STORE>
-__global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
-    const uint64_t *__restrict__ ct_in, const int8_t *__restrict__ w_pack, const uint32_t *__restrict__ r, int Cin,
-    int Cout, int64_t F, int n, uint64_t delta, uint64_t *__restrict__ ct_out, int n_ot, int n_jt, int n_ks,
-    int n_items, int64_t n_tiles) {
+// MULTI: the launch walks the concatenated tiles of several HomConv
+// problems (layers of uneven shapes) read from a device table; otherwise the
+// one problem comes in the kernel arguments.
+// Tile schedule: with chunk == 0 each workgroup takes one contiguous range of
+// tiles; otherwise tiles are dealt out in chunks of `chunk` consecutive tiles,
+// chunk c to workgroup c mod gridDim.x.
+template <bool PAIRED, bool WIDE_STORE, bool MULTI>
+__global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, const HcLayer *__restrict__ table,
+                                                                  int nlayers, int64_t total_tiles, int64_t chunk,
+                                                                  uint64_t delta) {
     constexpr int kAItems = PAIRED ? 3 * 4 * 64 : 4 * 4 * 64;  // [limb 3 | sc 4][row block 4][lane 64] x 16 B
     constexpr int kA = kAItems * 16;
     constexpr int kZeroPlanes = PAIRED ? 0 : 2;  // the folded scheme reads planes -2, -1 as zero
@@ -169,21 +160,35 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, l16 = lane & 15;
     const int cg = wave & 3, rg = wave >> 2;  // MFMA role: columns 16 cg.., rows 32 rg..
-    const int64_t rowlen = (int64_t)n + 1;
-    const uint32_t in_block = (uint32_t)(rowlen * Cin * 8);  // bytes of one (b, f) input block
-    const uint32_t out_col_bytes = (uint32_t)(Cout * 8);      // one output word index j
-    const bool small = Cin <= kSmallCin;
+    // problem L's parameters (wave-uniform: scalar loads from the table)
+    auto layer = [&](int L) -> HcLayer { return MULTI ? table[L] : one; };
 
-    // this block's contiguous tile range
-    const int64_t per = n_tiles / gridDim.x, extra = n_tiles % gridDim.x;
-    const int64_t t0 = blockIdx.x * per + (blockIdx.x < extra ? blockIdx.x : extra);
-    const int64_t ntile = per + (blockIdx.x < extra ? 1 : 0);
-    if (ntile == 0) return;
-    const int64_t n_units = ntile * n_ks;
+    // this block's tiles: [t_lo, t_hi) when contiguous; else its chunks
+    const int64_t G = gridDim.x;
+    int64_t t_lo = 0, t_hi = 0;
+    if (chunk == 0) {
+        const int64_t per = total_tiles / G, extra = total_tiles % G;
+        t_lo = blockIdx.x * per + (blockIdx.x < extra ? blockIdx.x : extra);
+        t_hi = t_lo + per + (blockIdx.x < extra ? 1 : 0);
+    }
+    // number of this block's tiles below x
+    auto owned_below = [&](int64_t x) -> int64_t {
+        if (chunk == 0) return (x < t_lo ? t_lo : x > t_hi ? t_hi : x) - t_lo;
+        const int64_t S = G * chunk, rem = x % S - (int64_t)blockIdx.x * chunk;
+        return x / S * chunk + (rem < 0 ? 0 : rem > chunk ? chunk : rem);
+    };
+    // units = sum over problems of (owned tiles) x (K steps)
+    int64_t n_units = 0;
+    for (int L = 0; L < nlayers; ++L) {
+        const HcLayer P = layer(L);
+        n_units += (owned_below(P.tile0 + P.n_tiles) - owned_below(P.tile0)) * P.n_ks;
+    }
+    if (n_units == 0) return;
 
-    for (int i = tid; i < 2 * kZeroPlanes * kPlaneBytes / 16; i += kHcThreads) {
-        const int lb = i / (kZeroPlanes * kPlaneBytes / 16), k = i % (kZeroPlanes * kPlaneBytes / 16);
-        reinterpret_cast<uint4 *>(lds + lb * kLdsBuf)[k] = make_uint4(0, 0, 0, 0);
+    if (kZeroPlanes > 0) {
+        constexpr int kZero16 = (kZeroPlanes > 0 ? kZeroPlanes : 1) * kPlaneBytes / 16;  // per buffer
+        for (int i = tid; i < 2 * kZero16; i += kHcThreads)
+            reinterpret_cast<uint4 *>(lds + (i / kZero16) * kLdsBuf)[i % kZero16] = make_uint4(0, 0, 0, 0);
     }
 
     // load role: column ld_col, channel group ld_sc, half ld_h (8 channels)
@@ -195,9 +200,13 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
     const int out_row = 32 * rg + 8 * g;  // first of this lane's 8 output rows in the tile
 
     auto issue = [&](const HcCoord &u, HcBuf &buf) {
+        const HcLayer P = layer(u.L);
+        const int Cin = P.Cin, Cout = P.Cout;
+        const int64_t F = P.F, rowlen = (int64_t)P.n + 1;
         const int col = u.jt * 64 + ld_col;
-        const uint8_t *blk = uniform_ptr(reinterpret_cast<const uint8_t *>(ct_in + (u.b * F + u.f) * rowlen * Cin));
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc(blk, in_block);
+        const uint8_t *blk =
+            uniform_ptr(reinterpret_cast<const uint8_t *>(P.ct_in + (u.b * F + u.f) * rowlen * Cin));
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(blk, (uint32_t)(rowlen * Cin * 8));
         // columns past n read zero; channels past Cin read the next column's
         // words, which meet zero weights
         const uint32_t off = (uint32_t)(((int64_t)col * Cin + u.ks * 64 + ld_sc * 16 + ld_h * 8) * 8);
@@ -205,9 +214,9 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
         for (int q = 0; q < 4; ++q) buf.w[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16 * q), 0, 0);
         // the unit's weight fragments: n_items contiguous 16-byte items, item k
         // read by thread k % 512 (items past n_items read zero, with no traffic)
-        const int64_t unit = ((int64_t)u.f * n_ks + u.ks) * n_ot + u.ot;
-        const __amdgpu_buffer_rsrc_t ra =
-            make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(w_pack) + unit * n_items * 16), (uint32_t)(n_items * 16));
+        const int64_t unit = ((int64_t)u.f * P.n_ks + u.ks) * P.n_ot + u.ot;
+        const __amdgpu_buffer_rsrc_t ra = make_rsrc(
+            uniform_ptr(reinterpret_cast<const uint8_t *>(P.w_pack) + unit * P.n_items * 16), (uint32_t)(P.n_items * 16));
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(ra, (tid + kHcThreads * j) * 16, 0, 0);
@@ -218,30 +227,57 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
         // generates no memory traffic
         const int o = u.ot * 64 + tid;
         const __amdgpu_buffer_rsrc_t rr =
-            make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(r + u.b * Cout * F + u.f)),
-                      u.jt == n_jt - 1 ? (uint32_t)(((int64_t)(Cout - 1) * F + 1) * 4) : 0u);
+            make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(P.r + u.b * Cout * F + u.f)),
+                      u.jt == P.n_jt - 1 ? (uint32_t)(((int64_t)(Cout - 1) * F + 1) * 4) : 0u);
         buf.r = __builtin_amdgcn_raw_buffer_load_b32(rr, (int)(tid < 64 && o < Cout ? (uint32_t)(o * F * 4) : 0x80000000u),
                                                      0, 0);
     };
 
+    // coordinates of global tile t (K step 0); t past the end leaves c as is
+    auto seek = [&](HcCoord &c, int64_t t) {
+        if (t >= total_tiles) return;
+        int L = 0;
+        while (L + 1 < nlayers && t >= layer(L + 1).tile0) ++L;
+        const HcLayer P = layer(L);
+        int64_t x = t - P.tile0;
+        c.L = L;
+        c.t = t;
+        c.ks = 0;
+        c.ot = (int)(x % P.n_ot);
+        x /= P.n_ot;
+        c.jt = (int)(x % P.n_jt);
+        x /= P.n_jt;
+        c.f = x % P.F;
+        c.b = x / P.F;
+    };
+    // the next unit in processing order: K steps, then row tiles, column
+    // tiles, frequencies, images, problems; a new chunk is looked up
+    auto advance = [&](HcCoord &c) {
+        const HcLayer P = layer(c.L);
+        if (++c.ks < P.n_ks) return;
+        c.ks = 0;
+        ++c.t;
+        if (chunk != 0 && c.t % chunk == 0) {
+            seek(c, c.t + (G - 1) * chunk);
+            return;
+        }
+        if (++c.ot < P.n_ot) return;
+        c.ot = 0;
+        if (++c.jt < P.n_jt) return;
+        c.jt = 0;
+        if (++c.f < P.F) return;
+        c.f = 0;
+        if (++c.b < P.B) return;
+        c.b = 0;
+        if (c.L + 1 < nlayers) ++c.L;
+    };
     HcCoord cur, nx;
-    {
-        int64_t t = t0;
-        cur.ks = 0;
-        cur.ot = (int)(t % n_ot);
-        t /= n_ot;
-        cur.jt = (int)(t % n_jt);
-        t /= n_jt;
-        cur.f = t % F;
-        cur.b = t / F;
-    }
-    // 16-channel groups holding channels in the last K step (folded scheme)
-    const int sc_last = (Cin - 64 * (n_ks - 1) + 15) / 16;
+    seek(cur, chunk == 0 ? t_lo : (int64_t)blockIdx.x * chunk);
     v4i acc[8][2];
 
     // MFMA phase of one unit; FRESH: the first product into each shift
     // accumulator starts from zero (the unit is the tile's first K step)
-    auto contract = [&](auto fresh_tag, int lb) {
+    auto contract = [&](auto fresh_tag, int lb, int sc_here) {
         constexpr bool FRESH = decltype(fresh_tag)::value;
         const v4i zero = {0, 0, 0, 0};
         if (PAIRED) {
@@ -268,7 +304,7 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
         } else {
 #pragma unroll
             for (int sc = 0; sc < 4; ++sc) {
-                if (sc >= (cur.ks == n_ks - 1 ? sc_last : 4)) break;  // groups past Cin are zero
+                if (sc >= sc_here) break;  // groups past Cin are zero
                 v4i A[2];
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb)
@@ -288,7 +324,11 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
 
     // 8 output words of this lane: tile rows out_row + 4 rb + i of column b_col
     auto store_out = [&](const uint64_t (&res)[2][4], bool valid) {
-        const uint64_t *blk = ct_out + ((cur.b * F + cur.f) * rowlen + cur.jt * 64) * Cout;
+        const HcLayer P = layer(cur.L);
+        const int Cout = P.Cout;
+        const int64_t F = P.F, rowlen = (int64_t)P.n + 1;
+        const uint32_t out_col_bytes = (uint32_t)(Cout * 8);  // one output word index j
+        const uint64_t *blk = P.ct_out + ((cur.b * F + cur.f) * rowlen + cur.jt * 64) * Cout;
         // columns past n fall outside the block and are dropped
         const uint32_t nbytes = valid ? (uint32_t)((rowlen - cur.jt * 64) * Cout * 8) : 0u;
         const __amdgpu_buffer_rsrc_t rs =
@@ -350,13 +390,14 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
     nx = cur;
     issue(nx, buf0);
     store_out(none, false);
-    if (n_units > 1) nx.advance(n_ot, n_jt, n_ks, F);
+    if (n_units > 1) advance(nx);
     issue(nx, buf1);
     store_out(none, false);
     int64_t issued = n_units > 1 ? 2 : 1;
 
     auto body = [&](HcBuf &buf, int lb) {
-        const bool last_ks = cur.ks == n_ks - 1;
+        const HcLayer P = layer(cur.L);
+        const bool last_ks = cur.ks == P.n_ks - 1;
 
         // digit planes of this unit's 8 words: 8 bytes of each plane
         uint32_t pl[8][2];
@@ -393,15 +434,17 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
         // the unit two ahead reuses this buffer (past the end: reissue the
         // last one, keeping the load count static)
         if (issued < n_units) {
-            nx.advance(n_ot, n_jt, n_ks, F);
+            advance(nx);
             ++issued;
         }
         issue(nx, buf);
 
+        // 16-channel groups holding channels in this K step (folded scheme)
+        const int sc_here = last_ks ? (P.Cin - 64 * (P.n_ks - 1) + 15) / 16 : 4;
         if (cur.ks == 0)
-            contract(std::true_type{}, lb);
+            contract(std::true_type{}, lb, sc_here);
         else
-            contract(std::false_type{}, lb);
+            contract(std::false_type{}, lb, sc_here);
 
         // epilogue: recombine the shift accumulators (in every unit, so the
         // store count stays static; only the tile's last K step stores)
@@ -415,19 +458,19 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(
                     res[rb][i] = recombine<SMALL>(acc[0][rb][i], acc[1][rb][i], acc[2][rb][i], acc[3][rb][i],
                                                   acc[4][rb][i], acc[5][rb][i], acc[6][rb][i], acc[7][rb][i]);
         };
-        if (small)
+        if (P.Cin <= kSmallCin)
             recombine_all(std::true_type{});
         else
             recombine_all(std::false_type{});
         // HomShare: Delta * r on the b word (column n)
-        if (cur.jt * 64 + 64 > n && cur.jt * 64 + b_col == n) {
+        if (cur.jt * 64 + 64 > P.n && cur.jt * 64 + b_col == P.n) {
 #pragma unroll
             for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) res[rb][i] += delta * (uint64_t)lds_r(lb)[out_row + 4 * rb + i];
         }
         store_out(res, last_ks);
-        cur.advance(n_ot, n_jt, n_ks, F);
+        advance(cur);
     };
 
     for (int64_t it = 0; it < n_units / 2; ++it) {
@@ -541,54 +584,103 @@ static int check_homconv(const ensei_ctx *ctx, const void *ct_in, const void *w,
     return ENSEI_OK;
 }
 
+size_t wpack_bytes_as(int Cout, int Cin, int64_t F, bool paired) {
+    if (Cout <= 0 || Cin <= 0 || F <= 0) return 0;
+    return (size_t)F * ((Cin + 63) / 64) * ((Cout + 63) / 64) * frag_items(Cin, paired) * 16;
+}
+
+int pack_weights_as(const ensei_ctx *ctx, const uint32_t *w_hat, int Cout, int Cin, int64_t F, bool paired,
+                    int8_t *w_pack, hipStream_t stream) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!w_hat || !w_pack || Cout <= 0 || Cin <= 0 || F <= 0) return ENSEI_ERR_ARG;
+    if (Cin > ENSEI_MAX_CIN || Cout > ENSEI_MAX_COUT || F > (1 << 20)) return ENSEI_ERR_LIMIT;
+    if (!paired && Cin >= 64) return ENSEI_ERR_ARG;  // the folded layout holds one 64-channel step
+    if (((uintptr_t)w_hat & 3) || ((uintptr_t)w_pack & 15)) return ENSEI_ERR_ALIGN;
+    if (overlaps(w_pack, wpack_bytes_as(Cout, Cin, F, paired), w_hat, (size_t)Cout * Cin * F * 4))
+        return ENSEI_ERR_OVERLAP;
+    const int n_ks = (Cin + 63) / 64, n_ot = (Cout + 63) / 64, n_items = frag_items(Cin, paired);
+    const int64_t total = F * n_ks * n_ot * n_items;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(pack_weights_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, w_hat, Cout, Cin, F, n_ks,
+                       n_ot, n_items, (int)paired, w_pack);
+    return launch_status();
+}
+
+int homconv_problem(const ensei_ctx *ctx, HcLayer *P, const uint64_t *ct_in, const int8_t *w_pack, const uint32_t *r,
+                    int64_t B, int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, size_t wbytes) {
+    int st = check_homconv(ctx, ct_in, w_pack, r, B, Cin, Cout, F, n, ct_out, wbytes);
+    if (st) return st;
+    if ((uintptr_t)w_pack & 15) return ENSEI_ERR_ALIGN;
+    P->ct_in = ct_in;
+    P->w_pack = w_pack;
+    P->r = r;
+    P->ct_out = ct_out;
+    P->F = F;
+    P->B = B;
+    P->Cin = Cin;
+    P->Cout = Cout;
+    P->n = n;
+    P->n_ot = (Cout + 63) / 64;
+    P->n_jt = (n + 1 + 63) / 64;
+    P->n_ks = (Cin + 63) / 64;
+    P->n_items = frag_items(Cin, Cin >= kPairedCin);
+    P->tile0 = 0;
+    P->n_tiles = B * F * P->n_jt * P->n_ot;
+    P->pad = 0;
+    return ENSEI_OK;
+}
+
+int homconv_launch(const ensei_ctx *ctx, const HcLayer *problems, const HcLayer *dev_table, int nlayers, bool paired,
+                   HcSchedule sched, hipStream_t stream) {
+    if (nlayers < 1 || (nlayers > 1 && (!dev_table || !paired))) return ENSEI_ERR_ARG;
+    int64_t total = 0;
+    bool wide = true;
+    for (int L = 0; L < nlayers; ++L) {
+        total += problems[L].n_tiles;
+        wide = wide && problems[L].Cout % 2 == 0;
+    }
+    // persistent grid: at most one resident 8-wave workgroup per CU
+    int64_t blocks = sched.blocks > 0 ? sched.blocks : ctx->num_cus;
+    if (blocks > ctx->num_cus) blocks = ctx->num_cus;
+    if (sched.chunk == 0 && total < blocks) blocks = total;
+    if (sched.chunk < 0) return ENSEI_ERR_ARG;
+    if (nlayers > 1) {
+        auto kernel = wide ? homconv_mfma_kernel<true, true, true> : homconv_mfma_kernel<true, false, true>;
+        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kHcThreads), 0, stream, problems[0], dev_table, nlayers,
+                           total, sched.chunk, ctx->delta);
+    } else {
+        // one limb pair per MFMA once the 64-channel K steps are full enough;
+        // limbs folded into K for narrow inputs
+        auto kernel = paired ? (wide ? homconv_mfma_kernel<true, true, false> : homconv_mfma_kernel<true, false, false>)
+                             : (wide ? homconv_mfma_kernel<false, true, false> : homconv_mfma_kernel<false, false, false>);
+        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kHcThreads), 0, stream, problems[0], dev_table, 1,
+                           total, sched.chunk, ctx->delta);
+    }
+    return launch_status();
+}
+
 }  // namespace ensei
 
 using namespace ensei;
 
 extern "C" {
 
-size_t ensei_wpack_bytes(int Cout, int Cin, int64_t F) {
-    if (Cout <= 0 || Cin <= 0 || F <= 0) return 0;
-    return (size_t)F * ((Cin + 63) / 64) * ((Cout + 63) / 64) * frag_items(Cin) * 16;
-}
+size_t ensei_wpack_bytes(int Cout, int Cin, int64_t F) { return wpack_bytes_as(Cout, Cin, F, Cin >= kPairedCin); }
 
 int ensei_pack_weights(ensei_ctx *ctx, const uint32_t *w_hat, int Cout, int Cin, int64_t F, int8_t *w_pack,
                        void *stream) {
-    int st = check_ctx(ctx);
-    if (st) return st;
-    if (!w_hat || !w_pack || Cout <= 0 || Cin <= 0 || F <= 0) return ENSEI_ERR_ARG;
-    if (Cin > ENSEI_MAX_CIN || Cout > ENSEI_MAX_COUT || F > (1 << 20)) return ENSEI_ERR_LIMIT;
-    if (((uintptr_t)w_hat & 3) || ((uintptr_t)w_pack & 15)) return ENSEI_ERR_ALIGN;
-    if (overlaps(w_pack, ensei_wpack_bytes(Cout, Cin, F), w_hat, (size_t)Cout * Cin * F * 4)) return ENSEI_ERR_OVERLAP;
-    const int n_ks = (Cin + 63) / 64, n_ot = (Cout + 63) / 64, n_items = frag_items(Cin);
-    const int64_t total = F * n_ks * n_ot * n_items;
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(pack_weights_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, w_hat, Cout,
-                       Cin, F, n_ks, n_ot, n_items, (int)(Cin >= kPairedCin), w_pack);
-    return launch_status();
+    return pack_weights_as(ctx, w_hat, Cout, Cin, F, Cin >= kPairedCin, w_pack, (hipStream_t)stream);
 }
 
 int ensei_homconv(ensei_ctx *ctx, const uint64_t *ct_in, const int8_t *w_pack, const uint32_t *r, int64_t batch,
                   int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, void *stream) {
-    int st = check_homconv(ctx, ct_in, w_pack, r, batch, Cin, Cout, F, n, ct_out, ensei_wpack_bytes(Cout, Cin, F));
+    HcLayer P;
+    int st = homconv_problem(ctx, &P, ct_in, w_pack, r, batch, Cin, Cout, F, n, ct_out,
+                             ensei_wpack_bytes(Cout, Cin, F));
     if (st) return st;
-    if ((uintptr_t)w_pack & 15) return ENSEI_ERR_ALIGN;
-    const int n_ot = (Cout + 63) / 64;
-    const int n_jt = (n + 1 + 63) / 64;
-    const int n_ks = (Cin + 63) / 64;
-    const int64_t n_tiles = batch * F * n_jt * n_ot;
-    // persistent grid: one resident 8-wave workgroup per CU
-    int64_t blocks = (int64_t)ctx->num_cus;
-    if (n_tiles < blocks) blocks = n_tiles;
-    // one limb pair per MFMA once the 64-channel K steps are full enough;
-    // limbs folded into K for narrow inputs
-    auto kernel = Cin >= kPairedCin
-                      ? (Cout % 2 == 0 ? homconv_mfma_kernel<true, true> : homconv_mfma_kernel<true, false>)
-                      : (Cout % 2 == 0 ? homconv_mfma_kernel<false, true> : homconv_mfma_kernel<false, false>);
-    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kHcThreads), 0, (hipStream_t)stream, ct_in, w_pack, r, Cin,
-                       Cout, F, n, ctx->delta, ct_out, n_ot, n_jt, n_ks, frag_items(Cin), n_tiles);
-    return launch_status();
+    return homconv_launch(ctx, &P, nullptr, 1, Cin >= kPairedCin, HcSchedule{0, 0}, (hipStream_t)stream);
 }
 
 int ensei_homconv_valu(ensei_ctx *ctx, const uint64_t *ct_in, const uint32_t *w_hat, const uint32_t *r,

@@ -1,0 +1,290 @@
+// Batched plans: a stack of independent secure convolutions captured as one
+// HIP graph, with the HomConv of all layers in one persistent launch and its
+// tile schedule picked by timing candidates on the plan's own shapes.
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "ensei_internal.hpp"
+
+struct ensei_plan {
+    ensei_ctx *ctx = nullptr;
+    std::vector<ensei_layer> layers;
+    std::vector<uint32_t *> w_hat;
+    std::vector<int8_t *> w_pack;
+    std::vector<ensei::HcLayer> problems;
+    ensei::HcLayer *d_table = nullptr;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ensei::HcSchedule sched{0, 0};
+    ensei_schedule info{};
+};
+
+namespace ensei {
+namespace {
+
+struct DeviceGuard {
+    int prev = 0;
+    explicit DeviceGuard(int dev) {
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() { (void)hipSetDevice(prev); }
+};
+
+void release(ensei_plan *P) {
+    if (P->stream) (void)hipStreamSynchronize(P->stream);  // setup work may still read the buffers
+    if (P->exec) (void)hipGraphExecDestroy(P->exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    for (auto *q : P->w_hat) (void)hipFree(q);
+    for (auto *q : P->w_pack) (void)hipFree(q);
+    if (P->d_table) (void)hipFree(P->d_table);
+    if (P->stream) (void)hipStreamDestroy(P->stream);
+    delete P;
+}
+
+// Client side of every layer: x^ = NTT2D(x), ct_in = Enc(x^).
+int run_front(ensei_plan *P, hipStream_t st) {
+    for (const ensei_layer &l : P->layers) {
+        const int64_t F = (int64_t)l.H * l.W;
+        int rc = ensei_ntt2d(P->ctx, l.x, l.x_hat, l.batch * l.Cin, l.H, l.W, st);
+        if (!rc) rc = ensei_encrypt(P->ctx, l.x_hat, l.s, l.e, l.batch, l.Cin, F, l.n, l.seed_a, 0, l.ct_in, st);
+        if (rc) return rc;
+    }
+    return ENSEI_OK;
+}
+
+// Dec, the client's INTT2D and the server's share of every layer.
+int run_back(ensei_plan *P, hipStream_t st) {
+    for (const ensei_layer &l : P->layers) {
+        const int64_t F = (int64_t)l.H * l.W;
+        int rc = ensei_decrypt(P->ctx, l.ct_out, l.s, l.batch, l.Cout, F, l.n, l.m, st);
+        if (!rc) rc = ensei_intt2d(P->ctx, l.m, l.s_a, l.batch * l.Cout, l.H, l.W, st);
+        if (!rc) rc = ensei_server_share(P->ctx, l.r, l.s_b, l.batch * l.Cout, l.H, l.W, st);
+        if (rc) return rc;
+    }
+    return ENSEI_OK;
+}
+
+int run_homconv(ensei_plan *P, HcSchedule s, hipStream_t st) {
+    return homconv_launch(P->ctx, P->problems.data(), P->d_table, (int)P->problems.size(), true, s, st);
+}
+
+// Cache key: device, modulus and every layer's HomConv shape.
+std::string plan_key(const ensei_plan *P) {
+    hipDeviceProp_t prop;
+    char buf[160];
+    const char *arch = hipGetDeviceProperties(&prop, P->ctx->device) == hipSuccess ? prop.gcnArchName : "unknown";
+    snprintf(buf, sizeof buf, "%s/cus=%d/p=%u", arch, P->ctx->num_cus, P->ctx->p);
+    std::string key = buf;
+    for (const HcLayer &h : P->problems) {
+        snprintf(buf, sizeof buf, "|b%lld.f%lld.i%d.o%d.n%d", (long long)h.B, (long long)h.F, h.Cin, h.Cout, h.n);
+        key += buf;
+    }
+    for (char &c : key)
+        if (c == ' ') c = '_';
+    return key;
+}
+
+bool cache_lookup(const char *path, const std::string &key, HcSchedule *s) {
+    FILE *fh = fopen(path, "r");
+    if (!fh) return false;
+    char line[4096];
+    bool found = false;
+    while (fgets(line, sizeof line, fh)) {
+        char k[3900];
+        int blocks;
+        long long chunk;
+        if (sscanf(line, "%3899s %d %lld", k, &blocks, &chunk) == 3 && (key == k || strcmp(k, "*") == 0) &&
+            blocks > 0 && chunk >= 0) {
+            *s = HcSchedule{blocks, (int64_t)chunk};
+            found = true;  // the last entry for a key wins
+        }
+    }
+    fclose(fh);
+    return found;
+}
+
+void cache_append(const char *path, const std::string &key, HcSchedule s, double us) {
+    FILE *fh = fopen(path, "a");
+    if (!fh) return;
+    fprintf(fh, "%s %d %lld %.1f\n", key.c_str(), s.blocks, (long long)s.chunk, us);
+    fclose(fh);
+}
+
+// Mean time of the HomConv launch under schedule s (one warm-up, three timed).
+int time_schedule(ensei_plan *P, HcSchedule s, double *us) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return ENSEI_ERR_HIP;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return ENSEI_ERR_HIP;
+    }
+    int rc = run_homconv(P, s, P->stream);
+    const int reps = 3;
+    if (!rc && hipEventRecord(a, P->stream) != hipSuccess) rc = ENSEI_ERR_HIP;
+    for (int i = 0; i < reps && !rc; ++i) rc = run_homconv(P, s, P->stream);
+    if (!rc && hipEventRecord(b, P->stream) != hipSuccess) rc = ENSEI_ERR_HIP;
+    float ms = 0;
+    if (!rc && (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess))
+        rc = ENSEI_ERR_HIP;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *us = ms * 1e3 / reps;
+    return rc;
+}
+
+}  // namespace
+}  // namespace ensei
+
+using namespace ensei;
+
+extern "C" {
+
+int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const char *tune_cache,
+                      ensei_plan **out) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!out || !layers || nlayers < 1) return ENSEI_ERR_ARG;
+    if (nlayers > ENSEI_MAX_PLAN_LAYERS) return ENSEI_ERR_LIMIT;
+    *out = nullptr;
+    DeviceGuard guard(ctx->device);
+    ensei_plan *P = new ensei_plan;
+    P->ctx = ctx;
+    P->layers.assign(layers, layers + nlayers);
+    if (hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) != hipSuccess) {
+        P->stream = nullptr;
+        release(P);
+        return ENSEI_ERR_HIP;
+    }
+    // server setup: transformed and packed filters (paired layout for every
+    // layer, so that all of them run in the same persistent kernel)
+    int64_t tile0 = 0;
+    for (const ensei_layer &l : P->layers) {
+        if (l.H <= 0 || l.W <= 0 || l.Cin <= 0 || l.Cout <= 0 || l.batch <= 0) {
+            release(P);
+            return ENSEI_ERR_ARG;
+        }
+        const int64_t F = (int64_t)l.H * l.W;
+        uint32_t *wh = nullptr;
+        int8_t *wp = nullptr;
+        const size_t wpb = wpack_bytes_as(l.Cout, l.Cin, F, true);
+        if (hipMalloc(&wh, (size_t)l.Cout * l.Cin * F * 4) != hipSuccess) wh = nullptr;
+        if (wh && hipMalloc(&wp, wpb) != hipSuccess) wp = nullptr;
+        if (wh) P->w_hat.push_back(wh);
+        if (wp) P->w_pack.push_back(wp);
+        if (!wh || !wp) {
+            release(P);
+            return ENSEI_ERR_HIP;
+        }
+        rc = ensei_weight_prep(ctx, l.w, l.Cout, l.Cin, l.kh, l.kw, l.H, l.W, wh, P->stream);
+        if (!rc) rc = pack_weights_as(ctx, wh, l.Cout, l.Cin, F, true, wp, P->stream);
+        HcLayer h;
+        if (!rc) rc = homconv_problem(ctx, &h, l.ct_in, wp, l.r, l.batch, l.Cin, l.Cout, F, l.n, l.ct_out, wpb);
+        if (rc) {
+            release(P);
+            return rc;
+        }
+        h.n_items = frag_items(l.Cin, true);
+        h.tile0 = tile0;
+        tile0 += h.n_tiles;
+        P->problems.push_back(h);
+    }
+    const size_t tb = P->problems.size() * sizeof(HcLayer);
+    if (hipMalloc(&P->d_table, tb) != hipSuccess) {
+        P->d_table = nullptr;
+        release(P);
+        return ENSEI_ERR_HIP;
+    }
+    if (hipMemcpyAsync(P->d_table, P->problems.data(), tb, hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+        hipStreamSynchronize(P->stream) != hipSuccess) {
+        release(P);
+        return ENSEI_ERR_HIP;
+    }
+
+    // one eager pass: every argument check of the single calls, on real buffers
+    rc = run_front(P, P->stream);
+    if (!rc) rc = run_homconv(P, HcSchedule{0, 0}, P->stream);
+    if (!rc) rc = run_back(P, P->stream);
+    if (!rc && hipStreamSynchronize(P->stream) != hipSuccess) rc = ENSEI_ERR_HIP;
+    if (rc) {
+        release(P);
+        return rc;
+    }
+
+    // the HomConv tile schedule: cached, or the fastest candidate
+    const std::string key = plan_key(P);
+    HcSchedule best{ctx->num_cus, 0};
+    double best_us = 0;
+    if (tune_cache && cache_lookup(tune_cache, key, &best)) {
+        P->info.from_cache = 1;
+    } else {
+        const int64_t chunks[] = {0, 1, 4, 16, 64, 256};
+        bool first = true;
+        for (int64_t c : chunks) {
+            const HcSchedule s{ctx->num_cus, c};
+            double us = 0;
+            rc = time_schedule(P, s, &us);
+            if (rc) {
+                release(P);
+                return rc;
+            }
+            if (first || us < best_us) {
+                best = s;
+                best_us = us;
+                first = false;
+            }
+        }
+        if (tune_cache) cache_append(tune_cache, key, best, best_us);
+    }
+    P->sched = best;
+    P->info.blocks = best.blocks;
+    P->info.chunk = best.chunk;
+    P->info.homconv_us = best_us;
+
+    // capture the whole stack as one graph
+    if (hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        release(P);
+        return ENSEI_ERR_HIP;
+    }
+    rc = run_front(P, P->stream);
+    if (!rc) rc = run_homconv(P, P->sched, P->stream);
+    if (!rc) rc = run_back(P, P->stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(P->stream, &g);
+    P->graph = g;
+    if (!rc && (ec != hipSuccess || !g)) rc = ENSEI_ERR_HIP;
+    if (!rc && hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) != hipSuccess) {
+        P->exec = nullptr;
+        rc = ENSEI_ERR_HIP;
+    }
+    if (rc) {
+        release(P);
+        return rc;
+    }
+    *out = P;
+    return ENSEI_OK;
+}
+
+int ensei_plan_run(ensei_plan *plan, void *stream) {
+    if (!plan || !plan->exec) return ENSEI_ERR_ARG;
+    return hipGraphLaunch(plan->exec, (hipStream_t)stream) == hipSuccess ? ENSEI_OK : ENSEI_ERR_HIP;
+}
+
+int ensei_plan_schedule(const ensei_plan *plan, ensei_schedule *out) {
+    if (!plan || !out) return ENSEI_ERR_ARG;
+    *out = plan->info;
+    return ENSEI_OK;
+}
+
+int ensei_plan_destroy(ensei_plan *plan) {
+    if (!plan) return ENSEI_OK;
+    DeviceGuard guard(plan->ctx->device);
+    release(plan);
+    return ENSEI_OK;
+}
+
+}  // extern "C"

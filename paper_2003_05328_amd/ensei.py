@@ -51,7 +51,26 @@ SIGNATURES = {
     "ensei_homconv": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
     "ensei_homconv_valu": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
     "ensei_decrypt": (_i32, [_vp, _vp, _vp, _i64, _i32, _i64, _i32, _vp, _vp]),
+    "ensei_plan_create": (_i32, [_vp, _vp, _i32, C.c_char_p, C.POINTER(_vp)]),
+    "ensei_plan_run": (_i32, [_vp, _vp]),
+    "ensei_plan_schedule": (_i32, [_vp, _vp]),
+    "ensei_plan_destroy": (_i32, [_vp]),
 }
+
+
+class LayerDesc(C.Structure):
+    """``ensei_layer``: one layer of a batched plan."""
+
+    _fields_ = [(f, _i32) for f in ("H", "W", "Cin", "Cout", "kh", "kw", "n")] + [
+        ("batch", _i64),
+        ("seed_a", _u64),
+    ] + [(f, _vp) for f in ("w", "x", "s", "e", "r", "x_hat", "ct_in", "ct_out", "m", "s_a", "s_b")]
+
+
+class ScheduleDesc(C.Structure):
+    """``ensei_schedule``: the HomConv tile schedule a plan runs."""
+
+    _fields_ = [("blocks", _i32), ("from_cache", _i32), ("chunk", _i64), ("homconv_us", C.c_double)]
 
 
 class EnseiError(RuntimeError):
@@ -255,3 +274,73 @@ class Context:
         out = self._empty((B, F, n + 1, Cout), torch.uint64) if out is None else self._dev(out, "out", torch.uint64)
         self._call("ensei_homconv_valu", _ptr(ct_in), _ptr(w_hat), _ptr(r), B, Cin, Cout, F, n, _ptr(out))
         return out
+
+
+class Plan:
+    """A batched plan (``ensei_plan``): a stack of independent secure
+    convolutions captured as one HIP graph, HomConv of all layers in one
+    persistent launch with an autotuned tile schedule.
+
+    ``layers`` is a list of dicts with the shape (H, W, Cin, Cout, kh, kw, n,
+    seed_a) and the device tensors w, x, s, e, r (inputs) and x_hat, ct_in,
+    ct_out, m, s_a, s_b (written by every run); the plan keeps references to
+    them. ``Plan.buffers(ctx, shape, ...)`` allocates the outputs."""
+
+    _INPUTS = ("w", "x", "s", "e", "r")
+    _OUTPUTS = ("x_hat", "ct_in", "ct_out", "m", "s_a", "s_b")
+
+    def __init__(self, ctx: "Context", layers: list, tune_cache: str | None = None):
+        self.ctx = ctx
+        self.layers = layers
+        arr = (LayerDesc * len(layers))()
+        for d, l in zip(arr, layers):
+            B = l["x"].shape[0]
+            for k in ("H", "W", "Cin", "Cout", "kh", "kw", "n"):
+                setattr(d, k, int(l[k]))
+            d.batch = int(B)
+            d.seed_a = int(l["seed_a"]) & (2**64 - 1)
+            dtypes = {"w": torch.int32, "x": torch.uint32, "s": torch.int8, "e": torch.int32, "r": torch.uint32,
+                      "x_hat": torch.uint32, "ct_in": torch.uint64, "ct_out": torch.uint64, "m": torch.uint32,
+                      "s_a": torch.uint32, "s_b": torch.uint32}
+            for k in self._INPUTS + self._OUTPUTS:
+                setattr(d, k, _ptr(ctx._dev(l[k], k, dtypes[k])).value)
+        h = C.c_void_p()
+        cache = tune_cache.encode() if tune_cache else None
+        with torch.cuda.device(ctx.device):
+            _check(lib().ensei_plan_create(ctx._h, arr, len(layers), cache, C.byref(h)), "ensei_plan_create")
+        self._h = h
+
+    @staticmethod
+    def buffers(ctx: "Context", H, W, Cin, Cout, n, batch) -> dict:
+        """Device outputs of one layer of a plan."""
+        F = H * W
+        return {
+            "x_hat": ctx._empty((batch, Cin, F), torch.uint32),
+            "ct_in": ctx._empty((batch, F, n + 1, Cin), torch.uint64),
+            "ct_out": ctx._empty((batch, F, n + 1, Cout), torch.uint64),
+            "m": ctx._empty((batch, Cout, F), torch.uint32),
+            "s_a": ctx._empty((batch, Cout, H, W), torch.uint32),
+            "s_b": ctx._empty((batch, Cout, H, W), torch.uint32),
+        }
+
+    def run(self):
+        """Enqueue one run of the captured graph on the current stream."""
+        with torch.cuda.device(self.ctx.device):
+            _check(lib().ensei_plan_run(self._h, self.ctx._stream()), "ensei_plan_run")
+
+    def schedule(self) -> dict:
+        sd = ScheduleDesc()
+        _check(lib().ensei_plan_schedule(self._h, C.byref(sd)), "ensei_plan_schedule")
+        return {"blocks": sd.blocks, "chunk": sd.chunk, "homconv_us": sd.homconv_us, "from_cache": bool(sd.from_cache)}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            torch.cuda.synchronize(self.ctx.device)
+            lib().ensei_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

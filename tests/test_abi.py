@@ -52,7 +52,7 @@ def test_status_strings_and_host_only_calls(lib):
         s = lib.ensei_status_str(code)
         assert isinstance(s, bytes) and len(s) > 0
     assert lib.ensei_status_str(12345) == b"unknown status"
-    # packed-weight size is pure host arithmetic: F * ceil(Cin/64)*4 * roundup(Cout,16) * 48
+    # packed-weight size is pure host arithmetic:
     # F * ceil(Cin/64) * ceil(Cout/64) * U * 16, U = 768 (Cin >= 48) or 256 * ceil(Cin/16)
     assert lib.ensei_wpack_bytes(64, 64, 1024) == 1024 * 1 * 1 * 768 * 16
     assert lib.ensei_wpack_bytes(8, 3, 256) == 256 * 1 * 1 * 256 * 16
@@ -73,6 +73,18 @@ def test_entry_points_reject_null_context(lib):
     assert lib.ensei_decrypt(None, None, None, 1, 1, 1, 1, None, None) < 0
     h = ctypes.c_void_p()
     assert lib.ensei_ctx_create(None, 65537, 0) == -1  # ENSEI_ERR_ARG
+    # batched plans
+    assert lib.ensei_plan_create(None, None, 1, None, ctypes.byref(h)) < 0
+    assert lib.ensei_plan_run(None, None) == -1
+    assert lib.ensei_plan_schedule(None, None) == -1
+    assert lib.ensei_plan_destroy(None) == 0
+
+
+def test_plan_structs_match_the_header():
+    # ensei_layer: 7 ints, int64 batch, uint64 seed_a, 11 pointers
+    assert ctypes.sizeof(ensei.LayerDesc) == 7 * 4 + 4 + 8 + 8 + 11 * 8
+    assert ensei.LayerDesc.batch.offset == 32 and ensei.LayerDesc.w.offset == 48
+    assert ctypes.sizeof(ensei.ScheduleDesc) == 24
 
 
 def test_modulus_rejected_before_device_use(lib):

@@ -1,0 +1,132 @@
+"""GPU parity of batched plans (ensei_plan_*): a stack of uneven layers in one
+captured graph with one persistent HomConv launch must give, bit for bit, what
+the single calls give, and the oracle's HomConv and convolution identity."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2003_05328_amd import synth
+from paper_2003_05328_amd.ensei import Context, Plan
+from paper_2003_05328_amd.synth import LayerShape
+from tests.gpu_helpers import P, dev, host
+
+pytestmark = pytest.mark.gpu
+
+# uneven shapes: narrow input (folded-size Cin run through the paired layout),
+# several K steps, several row tiles, a ragged column tile
+STACK = [
+    LayerShape(H=8, W=8, Cin=3, Cout=16, kh=3, kw=3, n=70, B=2),
+    LayerShape(H=4, W=8, Cin=130, Cout=70, kh=3, kw=3, n=64, B=1),
+    LayerShape(H=16, W=16, Cin=64, Cout=64, kh=3, kw=3, n=100, B=2, hidden=True),
+]
+STACK_ODD = [
+    LayerShape(H=8, W=4, Cin=5, Cout=17, kh=2, kw=3, n=33, B=1),
+    LayerShape(H=4, W=4, Cin=48, Cout=9, kh=3, kw=3, n=129, B=3),
+]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = Context(P, 0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    o = oracle.default()
+    o.set_threads(16)
+    return o
+
+
+def _layer(ctx, S, seed):
+    inp = synth.generate(S, P, seed)
+    l = {"H": S.H, "W": S.W, "Cin": S.Cin, "Cout": S.Cout, "kh": S.kh, "kw": S.kw, "n": S.n, "seed_a": inp.seed_a,
+         "w": dev(inp.w), "x": dev(inp.x), "s": dev(inp.s), "e": dev(inp.e.reshape(S.B, S.Cin, S.F)),
+         "r": dev(inp.r.reshape(S.B, S.Cout, S.F))}
+    l.update(Plan.buffers(ctx, S.H, S.W, S.Cin, S.Cout, S.n, S.B))
+    return inp, l
+
+
+def _single_calls(ctx, S, l):
+    """The same layer through the single entry points."""
+    x_hat = ctx.ntt2d(l["x"]).view(S.B, S.Cin, S.F)
+    ct_in = ctx.encrypt(x_hat, l["s"], l["e"], l["seed_a"])
+    pack = ctx.pack_weights(ctx.weight_prep(l["w"], S.H, S.W))
+    ct_out = ctx.homconv(ct_in, pack, l["r"], S.Cout)
+    m = ctx.decrypt(ct_out, l["s"])
+    s_a = ctx.intt2d(m.view(S.B * S.Cout, S.F), S.H, S.W)
+    s_b = ctx.server_share(l["r"].view(S.B * S.Cout, S.F), S.H, S.W)
+    return {"x_hat": x_hat, "ct_in": ct_in, "ct_out": ct_out, "m": m, "s_a": s_a, "s_b": s_b}
+
+
+def _check_layer(orc, S, inp, l, ref):
+    for k in ("x_hat", "ct_in", "ct_out", "m"):
+        assert np.array_equal(host(l[k]).reshape(-1), host(ref[k]).reshape(-1)), k
+    for k in ("s_a", "s_b"):
+        assert np.array_equal(host(l[k]).reshape(-1), host(ref[k]).reshape(-1)), k
+    # the oracle's HomConv of the plan's own input ciphertexts, and the shares' identity
+    ct_in = host(l["ct_in"])
+    w_hat = orc.weight_prep(inp.w, S.H, S.W, P)
+    r = inp.r.reshape(S.B, S.Cout, S.F)
+    assert np.array_equal(host(l["ct_out"]), orc.homconv(ct_in, w_hat, r, P))
+    conv = orc.cyclic_conv(inp.x, inp.w, P)
+    shares = (host(l["s_a"]).astype(np.int64) + host(l["s_b"])) % P
+    assert np.array_equal(shares.reshape(conv.shape), conv)
+
+
+@pytest.mark.parametrize("stack", [STACK, STACK_ODD], ids=["even_cout", "odd_cout"])
+def test_plan_matches_single_calls_and_oracle(ctx, orc, tmp_path, stack):
+    layers = [_layer(ctx, S, 100 + i) for i, S in enumerate(stack)]
+    plan = Plan(ctx, [l for _, l in layers], tune_cache=str(tmp_path / "tune.txt"))
+    sch = plan.schedule()
+    assert sch["blocks"] > 0 and sch["chunk"] >= 0 and not sch["from_cache"]
+    for l in [l for _, l in layers]:
+        for k in Plan._OUTPUTS:
+            l[k].zero_()
+    plan.run()
+    torch.cuda.synchronize()
+    for S, (inp, l) in zip(stack, layers):
+        _check_layer(orc, S, inp, l, _single_calls(ctx, S, l))
+    # same shapes again: the schedule now comes from the cache
+    plan2 = Plan(ctx, [l for _, l in layers], tune_cache=str(tmp_path / "tune.txt"))
+    assert plan2.schedule()["from_cache"] and plan2.schedule()["chunk"] == sch["chunk"]
+    plan2.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("chunk", [0, 1, 3, 64])
+def test_plan_every_schedule_is_exact(ctx, orc, tmp_path, chunk):
+    cache = tmp_path / "pin.txt"
+    cache.write_text(f"* {torch.cuda.get_device_properties(0).multi_processor_count} {chunk}\n")
+    layers = [_layer(ctx, S, 200 + i) for i, S in enumerate(STACK)]
+    plan = Plan(ctx, [l for _, l in layers], tune_cache=str(cache))
+    assert plan.schedule()["chunk"] == chunk and plan.schedule()["from_cache"]
+    plan.run()
+    torch.cuda.synchronize()
+    for S, (inp, l) in zip(STACK, layers):
+        _check_layer(orc, S, inp, l, _single_calls(ctx, S, l))
+    plan.close()
+
+
+def test_plan_replays_see_new_inputs(ctx, orc, tmp_path):
+    """Graph replays with eager work and new inputs in between: every replay
+    matches the single calls on that replay's inputs."""
+    layers = [_layer(ctx, S, 300 + i) for i, S in enumerate(STACK)]
+    plan = Plan(ctx, [l for _, l in layers], tune_cache=str(tmp_path / "t.txt"))
+    g = np.random.default_rng(5)
+    for rep in range(3):
+        for S, (inp, l) in zip(STACK, layers):
+            # new image, errors and masks written in place (the graph holds the pointers)
+            l["x"].copy_(dev(g.integers(0, P, size=tuple(l["x"].shape)).astype(np.uint32)))
+            l["r"].copy_(dev(g.integers(0, P, size=tuple(l["r"].shape)).astype(np.uint32)))
+            l["e"].copy_(dev(g.integers(-9, 10, size=tuple(l["e"].shape)).astype(np.int32)))
+        torch.cuda.synchronize()
+        plan.run()
+        torch.cuda.synchronize()
+        for S, (inp, l) in zip(STACK, layers):
+            ref = _single_calls(ctx, S, l)
+            for k in Plan._OUTPUTS:
+                assert np.array_equal(host(l[k]).reshape(-1), host(ref[k]).reshape(-1)), (rep, k)
+    plan.close()
