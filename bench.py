@@ -46,6 +46,14 @@ def parse():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target host time of the CPU-oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the NTT2D throughput and the batched conv-stack comparison")
+    ap.add_argument("--stack-reps", type=int, default=5)
+    ap.add_argument("--serve", action="store_true",
+                    help="only the serving sweep (Poisson arrivals of mixed-shape requests), one JSON line")
+    ap.add_argument("--serve-rates", default="250,500,1000,2000", help="arrival rates, requests/s")
+    ap.add_argument("--serve-requests", type=int, default=1000, help="requests per rate")
+    ap.add_argument("--serve-budget-gb", type=float, default=160.0)
     ap.add_argument("--probe-copy", action="store_true",
                     help="run only a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     return ap.parse_args()
@@ -85,6 +93,271 @@ def traffic_entry(launch_bytes: int):
         return None
 
 
+def ntt_throughput(ctx, S, reps: int = 20):
+    """NTT2D on the weight-preparation batch of the layer (Cout*Cin grids): points/s
+    and algorithmic HBM rate (4 bytes read + 4 written per point)."""
+    import torch
+
+    batch = S.Cout * S.Cin
+    x = torch.randint(0, 65537, (batch, S.H, S.W), dtype=torch.int64, device="cuda:0").to(torch.uint32)
+    out = torch.empty((batch, S.H * S.W), dtype=torch.uint32, device="cuda:0")
+    for _ in range(3):
+        ctx.ntt2d(x, out=out)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        ctx.ntt2d(x, out=out)
+    ev[1].record()
+    torch.cuda.synchronize()
+    us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+    pts = batch * S.H * S.W
+    gbs = 8 * pts / (us * 1e-6) / 1e9
+    return {"grids": batch, "grid": f"{S.H}x{S.W}", "avg_us": us, "points_per_s": pts / (us * 1e-6),
+            "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+            "bytes_per_point": 8}
+
+
+def stack_batched(ctx, reps: int, seed: int):
+    """The seven-layer conv stack (batch of 8 images) as one batched plan (one
+    graph, one persistent HomConv launch, tuned schedule) against the same
+    layers run one after another through the single calls; both bit-exact."""
+    import numpy as np
+    import torch
+
+    from paper_2003_05328_amd import configs, synth
+    from paper_2003_05328_amd.ensei import Plan
+
+    shapes = configs.stack_shapes(B=8)
+    P = configs.P
+    layers, packs = [], []
+    for i, S in enumerate(shapes):
+        inp = synth.generate(S, P, seed + 1000 + i)
+        d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+        l = {"H": S.H, "W": S.W, "Cin": S.Cin, "Cout": S.Cout, "kh": S.kh, "kw": S.kw, "n": S.n,
+             "seed_a": inp.seed_a, "w": d(inp.w), "x": d(inp.x), "s": d(inp.s), "e": d(inp.e), "r": d(inp.r)}
+        l.update(Plan.buffers(ctx, S.H, S.W, S.Cin, S.Cout, S.n, S.B))
+        layers.append(l)
+    t0 = time.perf_counter()
+    plan = Plan(ctx, layers)
+    create_s = time.perf_counter() - t0
+    sched = plan.schedule()
+    # one-at-a-time baseline: the same kernels, single calls, filters prepared beforehand
+    seq = []
+    for S, l in zip(shapes, layers):
+        pack = ctx.pack_weights(ctx.weight_prep(l["w"], S.H, S.W))
+        seq.append({k: torch.empty_like(l[k]) for k in ("x_hat", "ct_in", "ct_out", "m", "s_a", "s_b")})
+        packs.append(pack)
+
+    def sequential():
+        for S, l, o, pk in zip(shapes, layers, seq, packs):
+            ctx.ntt2d(l["x"], out=o["x_hat"].view(S.B * S.Cin, S.F))
+            ctx.encrypt(o["x_hat"], l["s"], l["e"], l["seed_a"], out=o["ct_in"])
+            ctx.homconv(o["ct_in"], pk, l["r"], S.Cout, out=o["ct_out"])
+            ctx.decrypt(o["ct_out"], l["s"], out=o["m"])
+            ctx.intt2d(o["m"].view(S.B * S.Cout, S.F), S.H, S.W, out=o["s_a"].view(S.B * S.Cout, S.F))
+            ctx.server_share(l["r"].view(S.B * S.Cout, S.F), S.H, S.W, out=o["s_b"].view(S.B * S.Cout, S.F))
+
+    def timed(fn):
+        fn()
+        ts = []
+        for _ in range(reps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            ev[0].record()
+            fn()
+            ev[1].record()
+            torch.cuda.synchronize()
+            ts.append(ev[0].elapsed_time(ev[1]))
+        return float(np.median(ts))
+
+    plan_ms = timed(plan.run)
+    seq_ms = timed(sequential)
+    same = all(torch.equal(l[k], o[k]) for l, o in zip(layers, seq) for k in ("ct_in", "ct_out", "m", "s_a", "s_b"))
+    macs = sum(S.B * S.Cout * S.Cin * S.F for S in shapes)
+    hc_bytes = sum(8 * (S.n + 1) * S.F * S.B * (S.Cin + S.Cout) for S in shapes)
+    plan.close()
+    return {
+        "workload": "stack8: 7 layers (3,64,32),(64,64,32),(64,128,16),(128,128,16),(128,256,8),(256,256,8),"
+                    "(256,512,4), 3x3, n=1024, batch 8",
+        "ct_macs": macs,
+        "batched_ms": plan_ms,
+        "sequential_ms": seq_ms,
+        "batched_ct_mac_per_s": macs / (plan_ms * 1e-3),
+        "sequential_ct_mac_per_s": macs / (seq_ms * 1e-3),
+        "speedup": seq_ms / plan_ms,
+        "homconv_schedule": sched,
+        "homconv_ct_bytes": hc_bytes,
+        "plan_create_s": create_s,
+        "bit_exact_vs_sequential": bool(same),
+    }
+
+
+def serving(ctx, rates, n_req: int, budget_gb: float, seed: int, nstreams: int = 4, max_batch: int = 16):
+    """Secure-convolution requests of mixed shapes (one image each: pick one of
+    the four workload families uniformly, then one of its layers) arriving as
+    a Poisson process, served with continuous batching under a ciphertext
+    budget; against the same requests run one at a time. Every result is
+    compared with the same request computed alone."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2003_05328_amd import configs, synth
+    from paper_2003_05328_amd.ensei import Server
+
+    P = configs.P
+    W = configs.WORKLOADS
+    families = [
+        [W["conv16x16_c3to8_k3_n512"]],
+        [W["conv32x32_c64to64_k3_n1024"], W["conv32x32_c64to64_k3_n1024_hidden"]],
+        [S for k, S in W.items() if k.startswith("stack8_L")],
+        [W["conv64x64(56)_c64to64_k3_n1024"], W["conv128x128_c3to64_k7_n1024"]],
+    ]
+    budget = int(budget_gb * (1 << 30))
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+    def setup(server):
+        fams = []
+        for fi, fam in enumerate(families):
+            lst = []
+            for li, S0 in enumerate(fam):
+                S = synth.LayerShape(S0.H, S0.W, S0.Cin, S0.Cout, S0.kh, S0.kw, S0.n, 1, S0.img_h, S0.img_w,
+                                     S0.hidden, S0.binary)
+                base = synth.generate(S, P, seed + 100 * fi + li)
+                w = d(base.w)
+                sid = server.add_shape(S.H, S.W, S.Cin, S.Cout, S.kh, S.kw, S.n, w)
+                sets = []
+                for j in range(2):
+                    inp = synth.generate(S, P, seed + 10000 + 100 * fi + 10 * li + j)
+                    sets.append({"x": d(inp.x[0]), "s": d(inp.s), "e": d(inp.e[0]), "r": d(inp.r[0]),
+                                 "seed_a": inp.seed_a})
+                ring = [(torch.empty((S.Cout, S.H, S.W), dtype=torch.uint32, device="cuda:0"),
+                         torch.empty((S.Cout, S.H, S.W), dtype=torch.uint32, device="cuda:0")) for _ in range(48)]
+                lst.append({"S": S, "sid": sid, "sets": sets, "ring": ring, "free": list(range(48)), "ref": [None, None]})
+            fams.append(lst)
+        return fams
+
+    def draw(g, n):
+        out = []
+        for _ in range(n):
+            fi = int(g.integers(len(families)))
+            li = int(g.integers(len(families[fi])))
+            out.append((fi, li, int(g.integers(2))))
+        return out
+
+    server = Server(ctx, budget, nstreams=nstreams, max_batch=max_batch)
+    fams = setup(server)
+    # references: each input set alone, through the server one at a time
+    for lst in fams:
+        for L in lst:
+            for j, io in enumerate(L["sets"]):
+                s_a, s_b = torch.empty_like(L["ring"][0][0]), torch.empty_like(L["ring"][0][1])
+                torch.cuda.synchronize()
+                t = server.submit(L["sid"], io["x"], io["s"], io["e"], io["r"], io["seed_a"], s_a, s_b)
+                server.wait(t)
+                server.forget(t)
+                L["ref"][j] = (s_a, s_b)
+    torch.cuda.synchronize()
+
+    def run(plan, rate):
+        """plan: list of (family, layer, set); rate None = closed loop, one at a time."""
+        lock = threading.Condition()
+        tickets = []
+        done_flag = [False]
+        ok = [True]
+        times = []
+
+        def collector():
+            k = 0
+            while True:
+                with lock:
+                    while k >= len(tickets) and not done_flag[0]:
+                        lock.wait()
+                    if k >= len(tickets):
+                        return
+                    t, L, j, slot = tickets[k]
+                server.wait(t)
+                info = server.poll(t)
+                s_a, s_b = L["ring"][slot]
+                same = torch.equal(s_a, L["ref"][j][0]) and torch.equal(s_b, L["ref"][j][1])
+                server.forget(t)
+                with lock:
+                    ok[0] = ok[0] and same and info["state"] == "done"
+                    times.append((info["t_submit"], info["t_start"], info["t_done"]))
+                    L["free"].append(slot)
+                    lock.notify_all()
+                k += 1
+
+        th = threading.Thread(target=collector)
+        th.start()
+        g = np.random.default_rng(seed + 7)
+        gaps = g.exponential(1.0 / rate, size=len(plan)) if rate else np.zeros(len(plan))
+        t0 = time.perf_counter()
+        due = 0.0
+        for (fi, li, j), gap in zip(plan, gaps):
+            L = fams[fi][li]
+            if rate:
+                due += gap
+                while time.perf_counter() - t0 < due:
+                    pass
+            with lock:
+                while not L["free"]:
+                    lock.wait()
+                slot = L["free"].pop()
+            io = L["sets"][j]
+            s_a, s_b = L["ring"][slot]
+            t = server.submit(L["sid"], io["x"], io["s"], io["e"], io["r"], io["seed_a"], s_a, s_b)
+            with lock:
+                tickets.append((t, L, j, slot))
+                lock.notify_all()
+                if not rate:  # one at a time: the next request waits until this one is done
+                    while len(times) < len(tickets):
+                        lock.wait()
+        with lock:
+            done_flag[0] = True
+            lock.notify_all()
+        th.join()
+        ts = np.array(times)
+        lat = (ts[:, 2] - ts[:, 0]) * 1e3
+        span = ts[:, 2].max() - ts[:, 0].min()
+        return {"requests": len(plan), "throughput_req_s": len(plan) / span, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                "queue_p99_ms": float(np.percentile((ts[:, 1] - ts[:, 0]) * 1e3, 99)), "bit_exact": bool(ok[0])}
+
+    g = np.random.default_rng(seed)
+    plan = draw(g, n_req)
+    sweep = []
+    for rate in rates:
+        r = run(plan, rate)
+        r["offered_req_s"] = rate
+        sweep.append(r)
+    st = server.stats()
+    server.close()
+    # one at a time on the same GPU: a server with one stream and batches of one, closed loop
+    seq_server = Server(ctx, budget, nstreams=1, max_batch=1)
+    server = seq_server
+    fams_seq = setup(seq_server)
+    for lst, lst_ref in zip(fams_seq, fams):
+        for L, Lr in zip(lst, lst_ref):
+            L["ref"] = Lr["ref"]
+    fams = fams_seq
+    seq = run(plan, None)
+    seq_server.close()
+    return {
+        "workload": "requests drawn per family uniformly from {16x16 3->8 n=512}, {32x32 64->64 n=1024 pixel, "
+                    "hidden}, {the 7 stack layers}, {64x64(56) 64->64, 128x128 3->64 7x7}; one image each, "
+                    "fresh inputs; Poisson arrivals",
+        "budget_gb": budget_gb,
+        "nstreams": nstreams,
+        "max_batch": max_batch,
+        "sweep": sweep,
+        "sequential": seq,
+        "peak_budget_used_gb": st["peak_used_bytes"] / (1 << 30),
+        "batches": st["batches"],
+        "bit_exact": all(r["bit_exact"] for r in sweep) and seq["bit_exact"],
+    }
+
+
 def cpu_baseline(inp, target_s: float):
     """The CPU oracle's whole step (same layer, same inputs) on the host cores."""
     import oracle
@@ -114,6 +387,20 @@ def main():
     args = parse()
     if args.probe_copy:
         probe_copy()
+        return
+    if args.serve:
+        from paper_2003_05328_amd.ensei import Context
+
+        ctx = Context(65537, 0)
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        res = serving(ctx, rates, args.serve_requests, args.serve_budget_gb, args.seed)
+        best = max(res["sweep"], key=lambda r: r["throughput_req_s"])
+        print(json.dumps({"metric": "served secure-conv requests/s (mixed shapes, continuous batching)",
+                          "value": best["throughput_req_s"], "unit": "req/s", "n_gpus": 1,
+                          "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+                          "config": {"workload": "serving"}, "serving": res}), flush=True)
+        if not res["bit_exact"]:
+            sys.exit(3)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
@@ -259,10 +546,20 @@ def main():
         "word_mac_per_s_homconv": macs * (S.n + 1) / (hc_ms * 1e-3),
         "verified": ok and conv_ok,
     }
+    if not args.no_extras:
+        result["ntt2d"] = ntt_throughput(ctx, S)
+        del ct_in, ct_out
+        torch.cuda.empty_cache()
+        result["batched"] = stack_batched(ctx, args.stack_reps, args.seed)
+        result["verified"] = result["verified"] and result["batched"]["bit_exact_vs_sequential"]
+        torch.cuda.empty_cache()
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        result["serving"] = serving(ctx, rates, args.serve_requests, args.serve_budget_gb, args.seed)
+        result["verified"] = result["verified"] and result["serving"]["bit_exact"]
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(inp, args.cpu_seconds)
     print(json.dumps(result), flush=True)
-    if not (ok and conv_ok):
+    if not result["verified"]:
         sys.exit(3)
 
 

@@ -48,7 +48,8 @@ enum ensei_status {
     ENSEI_ERR_OVERLAP = -5, /* output range overlaps an input range */
     ENSEI_ERR_LIMIT = -6,   /* size beyond the supported range (see each call) */
     ENSEI_ERR_DEVICE = -7,  /* current HIP device is not the context's device */
-    ENSEI_ERR_HIP = -8      /* HIP runtime error (allocation at create, launch failure) */
+    ENSEI_ERR_HIP = -8,     /* HIP runtime error (allocation at create, launch failure) */
+    ENSEI_ERR_TIMEOUT = -9  /* a wait ended before the request finished (serving) */
 };
 
 /* Largest supported sizes. */
@@ -276,6 +277,91 @@ int ensei_plan_schedule(const ensei_plan *plan, ensei_schedule *out);
 /* Frees the plan's device memory and graph; NULL is accepted. Wait for the
  * plan's runs to finish first. */
 int ensei_plan_destroy(ensei_plan *plan);
+
+/* ------------------------------------------------------------ serving --
+ * A server runs secure-convolution requests (the start round of Fig. 2 for
+ * one image) of mixed shapes with continuous batching. A worker thread
+ * admits queued requests in arrival order while their ciphertext state fits
+ * the free part of a device budget, groups them into a batch and enqueues it
+ * on one of `nstreams` streams (default priority): per request NTT2D and Enc,
+ * one persistent HomConv launch over the tiles of every request of the batch,
+ * then per request Dec, INTT2D and the server's share. Batches on different
+ * streams overlap on the device; when a batch completes, its memory returns
+ * to the budget and waiting requests are admitted. A request's ciphertexts
+ * (x^, ct_in, ct_out, m: ensei_request_bytes) live in the server's budget
+ * from admission to completion and never leave the device. Results are
+ * bit-identical to the single calls on the same inputs, alone or in a mix.
+ *
+ * The server's filters of each shape are prepared once by
+ * ensei_server_add_shape. A request's inputs and outputs are the caller's
+ * device buffers: x [Cin][H][W] residues < p, s [n] ternary, e [Cin][F]
+ * int32, r [Cout][F] masks < p, and the written shares s_a, s_b
+ * [Cout][H][W]; inputs must be complete when the request is submitted and
+ * every buffer must stay valid until the request is done. Word j of
+ * ciphertext (c, f) is keyed by seed_a and q = f*Cin + c, as ensei_encrypt
+ * with one image and ct_index0 = 0.
+ *
+ * The server allocates its budget, launch tables and per-shape filters on the
+ * context's device (at create / add_shape; nothing while serving). All calls
+ * are thread-safe. Times are seconds since the server was created. */
+typedef struct ensei_server ensei_server;
+
+typedef struct ensei_shape {
+    int H, W, Cin, Cout, kh, kw, n;
+} ensei_shape;
+
+typedef struct ensei_request {
+    const uint32_t *x;
+    const int8_t *s;
+    const int32_t *e;
+    const uint32_t *r;
+    uint64_t seed_a;
+    uint32_t *s_a;
+    uint32_t *s_b;
+} ensei_request;
+
+/* state: 0 queued, 1 running, 2 done, 3 failed (status holds the error). */
+typedef struct ensei_request_info {
+    int state;
+    int status;
+    double t_submit, t_start, t_done;
+} ensei_request_info;
+
+typedef struct ensei_server_info {
+    uint64_t budget_bytes, used_bytes, peak_used_bytes;
+    uint64_t queued, inflight_batches, completed, failed, batches;
+} ensei_server_info;
+
+/* Device bytes of one request of this shape inside the budget (0 if invalid). */
+size_t ensei_request_bytes(const ensei_shape *shape);
+
+/* budget_bytes of ciphertext state; 1 <= nstreams <= 8; 1 <= max_batch <= 256
+ * requests per batch. Starts the worker thread. */
+int ensei_server_create(ensei_ctx *ctx, size_t budget_bytes, int nstreams, int max_batch, ensei_server **out);
+
+/* Registers a shape with the server's filters w [Cout][Cin][kh][kw] int32
+ * (read once, synchronously). ENSEI_ERR_LIMIT if one request of the shape
+ * does not fit the budget; the single calls' shape errors otherwise. */
+int ensei_server_add_shape(ensei_server *server, const ensei_shape *shape, const int32_t *w, int *shape_id);
+
+/* Queues one request; returns at once with its ticket. */
+int ensei_server_submit(ensei_server *server, int shape_id, const ensei_request *req, uint64_t *ticket);
+
+/* The request's state and times (ENSEI_ERR_ARG for an unknown ticket). */
+int ensei_server_poll(ensei_server *server, uint64_t ticket, ensei_request_info *info);
+
+/* Blocks until the request is done (timeout_ms < 0: no limit); returns its
+ * status, or ENSEI_ERR_TIMEOUT. */
+int ensei_server_wait(ensei_server *server, uint64_t ticket, int timeout_ms);
+
+/* Drops a finished request's record (ENSEI_ERR_ARG if unknown or not done). */
+int ensei_server_forget(ensei_server *server, uint64_t ticket);
+
+/* Budget use (now and peak), queue length, batches in flight and counts. */
+int ensei_server_stats(ensei_server *server, ensei_server_info *out);
+
+/* Finishes every queued and running request, then frees the server. */
+int ensei_server_destroy(ensei_server *server);
 
 #ifdef __cplusplus
 }

@@ -84,6 +84,7 @@ const char *ensei_status_str(int s) {
         case ENSEI_ERR_LIMIT: return "size beyond the supported range";
         case ENSEI_ERR_DEVICE: return "current HIP device is not the context's device";
         case ENSEI_ERR_HIP: return "HIP runtime error";
+        case ENSEI_ERR_TIMEOUT: return "timed out before the request finished";
         default: return "unknown status";
     }
 }

@@ -89,6 +89,8 @@ inline int frag_items(int Cin, bool paired) { return paired ? 768 : 256 * ((Cin 
 size_t wpack_bytes_as(int Cout, int Cin, int64_t F, bool paired);
 int pack_weights_as(const ensei_ctx *ctx, const uint32_t *w_hat, int Cout, int Cin, int64_t F, bool paired,
                     int8_t *w_pack, hipStream_t stream);
+// HomConv's size limits alone (ENSEI_ERR_ARG / ENSEI_ERR_LIMIT).
+int homconv_sizes(int64_t batch, int Cin, int Cout, int64_t F, int n);
 // Checks one problem's sizes and fills its derived fields (tile0 = 0).
 int homconv_problem(const ensei_ctx *ctx, HcLayer *P, const uint64_t *ct_in, const int8_t *w_pack, const uint32_t *r,
                     int64_t B, int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, size_t wbytes);

@@ -566,16 +566,22 @@ __global__ __launch_bounds__(256) void homconv_valu_kernel(const uint64_t *__res
     }
 }
 
-static int check_homconv(const ensei_ctx *ctx, const void *ct_in, const void *w, const void *r, int64_t batch,
-                         int Cin, int Cout, int64_t F, int n, const void *ct_out, size_t wbytes) {
-    int st = check_ctx(ctx);
-    if (st) return st;
-    if (!ct_in || !w || !r || !ct_out || batch <= 0 || Cin <= 0 || Cout <= 0 || F <= 0 || n <= 0)
-        return ENSEI_ERR_ARG;
+int homconv_sizes(int64_t batch, int Cin, int Cout, int64_t F, int n) {
+    if (batch <= 0 || Cin <= 0 || Cout <= 0 || F <= 0 || n <= 0) return ENSEI_ERR_ARG;
     if (Cin > ENSEI_MAX_CIN || Cout > ENSEI_MAX_COUT || n > ENSEI_MAX_LWE_N || F > (1 << 20)) return ENSEI_ERR_LIMIT;
     // one (b, f) block of either side is addressed with 32-bit byte offsets
     if ((int64_t)(n + 1) * (Cin > Cout ? Cin : Cout) * 8 > 0x7fffffff) return ENSEI_ERR_LIMIT;
     if ((int64_t)Cout * F * 4 > 0x7fffffff) return ENSEI_ERR_LIMIT;  // one image's masks, likewise
+    return ENSEI_OK;
+}
+
+static int check_homconv(const ensei_ctx *ctx, const void *ct_in, const void *w, const void *r, int64_t batch,
+                         int Cin, int Cout, int64_t F, int n, const void *ct_out, size_t wbytes) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!ct_in || !w || !r || !ct_out) return ENSEI_ERR_ARG;
+    st = homconv_sizes(batch, Cin, Cout, F, n);
+    if (st) return st;
     if (((uintptr_t)ct_in & 7) || ((uintptr_t)ct_out & 7) || ((uintptr_t)r & 3)) return ENSEI_ERR_ALIGN;
     const size_t inb = (size_t)batch * Cin * F * (n + 1) * 8, outb = (size_t)batch * Cout * F * (n + 1) * 8;
     if (overlaps(ct_out, outb, ct_in, inb) || overlaps(ct_out, outb, w, wbytes) ||

@@ -3,13 +3,18 @@
 //
 // Layout: one workgroup transforms T whole channels. The channels are staged
 // from HBM into LDS with 16-byte loads (rows padded to W+1 words so that
-// both row and column accesses are bank-conflict free); one thread then owns
-// one row, transforms it in registers (radix-2 decimation in frequency, fully
-// unrolled, twiddles read as uniform scalars), and writes it back in natural
-// order; after a barrier one thread owns one column, transforms it, applies
-// the inverse's (HW)^-1 if needed, and stores it straight to HBM, lanes
-// covering consecutive columns so the stores coalesce. HBM traffic is the
-// algorithmic 4 B read + 4 B written per point.
+// both row and column accesses are bank-conflict free). Every row is then
+// transformed by two threads: the first radix-2 decimation-in-frequency stage
+// splits a length-L line into two independent length-L/2 lines (the sums,
+// whose transform gives the even outputs, and the twiddled differences, which
+// give the odd ones), so thread h = 0 / 1 computes its half of that stage
+// from the line in LDS and the rest of its half-length transform in registers
+// (fully unrolled, twiddles as uniform scalars), writing outputs 2k + h back
+// in natural order. After a barrier the columns are done the same way, the
+// inverse's (HW)^-1 applied, and stored straight to HBM with lanes covering
+// consecutive columns so the stores coalesce. h is uniform per wave whenever
+// a half-phase spans whole waves. HBM traffic is the algorithmic 4 B read +
+// 4 B written per point.
 #include "ensei_internal.hpp"
 
 namespace ensei {
@@ -52,13 +57,40 @@ __device__ __forceinline__ void dif_line(uint32_t (&v)[L], const uint2 *__restri
     }
 }
 
+// Half h of a length-L DIF transform of the line x[0], x[st], ..., x[(L-1) st]
+// (residues < 2p): the first stage's sums (h = 0) or twiddled differences
+// (h = 1), then the length-L/2 transform. out[k] is output 2k + h in
+// bit-reversed order of k (residues < 2p).
+template <int L>
+__device__ __forceinline__ void dif_half(const uint32_t *x, int st, int h, uint32_t (&v)[L / 2],
+                                         const uint2 *__restrict__ tw, uint32_t p) {
+    constexpr int H2 = L / 2;
+    const uint32_t p2 = 2 * p;
+    if (h == 0) {
+#pragma unroll
+        for (int j = 0; j < H2; ++j) v[j] = reduce_once(x[j * st] + x[(j + H2) * st], p2);
+    } else {
+#pragma unroll
+        for (int j = 0; j < H2; ++j) {
+            const uint32_t d = x[j * st] - x[(j + H2) * st] + p2;  // (0, 4p)
+            if (j == 0) {
+                v[j] = reduce_once(d, p2);
+            } else {
+                const uint2 w = tw[H2 - 1 + j];
+                v[j] = mulmod_lazy(d, w.x, w.y, p);
+            }
+        }
+    }
+    if constexpr (H2 >= 2) dif_line<H2>(v, tw, p);
+}
+
 template <int LOGH, int LOGW>
 struct NttShape {
     static constexpr int H = 1 << LOGH, W = 1 << LOGW, F = H * W;
     static constexpr int LMAX = H > W ? H : W;
-    static constexpr int T = LMAX >= 128 ? 1 : 256 / LMAX;  // channels per workgroup
-    static constexpr int NT = T * LMAX;                       // threads per workgroup
-    static constexpr int STRIDE = W + 1;                      // padded LDS row
+    static constexpr int T = 2 * LMAX >= 256 ? 1 : 256 / (2 * LMAX);  // channels per workgroup
+    static constexpr int NT = 2 * T * LMAX;                           // threads: two per row / column
+    static constexpr int STRIDE = W + 1;                               // padded LDS row
     static constexpr int LDS_WORDS = T * H * STRIDE;
 };
 
@@ -102,31 +134,32 @@ __global__ __launch_bounds__((NttShape<LOGH, LOGW>::NT)) void ntt2d_kernel(const
     __syncthreads();
 
     const uint2 *twd = tw + MODE * kTwPerDir;
-    if (tid < T * H) {  // rows
-        uint32_t v[W];
-        uint32_t *rowp = lds + tid * STR;  // channel tid / H, row tid % H
+    {  // rows: half h of row tid % (T H); every thread meets the same barriers
+        const bool active = tid < 2 * T * H;
+        const int h = tid / (T * H), row = tid % (T * H);
+        uint32_t v[W / 2];
+        uint32_t *rowp = lds + row * STR;  // channel row / H, row row % H
+        if (active) dif_half<W>(rowp, 1, h, v, twd, p);
+        __syncthreads();  // both halves have read their row before it is overwritten
+        if (active) {
 #pragma unroll
-        for (int k = 0; k < W; ++k) v[k] = rowp[k];
-        dif_line<W>(v, twd, p);
-#pragma unroll
-        for (int k = 0; k < W; ++k) rowp[k] = v[BitRev<W>::apply(k)];
+            for (int k = 0; k < W / 2; ++k) rowp[2 * k + h] = v[BitRev<W / 2>::apply(k)];
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
-    if (tid < T * W) {  // columns
-        const int ch = tid / W, c = tid % W;
-        uint32_t v[H];
-        const uint32_t *colp = lds + ch * H * STR + c;
-#pragma unroll
-        for (int k = 0; k < H; ++k) v[k] = colp[k * STR];
-        dif_line<H>(v, twd, p);
+    if (tid < 2 * T * W) {  // columns: half h of column tid % (T W)
+        const int h = tid / (T * W), cc = tid % (T * W);
+        const int ch = cc / W, c = cc % W;
+        uint32_t v[H / 2];
+        dif_half<H>(lds + ch * H * STR + c, STR, h, v, twd, p);
         if (ch < nt) {
             uint32_t *dst = out + (first + ch) * F + c;
 #pragma unroll
-            for (int k = 0; k < H; ++k) {
-                uint32_t x = v[BitRev<H>::apply(k)];
+            for (int k = 0; k < H / 2; ++k) {
+                uint32_t x = v[BitRev<H / 2>::apply(k)];
                 if (MODE == 1) x = mulmod_lazy(x, scale, scale_q, p);
-                dst[k * W] = reduce_once(x, p);
+                dst[(2 * k + h) * W] = reduce_once(x, p);
             }
         }
     }

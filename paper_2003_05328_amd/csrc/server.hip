@@ -1,0 +1,492 @@
+// Serving: continuous batching of secure-convolution requests of mixed shapes.
+//
+// A worker thread owns the device work. Each round it admits queued requests
+// in arrival order while their ciphertext footprint (x^, ct_in, ct_out, m)
+// fits the free part of the budget (an arena carved out of one allocation),
+// groups the admitted requests into a batch, and enqueues the batch on one of
+// a few HIP streams: per request NTT2D and Enc, one persistent HomConv launch
+// over the tiles of every request of the batch, then per request Dec, the
+// client's INTT2D and the server's share. Batches on different streams
+// overlap on the device. When a batch's completion event has fired its arena
+// blocks are released and queued requests are admitted into the space.
+// Ciphertexts never leave the device between Enc, HomConv and Dec.
+#include <stdio.h>
+#include <string.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "ensei_internal.hpp"
+
+namespace ensei {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+constexpr size_t kAlign = 256;
+
+// First-fit allocator over [0, size) with coalescing of free neighbours.
+class Arena {
+   public:
+    void reset(size_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+        used_ = 0;
+    }
+    bool alloc(size_t n, size_t *off) {
+        n = (n + kAlign - 1) / kAlign * kAlign;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < n) continue;
+            *off = it->first;
+            const size_t rest = it->second - n, at = it->first + n;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            used_ += n;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        n = (n + kAlign - 1) / kAlign * kAlign;
+        used_ -= n;
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + n == next->first) {
+            n += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += n;
+                return;
+            }
+        }
+        free_[off] = n;
+    }
+    size_t used() const { return used_; }
+
+   private:
+    std::map<size_t, size_t> free_;
+    size_t used_ = 0;
+};
+
+struct Shape {
+    ensei_shape d;
+    int64_t F;
+    uint32_t *w_hat = nullptr;
+    int8_t *w_pack = nullptr;
+    size_t wpack_bytes = 0;
+    size_t footprint = 0;  // arena bytes of one request
+};
+
+enum ReqState { kQueued = 0, kRunning = 1, kDone = 2, kFailed = 3 };
+
+struct Request {
+    uint64_t ticket;
+    int shape;
+    ensei_request io;
+    ReqState state = kQueued;
+    int status = ENSEI_OK;
+    size_t off = 0;
+    Clock::time_point t_submit, t_start, t_done;
+};
+
+struct Batch {
+    std::vector<uint64_t> tickets;
+    hipStream_t stream;
+    hipEvent_t done;
+    int slot;  // launch-table slot
+};
+
+}  // namespace
+}  // namespace ensei
+
+using namespace ensei;
+
+struct ensei_server {
+    ensei_ctx *ctx = nullptr;
+    size_t budget = 0;
+    int nstreams = 0, max_batch = 0;
+    uint8_t *pool = nullptr;
+    Arena arena;
+    std::vector<Shape> shapes;
+    std::vector<hipStream_t> streams;
+    int next_stream = 0;
+    // launch tables of the multi-problem HomConv: per slot max_batch entries,
+    // device copy and pinned host staging; a slot is busy while its batch runs
+    HcLayer *d_tables = nullptr, *h_tables = nullptr;
+    std::vector<int> free_slots;
+    std::vector<hipEvent_t> event_pool;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, Request> reqs;
+    std::deque<Batch> inflight;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread worker;
+    Clock::time_point t0 = Clock::now();
+    uint64_t n_done = 0, n_failed = 0, n_batches = 0;
+    size_t peak_used = 0;
+};
+
+namespace ensei {
+namespace {
+
+double secs(const ensei_server *S, Clock::time_point t) { return std::chrono::duration<double>(t - S->t0).count(); }
+
+// Arena layout of one request: x^ [Cin][F] u32, ct_in [F][n+1][Cin] u64,
+// ct_out [F][n+1][Cout] u64, m [Cout][F] u32 (each 256-byte aligned).
+struct Parts {
+    size_t x_hat, ct_in, ct_out, m, total;
+};
+Parts parts_of(const ensei_shape &d) {
+    auto al = [](size_t v) { return (v + kAlign - 1) / kAlign * kAlign; };
+    const size_t F = (size_t)d.H * d.W;
+    Parts p;
+    p.x_hat = 0;
+    p.ct_in = al(F * d.Cin * 4);
+    p.ct_out = p.ct_in + al(F * (d.n + 1) * d.Cin * 8);
+    p.m = p.ct_out + al(F * (d.n + 1) * d.Cout * 8);
+    p.total = p.m + al(F * d.Cout * 4);
+    return p;
+}
+
+// Enqueues one batch; the caller holds the lock. Returns a status; on error
+// nothing of the batch is left running.
+int launch_batch(ensei_server *S, Batch &b) {
+    const hipStream_t st = b.stream;
+    HcLayer *tab = S->h_tables + (size_t)b.slot * S->max_batch;
+    int np = 0;
+    int64_t tile0 = 0;
+    int rc = ENSEI_OK;
+    for (uint64_t t : b.tickets) {
+        Request &q = S->reqs[t];
+        const Shape &sh = S->shapes[q.shape];
+        const ensei_shape &d = sh.d;
+        const Parts pt = parts_of(d);
+        uint8_t *base = S->pool + q.off;
+        uint32_t *x_hat = reinterpret_cast<uint32_t *>(base + pt.x_hat);
+        uint64_t *ct_in = reinterpret_cast<uint64_t *>(base + pt.ct_in);
+        uint64_t *ct_out = reinterpret_cast<uint64_t *>(base + pt.ct_out);
+        rc = ensei_ntt2d(S->ctx, q.io.x, x_hat, d.Cin, d.H, d.W, st);
+        if (!rc) rc = ensei_encrypt(S->ctx, x_hat, q.io.s, q.io.e, 1, d.Cin, sh.F, d.n, q.io.seed_a, 0, ct_in, st);
+        HcLayer h;
+        if (!rc)
+            rc = homconv_problem(S->ctx, &h, ct_in, sh.w_pack, q.io.r, 1, d.Cin, d.Cout, sh.F, d.n, ct_out,
+                                 sh.wpack_bytes);
+        if (rc) break;
+        h.n_items = frag_items(d.Cin, true);
+        h.tile0 = tile0;
+        tile0 += h.n_tiles;
+        tab[np++] = h;
+    }
+    if (!rc && np > 1) {
+        HcLayer *dtab = S->d_tables + (size_t)b.slot * S->max_batch;
+        if (hipMemcpyAsync(dtab, tab, np * sizeof(HcLayer), hipMemcpyHostToDevice, st) != hipSuccess)
+            rc = ENSEI_ERR_HIP;
+        if (!rc) rc = homconv_launch(S->ctx, tab, dtab, np, true, HcSchedule{0, 0}, st);
+    } else if (!rc) {
+        rc = homconv_launch(S->ctx, tab, nullptr, 1, true, HcSchedule{0, 0}, st);
+    }
+    for (uint64_t t : b.tickets) {
+        if (rc) break;
+        Request &q = S->reqs[t];
+        const Shape &sh = S->shapes[q.shape];
+        const ensei_shape &d = sh.d;
+        const Parts pt = parts_of(d);
+        uint8_t *base = S->pool + q.off;
+        const uint64_t *ct_out = reinterpret_cast<const uint64_t *>(base + pt.ct_out);
+        uint32_t *m = reinterpret_cast<uint32_t *>(base + pt.m);
+        rc = ensei_decrypt(S->ctx, ct_out, q.io.s, 1, d.Cout, sh.F, d.n, m, st);
+        if (!rc) rc = ensei_intt2d(S->ctx, m, q.io.s_a, d.Cout, d.H, d.W, st);
+        if (!rc) rc = ensei_server_share(S->ctx, q.io.r, q.io.s_b, d.Cout, d.H, d.W, st);
+    }
+    if (!rc && hipEventRecord(b.done, st) != hipSuccess) rc = ENSEI_ERR_HIP;
+    return rc;
+}
+
+void finish(ensei_server *S, Batch &b, int rc) {
+    const auto now = Clock::now();
+    for (uint64_t t : b.tickets) {
+        Request &q = S->reqs[t];
+        q.t_done = now;
+        q.status = rc;
+        q.state = rc ? kFailed : kDone;
+        S->arena.release(q.off, S->shapes[q.shape].footprint);
+        if (rc)
+            ++S->n_failed;
+        else
+            ++S->n_done;
+    }
+    S->free_slots.push_back(b.slot);
+    S->event_pool.push_back(b.done);
+}
+
+void worker_loop(ensei_server *S) {
+    (void)hipSetDevice(S->ctx->device);
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (true) {
+        // retire finished batches (in stream order per stream; check all)
+        for (auto it = S->inflight.begin(); it != S->inflight.end();) {
+            const hipError_t q = hipEventQuery(it->done);
+            if (q == hipErrorNotReady) {
+                ++it;
+                continue;
+            }
+            finish(S, *it, q == hipSuccess ? ENSEI_OK : ENSEI_ERR_HIP);
+            it = S->inflight.erase(it);
+            S->cv_done.notify_all();
+        }
+        // admit queued requests in arrival order while they fit, one batch
+        // per free launch slot
+        while (!S->queue.empty() && !S->free_slots.empty()) {
+            Batch b;
+            while (!S->queue.empty() && (int)b.tickets.size() < S->max_batch) {
+                Request &q = S->reqs[S->queue.front()];
+                size_t off;
+                if (!S->arena.alloc(S->shapes[q.shape].footprint, &off)) break;
+                q.off = off;
+                q.state = kRunning;
+                q.t_start = Clock::now();
+                b.tickets.push_back(q.ticket);
+                S->queue.pop_front();
+            }
+            if (b.tickets.empty()) break;
+            if (S->arena.used() > S->peak_used) S->peak_used = S->arena.used();
+            b.slot = S->free_slots.back();
+            S->free_slots.pop_back();
+            b.done = S->event_pool.back();
+            S->event_pool.pop_back();
+            b.stream = S->streams[S->next_stream];
+            S->next_stream = (S->next_stream + 1) % S->nstreams;
+            ++S->n_batches;
+            const int rc = launch_batch(S, b);
+            if (rc) {
+                // work already enqueued must finish before the memory is reused
+                (void)hipStreamSynchronize(b.stream);
+                finish(S, b, rc);
+                S->cv_done.notify_all();
+            } else {
+                S->inflight.push_back(b);
+            }
+        }
+        if (S->stop && S->queue.empty() && S->inflight.empty()) break;
+        if (S->inflight.empty() && (S->queue.empty() || S->free_slots.empty()) && !S->stop) {
+            S->cv_work.wait(lk);
+        } else {
+            // device work pending: poll its events at a fine interval
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        }
+    }
+}
+
+void destroy(ensei_server *S) {
+    if (S->worker.joinable()) {
+        {
+            std::lock_guard<std::mutex> g(S->mu);
+            S->stop = true;
+        }
+        S->cv_work.notify_all();
+        S->worker.join();
+    }
+    for (hipStream_t s : S->streams) {
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+    }
+    for (hipEvent_t e : S->event_pool) (void)hipEventDestroy(e);
+    for (Shape &sh : S->shapes) {
+        if (sh.w_hat) (void)hipFree(sh.w_hat);
+        if (sh.w_pack) (void)hipFree(sh.w_pack);
+    }
+    if (S->pool) (void)hipFree(S->pool);
+    if (S->d_tables) (void)hipFree(S->d_tables);
+    if (S->h_tables) (void)hipHostFree(S->h_tables);
+    delete S;
+}
+
+}  // namespace
+}  // namespace ensei
+
+extern "C" {
+
+size_t ensei_request_bytes(const ensei_shape *shape) {
+    if (!shape || shape->H <= 0 || shape->W <= 0 || shape->Cin <= 0 || shape->Cout <= 0 || shape->n <= 0) return 0;
+    return parts_of(*shape).total;
+}
+
+int ensei_server_create(ensei_ctx *ctx, size_t budget_bytes, int nstreams, int max_batch, ensei_server **out) {
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!out || budget_bytes == 0 || nstreams < 1 || nstreams > 8 || max_batch < 1 || max_batch > 256)
+        return ENSEI_ERR_ARG;
+    *out = nullptr;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(ctx->device);
+    ensei_server *S = new ensei_server;
+    S->ctx = ctx;
+    S->budget = (budget_bytes + kAlign - 1) / kAlign * kAlign;
+    S->nstreams = nstreams;
+    S->max_batch = max_batch;
+    const int slots = 2 * nstreams;  // launch tables: two batches in flight per stream
+    bool ok = hipMalloc(&S->pool, S->budget) == hipSuccess;
+    if (!ok) S->pool = nullptr;
+    ok = ok && hipMalloc(&S->d_tables, (size_t)slots * max_batch * sizeof(HcLayer)) == hipSuccess;
+    ok = ok && hipHostMalloc(&S->h_tables, (size_t)slots * max_batch * sizeof(HcLayer), hipHostMallocDefault) ==
+                   hipSuccess;
+    for (int i = 0; ok && i < nstreams; ++i) {
+        hipStream_t s;
+        ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+        if (ok) S->streams.push_back(s);
+    }
+    for (int i = 0; ok && i < slots; ++i) {
+        hipEvent_t e;
+        ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+        if (ok) {
+            S->event_pool.push_back(e);
+            S->free_slots.push_back(slots - 1 - i);
+        }
+    }
+    (void)hipSetDevice(prev);
+    if (!ok) {
+        destroy(S);
+        return ENSEI_ERR_HIP;
+    }
+    S->arena.reset(S->budget);
+    S->worker = std::thread(worker_loop, S);
+    *out = S;
+    return ENSEI_OK;
+}
+
+int ensei_server_add_shape(ensei_server *S, const ensei_shape *shape, const int32_t *w, int *shape_id) {
+    if (!S || !shape || !w || !shape_id) return ENSEI_ERR_ARG;
+    const ensei_shape &d = *shape;
+    if (d.H <= 0 || d.W <= 0 || d.Cin <= 0 || d.Cout <= 0 || d.n <= 0 || d.kh <= 0 || d.kw <= 0) return ENSEI_ERR_ARG;
+    if (homconv_sizes(1, d.Cin, d.Cout, (int64_t)d.H * d.W, d.n)) return homconv_sizes(1, d.Cin, d.Cout, (int64_t)d.H * d.W, d.n);
+    Shape sh;
+    sh.d = d;
+    sh.F = (int64_t)d.H * d.W;
+    sh.footprint = parts_of(d).total;
+    if (sh.footprint > S->budget) return ENSEI_ERR_LIMIT;
+    sh.wpack_bytes = wpack_bytes_as(d.Cout, d.Cin, sh.F, true);
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(S->ctx->device);
+    int rc = ENSEI_OK;
+    if (hipMalloc(&sh.w_hat, (size_t)d.Cout * d.Cin * sh.F * 4) != hipSuccess) sh.w_hat = nullptr;
+    if (sh.w_hat && hipMalloc(&sh.w_pack, sh.wpack_bytes) != hipSuccess) sh.w_pack = nullptr;
+    if (!sh.w_hat || !sh.w_pack) rc = ENSEI_ERR_HIP;
+    hipStream_t st = nullptr;
+    if (!rc && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        st = nullptr;
+        rc = ENSEI_ERR_HIP;
+    }
+    if (!rc) rc = ensei_weight_prep(S->ctx, w, d.Cout, d.Cin, d.kh, d.kw, d.H, d.W, sh.w_hat, st);
+    if (!rc) rc = pack_weights_as(S->ctx, sh.w_hat, d.Cout, d.Cin, sh.F, true, sh.w_pack, st);
+    if (st) {
+        if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = ENSEI_ERR_HIP;
+        (void)hipStreamDestroy(st);
+    }
+    (void)hipSetDevice(prev);
+    if (rc) {
+        if (sh.w_hat) (void)hipFree(sh.w_hat);
+        if (sh.w_pack) (void)hipFree(sh.w_pack);
+        return rc;
+    }
+    std::lock_guard<std::mutex> g(S->mu);
+    S->shapes.push_back(sh);
+    *shape_id = (int)S->shapes.size() - 1;
+    return ENSEI_OK;
+}
+
+int ensei_server_submit(ensei_server *S, int shape_id, const ensei_request *req, uint64_t *ticket) {
+    if (!S || !req || !ticket) return ENSEI_ERR_ARG;
+    if (!req->x || !req->s || !req->e || !req->r || !req->s_a || !req->s_b) return ENSEI_ERR_ARG;
+    std::lock_guard<std::mutex> g(S->mu);
+    if (shape_id < 0 || shape_id >= (int)S->shapes.size()) return ENSEI_ERR_ARG;
+    if (S->stop) return ENSEI_ERR_ARG;
+    Request q;
+    q.ticket = S->next_ticket++;
+    q.shape = shape_id;
+    q.io = *req;
+    q.t_submit = Clock::now();
+    S->reqs.emplace(q.ticket, q);
+    S->queue.push_back(q.ticket);
+    *ticket = q.ticket;
+    S->cv_work.notify_one();
+    return ENSEI_OK;
+}
+
+int ensei_server_poll(ensei_server *S, uint64_t ticket, ensei_request_info *info) {
+    if (!S || !info) return ENSEI_ERR_ARG;
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) return ENSEI_ERR_ARG;
+    const Request &q = it->second;
+    info->state = q.state;
+    info->status = q.status;
+    info->t_submit = secs(S, q.t_submit);
+    info->t_start = q.state >= kRunning ? secs(S, q.t_start) : 0.0;
+    info->t_done = q.state >= kDone ? secs(S, q.t_done) : 0.0;
+    return ENSEI_OK;
+}
+
+int ensei_server_wait(ensei_server *S, uint64_t ticket, int timeout_ms) {
+    if (!S) return ENSEI_ERR_ARG;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto done = [&] {
+        auto it = S->reqs.find(ticket);
+        return it == S->reqs.end() || it->second.state >= kDone;
+    };
+    if (S->reqs.find(ticket) == S->reqs.end()) return ENSEI_ERR_ARG;
+    if (timeout_ms < 0)
+        S->cv_done.wait(lk, done);
+    else if (!S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done))
+        return ENSEI_ERR_TIMEOUT;
+    return S->reqs[ticket].status;
+}
+
+int ensei_server_forget(ensei_server *S, uint64_t ticket) {
+    if (!S) return ENSEI_ERR_ARG;
+    std::lock_guard<std::mutex> g(S->mu);
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end() || it->second.state < kDone) return ENSEI_ERR_ARG;
+    S->reqs.erase(it);
+    return ENSEI_OK;
+}
+
+int ensei_server_stats(ensei_server *S, ensei_server_info *out) {
+    if (!S || !out) return ENSEI_ERR_ARG;
+    std::lock_guard<std::mutex> g(S->mu);
+    out->budget_bytes = S->budget;
+    out->used_bytes = S->arena.used();
+    out->peak_used_bytes = S->peak_used;
+    out->queued = S->queue.size();
+    out->inflight_batches = S->inflight.size();
+    out->completed = S->n_done;
+    out->failed = S->n_failed;
+    out->batches = S->n_batches;
+    return ENSEI_OK;
+}
+
+int ensei_server_destroy(ensei_server *S) {
+    if (!S) return ENSEI_OK;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(S->ctx->device);
+    destroy(S);
+    (void)hipSetDevice(prev);
+    return ENSEI_OK;
+}
+
+}  // extern "C"

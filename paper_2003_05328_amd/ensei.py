@@ -29,6 +29,7 @@ STATUS = {
     -6: "ENSEI_ERR_LIMIT",
     -7: "ENSEI_ERR_DEVICE",
     -8: "ENSEI_ERR_HIP",
+    -9: "ENSEI_ERR_TIMEOUT",
 }
 
 _vp, _i32, _i64, _u32, _u64 = C.c_void_p, C.c_int, C.c_int64, C.c_uint32, C.c_uint64
@@ -55,7 +56,42 @@ SIGNATURES = {
     "ensei_plan_run": (_i32, [_vp, _vp]),
     "ensei_plan_schedule": (_i32, [_vp, _vp]),
     "ensei_plan_destroy": (_i32, [_vp]),
+    "ensei_request_bytes": (C.c_size_t, [_vp]),
+    "ensei_server_create": (_i32, [_vp, C.c_size_t, _i32, _i32, C.POINTER(_vp)]),
+    "ensei_server_add_shape": (_i32, [_vp, _vp, _vp, C.POINTER(_i32)]),
+    "ensei_server_submit": (_i32, [_vp, _i32, _vp, C.POINTER(_u64)]),
+    "ensei_server_poll": (_i32, [_vp, _u64, _vp]),
+    "ensei_server_wait": (_i32, [_vp, _u64, _i32]),
+    "ensei_server_forget": (_i32, [_vp, _u64]),
+    "ensei_server_stats": (_i32, [_vp, _vp]),
+    "ensei_server_destroy": (_i32, [_vp]),
 }
+
+
+class ShapeDesc(C.Structure):
+    """``ensei_shape``: the shape of one secure convolution."""
+
+    _fields_ = [(f, _i32) for f in ("H", "W", "Cin", "Cout", "kh", "kw", "n")]
+
+
+class RequestDesc(C.Structure):
+    """``ensei_request``: one request's device buffers."""
+
+    _fields_ = [("x", _vp), ("s", _vp), ("e", _vp), ("r", _vp), ("seed_a", _u64), ("s_a", _vp), ("s_b", _vp)]
+
+
+class RequestInfo(C.Structure):
+    """``ensei_request_info``."""
+
+    _fields_ = [("state", _i32), ("status", _i32), ("t_submit", C.c_double), ("t_start", C.c_double),
+                ("t_done", C.c_double)]
+
+
+class ServerInfo(C.Structure):
+    """``ensei_server_info``."""
+
+    _fields_ = [(f, _u64) for f in ("budget_bytes", "used_bytes", "peak_used_bytes", "queued", "inflight_batches",
+                                    "completed", "failed", "batches")]
 
 
 class LayerDesc(C.Structure):
@@ -156,6 +192,19 @@ class Context:
     def _empty(self, shape, dtype):
         return torch.empty(shape, dtype=dtype, device=f"cuda:{self.device}")
 
+    def _out(self, out, shape, dtype):
+        """A new output of `shape`, or the caller's, which must hold exactly as
+        many elements (the kernels write all of them)."""
+        if out is None:
+            return self._empty(shape, dtype)
+        self._dev(out, "out", dtype)
+        need = 1
+        for d in shape:
+            need *= int(d)
+        if out.numel() != need:
+            raise ValueError(f"out holds {out.numel()} elements, {need} are written")
+        return out
+
     def _call(self, name, *args):
         with torch.cuda.device(self.device):
             _check(getattr(lib(), name)(self._h, *args, self._stream()), name)
@@ -166,7 +215,7 @@ class Context:
         self._dev(x, "x", torch.uint32)
         H, W = x.shape[-2:]
         batch = x.numel() // (H * W)
-        out = self._empty(x.shape[:-2] + (H * W,), torch.uint32) if out is None else self._dev(out, "out", torch.uint32)
+        out = self._out(out, x.shape[:-2] + (H * W,), torch.uint32)
         self._call("ensei_ntt2d", _ptr(x), _ptr(out), batch, H, W)
         return out
 
@@ -174,7 +223,7 @@ class Context:
         """X uint32 [..., H*W] -> out uint32 [..., H, W] (ensei_intt2d)."""
         self._dev(X, "X", torch.uint32)
         batch = X.numel() // (H * W)
-        out = self._empty(X.shape[:-1] + (H, W), torch.uint32) if out is None else self._dev(out, "out", torch.uint32)
+        out = self._out(out, X.shape[:-1] + (H, W), torch.uint32)
         self._call("ensei_intt2d", _ptr(X), _ptr(out), batch, H, W)
         return out
 
@@ -182,7 +231,7 @@ class Context:
         """r uint32 [..., H*W] -> s_B = INTT2D(-r) uint32 [..., H, W] (ensei_server_share)."""
         self._dev(r, "r", torch.uint32)
         batch = r.numel() // (H * W)
-        out = self._empty(r.shape[:-1] + (H, W), torch.uint32) if out is None else self._dev(out, "out", torch.uint32)
+        out = self._out(out, r.shape[:-1] + (H, W), torch.uint32)
         self._call("ensei_server_share", _ptr(r), _ptr(out), batch, H, W)
         return out
 
@@ -191,7 +240,7 @@ class Context:
         """w int32 [Cout][Cin][kh][kw] -> W^ uint32 [Cout][Cin][H*W] (ensei_weight_prep)."""
         self._dev(w, "w", torch.int32)
         Cout, Cin, kh, kw = w.shape
-        out = self._empty((Cout, Cin, H * W), torch.uint32) if out is None else self._dev(out, "out", torch.uint32)
+        out = self._out(out, (Cout, Cin, H * W), torch.uint32)
         self._call("ensei_weight_prep", _ptr(w), Cout, Cin, kh, kw, H, W, _ptr(out))
         return out
 
@@ -200,7 +249,7 @@ class Context:
         self._dev(w_hat, "w_hat", torch.uint32)
         Cout, Cin, F = w_hat.shape
         nb = int(lib().ensei_wpack_bytes(Cout, Cin, F))
-        out = self._empty((nb,), torch.int8) if out is None else self._dev(out, "out", torch.int8)
+        out = self._out(out, (nb,), torch.int8)
         if out.numel() < nb:
             raise ValueError(f"packed-weight buffer needs {nb} bytes")
         self._call("ensei_pack_weights", _ptr(w_hat), Cout, Cin, F, _ptr(out))
@@ -219,7 +268,7 @@ class Context:
         flat = m.dim() == 1
         B, C, F = (1, 1, m.shape[0]) if flat else tuple(m.shape)
         shape = (F, n + 1) if flat else (B, F, n + 1, C)
-        out = self._empty(shape, torch.uint64) if out is None else self._dev(out, "out", torch.uint64)
+        out = self._out(out, shape, torch.uint64)
         if out.numel() != B * C * F * (n + 1):
             raise ValueError("ct has the wrong size")
         self._call("ensei_encrypt", _ptr(m), _ptr(s), _ptr(e), B, C, F, n, seed_a % 2**64, ct_index0 % 2**64, _ptr(out))
@@ -239,7 +288,7 @@ class Context:
         if n1 != n + 1:
             raise ValueError("ciphertexts must have n+1 words")
         shape = (F,) if flat else (B, C, F)
-        out = self._empty(shape, torch.uint32) if out is None else self._dev(out, "out", torch.uint32)
+        out = self._out(out, shape, torch.uint32)
         self._call("ensei_decrypt", _ptr(ct), _ptr(s), B, C, F, n, _ptr(out))
         return out
 
@@ -258,7 +307,7 @@ class Context:
         B, Cin, F, n = self._hc_shapes(ct_in, Cout, r)
         if w_pack.numel() < int(lib().ensei_wpack_bytes(Cout, Cin, F)):
             raise ValueError("w_pack is smaller than ensei_wpack_bytes(Cout, Cin, F)")
-        out = self._empty((B, F, n + 1, Cout), torch.uint64) if out is None else self._dev(out, "out", torch.uint64)
+        out = self._out(out, (B, F, n + 1, Cout), torch.uint64)
         self._call("ensei_homconv", _ptr(ct_in), _ptr(w_pack), _ptr(r), B, Cin, Cout, F, n, _ptr(out))
         return out
 
@@ -271,7 +320,7 @@ class Context:
         B, Cin, F, n = self._hc_shapes(ct_in, Cout, r)
         if tuple(w_hat.shape) != (Cout, Cin, F):
             raise ValueError("w_hat must be [Cout][Cin][F]")
-        out = self._empty((B, F, n + 1, Cout), torch.uint64) if out is None else self._dev(out, "out", torch.uint64)
+        out = self._out(out, (B, F, n + 1, Cout), torch.uint64)
         self._call("ensei_homconv_valu", _ptr(ct_in), _ptr(w_hat), _ptr(r), B, Cin, Cout, F, n, _ptr(out))
         return out
 
@@ -302,8 +351,16 @@ class Plan:
             dtypes = {"w": torch.int32, "x": torch.uint32, "s": torch.int8, "e": torch.int32, "r": torch.uint32,
                       "x_hat": torch.uint32, "ct_in": torch.uint64, "ct_out": torch.uint64, "m": torch.uint32,
                       "s_a": torch.uint32, "s_b": torch.uint32}
+            H, W, Cin, Cout, n = (int(l[k]) for k in ("H", "W", "Cin", "Cout", "n"))
+            F = H * W
+            sizes = {"w": Cout * Cin * int(l["kh"]) * int(l["kw"]), "x": B * Cin * F, "s": n, "e": B * Cin * F,
+                     "r": B * Cout * F, "x_hat": B * Cin * F, "ct_in": B * F * (n + 1) * Cin,
+                     "ct_out": B * F * (n + 1) * Cout, "m": B * Cout * F, "s_a": B * Cout * F, "s_b": B * Cout * F}
             for k in self._INPUTS + self._OUTPUTS:
-                setattr(d, k, _ptr(ctx._dev(l[k], k, dtypes[k])).value)
+                t = ctx._dev(l[k], k, dtypes[k])
+                if t.numel() != sizes[k]:
+                    raise ValueError(f"layer buffer {k} holds {t.numel()} elements, the shape needs {sizes[k]}")
+                setattr(d, k, _ptr(t).value)
         h = C.c_void_p()
         cache = tune_cache.encode() if tune_cache else None
         with torch.cuda.device(ctx.device):
@@ -338,6 +395,89 @@ class Plan:
             torch.cuda.synchronize(self.ctx.device)
             lib().ensei_plan_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """A continuous-batching server (``ensei_server``) for secure-convolution
+    requests of mixed shapes under a device-memory budget for their
+    ciphertext state."""
+
+    STATES = ("queued", "running", "done", "failed")
+
+    def __init__(self, ctx: "Context", budget_bytes: int, nstreams: int = 4, max_batch: int = 16):
+        self.ctx = ctx
+        h = C.c_void_p()
+        with torch.cuda.device(ctx.device):
+            _check(lib().ensei_server_create(ctx._h, int(budget_bytes), nstreams, max_batch, C.byref(h)),
+                   "ensei_server_create")
+        self._h = h
+        self._shapes = {}
+        self._keep = {}  # ticket -> the request's tensors, kept alive until forget()
+
+    @staticmethod
+    def request_bytes(H, W, Cin, Cout, kh, kw, n) -> int:
+        return int(lib().ensei_request_bytes(C.byref(ShapeDesc(H, W, Cin, Cout, kh, kw, n))))
+
+    def add_shape(self, H, W, Cin, Cout, kh, kw, n, w: torch.Tensor) -> int:
+        """Registers a shape with the server's filters w int32 [Cout][Cin][kh][kw]; returns its id."""
+        self.ctx._dev(w, "w", torch.int32)
+        if w.numel() != Cout * Cin * kh * kw:
+            raise ValueError("w has the wrong size")
+        sid = C.c_int()
+        with torch.cuda.device(self.ctx.device):
+            _check(lib().ensei_server_add_shape(self._h, C.byref(ShapeDesc(H, W, Cin, Cout, kh, kw, n)), _ptr(w),
+                                                C.byref(sid)), "ensei_server_add_shape")
+        self._shapes[sid.value] = (H, W, Cin, Cout, kh, kw, n)
+        return sid.value
+
+    def submit(self, shape_id: int, x, s, e, r, seed_a: int, s_a, s_b) -> int:
+        """Queues one request (device tensors: x [Cin][H][W], s [n], e [Cin][F],
+        r [Cout][F]; outputs s_a, s_b [Cout][H][W]). Inputs must be complete."""
+        H, W, Cin, Cout, kh, kw, n = self._shapes[shape_id]
+        F = H * W
+        need = {"x": (x, torch.uint32, Cin * F), "s": (s, torch.int8, n), "e": (e, torch.int32, Cin * F),
+                "r": (r, torch.uint32, Cout * F), "s_a": (s_a, torch.uint32, Cout * F),
+                "s_b": (s_b, torch.uint32, Cout * F)}
+        for k, (t, dt, cnt) in need.items():
+            self.ctx._dev(t, k, dt)
+            if t.numel() != cnt:
+                raise ValueError(f"{k} holds {t.numel()} elements, the shape needs {cnt}")
+        rq = RequestDesc(_ptr(x).value, _ptr(s).value, _ptr(e).value, _ptr(r).value, int(seed_a) & (2**64 - 1),
+                         _ptr(s_a).value, _ptr(s_b).value)
+        t = C.c_uint64()
+        _check(lib().ensei_server_submit(self._h, shape_id, C.byref(rq), C.byref(t)), "ensei_server_submit")
+        self._keep[t.value] = (x, s, e, r, s_a, s_b)
+        return t.value
+
+    def poll(self, ticket: int) -> dict:
+        info = RequestInfo()
+        _check(lib().ensei_server_poll(self._h, ticket, C.byref(info)), "ensei_server_poll")
+        return {"state": self.STATES[info.state], "status": info.status, "t_submit": info.t_submit,
+                "t_start": info.t_start, "t_done": info.t_done}
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> None:
+        _check(lib().ensei_server_wait(self._h, ticket, timeout_ms), "ensei_server_wait")
+
+    def forget(self, ticket: int) -> None:
+        _check(lib().ensei_server_forget(self._h, ticket), "ensei_server_forget")
+        self._keep.pop(ticket, None)
+
+    def stats(self) -> dict:
+        si = ServerInfo()
+        _check(lib().ensei_server_stats(self._h, C.byref(si)), "ensei_server_stats")
+        return {k: int(getattr(si, k)) for k, _ in ServerInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().ensei_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

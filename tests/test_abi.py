@@ -80,6 +80,25 @@ def test_entry_points_reject_null_context(lib):
     assert lib.ensei_plan_destroy(None) == 0
 
 
+def test_server_host_checks(lib):
+    h = ctypes.c_void_p()
+    assert lib.ensei_server_create(None, 1 << 20, 1, 1, ctypes.byref(h)) < 0
+    assert lib.ensei_server_destroy(None) == 0
+    assert lib.ensei_server_submit(None, 0, None, None) == -1
+    assert lib.ensei_server_wait(None, 1, 0) == -1
+    assert lib.ensei_server_stats(None, None) == -1
+    # a request's device footprint: x^, ct_in, ct_out, m, each 256-byte aligned
+    sh = ensei.ShapeDesc(32, 32, 64, 64, 3, 3, 1024)
+    F = 32 * 32
+    al = lambda v: (v + 255) // 256 * 256
+    assert lib.ensei_request_bytes(ctypes.byref(sh)) == al(F * 64 * 4) + 2 * al(F * 1025 * 64 * 8) + al(F * 64 * 4)
+    sh.n = 0
+    assert lib.ensei_request_bytes(ctypes.byref(sh)) == 0
+    assert ctypes.sizeof(ensei.RequestDesc) == 7 * 8
+    assert ctypes.sizeof(ensei.RequestInfo) == 8 + 3 * 8
+    assert ctypes.sizeof(ensei.ServerInfo) == 8 * 8
+
+
 def test_plan_structs_match_the_header():
     # ensei_layer: 7 ints, int64 batch, uint64 seed_a, 11 pointers
     assert ctypes.sizeof(ensei.LayerDesc) == 7 * 4 + 4 + 8 + 8 + 11 * 8
