@@ -32,6 +32,8 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 DEFAULT_WORKLOAD = "conv32x32_c64to64_k3_n1024"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "homconv_traffic.json")
+# 32-bit integer vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HOMCONV_SRC = os.path.join(ROOT, "paper_2003_05328_amd", "csrc", "homconv.hip")
 
 
@@ -112,9 +114,22 @@ def ntt_throughput(ctx, S, reps: int = 20):
     us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
     pts = batch * S.H * S.W
     gbs = 8 * pts / (us * 1e-6) / 1e9
+    # integer ALU work of the radix-2 transforms: per butterfly 10 int32 ops
+    # with a twiddle (add, reduce, sub, Shoup multiply) and 6 without (j = 0)
+    def line_ops(L):
+        ops, m = 0, L
+        while m >= 2:
+            ops += (L // m) * (6 + 10 * (m // 2 - 1))
+            m //= 2
+        return ops
+
+    ops = batch * (S.H * line_ops(S.W) + S.W * line_ops(S.H))
+    tops = ops / (us * 1e-6) / 1e12
     return {"grids": batch, "grid": f"{S.H}x{S.W}", "avg_us": us, "points_per_s": pts / (us * 1e-6),
             "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-            "bytes_per_point": 8}
+            "bytes_per_point": 8,
+            "alu": {"achieved": tops, "peak": ALU_PEAK_TOPS, "unit": "T int32 op/s", "frac": tops / ALU_PEAK_TOPS,
+                    "ops_per_launch": ops}}
 
 
 def stack_batched(ctx, reps: int, seed: int):
