@@ -94,10 +94,14 @@ struct HcCoord {
 };
 
 // Data of one unit in flight: 8 words per thread, 2 weight-fragment items, 1 mask.
+// afresh: the weight fragments were loaded for this unit; otherwise the
+// LDS buffer of this parity already holds them (akey: their address).
 struct HcBuf {
     u32x4 w[4];
     v4i a[2];
     uint32_t r;
+    uint64_t akey;
+    bool afresh;
 };
 
 constexpr int kHcThreads = 512;
@@ -207,16 +211,24 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
         const uint8_t *blk =
             uniform_ptr(reinterpret_cast<const uint8_t *>(P.ct_in + (u.b * F + u.f) * rowlen * Cin));
         const __amdgpu_buffer_rsrc_t rs = make_rsrc(blk, (uint32_t)(rowlen * Cin * 8));
-        // columns past n read zero; channels past Cin read the next column's
-        // words, which meet zero weights
-        const uint32_t off = (uint32_t)(((int64_t)col * Cin + u.ks * 64 + ld_sc * 16 + ld_h * 8) * 8);
+        // columns past n read zero; an 8-channel group that starts past Cin
+        // is not read at all (no traffic), one that straddles it reads the next
+        // column's words, which meet zero weights
+        const bool any = ld_sc * 16 + ld_h * 8 < Cin - u.ks * 64;
+        const uint32_t off =
+            any ? (uint32_t)(((int64_t)col * Cin + u.ks * 64 + ld_sc * 16 + ld_h * 8) * 8) : 0x80000000u;
 #pragma unroll
         for (int q = 0; q < 4; ++q) buf.w[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16 * q), 0, 0);
         // the unit's weight fragments: n_items contiguous 16-byte items, item k
         // read by thread k % 512 (items past n_items read zero, with no traffic)
+        // Consecutive units mostly share them (same problem, f, K step and row
+        // tile for every column tile): when the unit two back, whose LDS buffer
+        // this unit reuses, had the same ones, nothing is read or rewritten.
         const int64_t unit = ((int64_t)u.f * P.n_ks + u.ks) * P.n_ot + u.ot;
-        const __amdgpu_buffer_rsrc_t ra = make_rsrc(
-            uniform_ptr(reinterpret_cast<const uint8_t *>(P.w_pack) + unit * P.n_items * 16), (uint32_t)(P.n_items * 16));
+        const uint8_t *abase = uniform_ptr(reinterpret_cast<const uint8_t *>(P.w_pack) + unit * P.n_items * 16);
+        buf.afresh = (uint64_t)abase != buf.akey;
+        buf.akey = (uint64_t)abase;
+        const __amdgpu_buffer_rsrc_t ra = make_rsrc(abase, buf.afresh ? (uint32_t)(P.n_items * 16) : 0u);
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
             const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(ra, (tid + kHcThreads * j) * 16, 0, 0);
@@ -347,6 +359,7 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
                 X[c][2] = (uint32_t)w1;
                 X[c][3] = (uint32_t)(w1 >> 32);
             }
+            if (valid) {  // (a unit that stores nothing skips the shuffle; its stores are dropped)
 #pragma unroll
             for (int d = 0; d < 4; ++d) {
 #pragma unroll
@@ -361,6 +374,7 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
                     X[c][d] = t[0];
                     X[c + 1][d] = t[1];
                 }
+            }
             }
             const int o = cur.ot * 64 + 32 * rg + 2 * g;  // + 8 q: rows of store q
             const uint32_t off = (uint32_t)(b_col * out_col_bytes + o * 8);
@@ -386,6 +400,7 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
     // store sequence as every iteration (stores fully out of bounds) so the
     // waits at the loop head see one static count on both incoming paths
     HcBuf buf0, buf1;
+    buf0.akey = buf1.akey = 0;  // no fragments in either LDS buffer yet
     const uint64_t none[2][4] = {};
     nx = cur;
     issue(nx, buf0);
@@ -395,6 +410,7 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
     store_out(none, false);
     int64_t issued = n_units > 1 ? 2 : 1;
 
+    uint64_t res[2][4] = {};  // the last finished tile's words (kept across units)
     auto body = [&](HcBuf &buf, int lb) {
         const HcLayer P = layer(cur.L);
         const bool last_ks = cur.ks == P.n_ks - 1;
@@ -427,7 +443,8 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
                 u32x2{pl[k][0] ^ 0x80808080u, pl[k][1] ^ 0x80808080u};
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-            if (tid + kHcThreads * j < kAItems) reinterpret_cast<v4i *>(lds_a(lb))[tid + kHcThreads * j] = buf.a[j];
+            if (buf.afresh && tid + kHcThreads * j < kAItems)
+                reinterpret_cast<v4i *>(lds_a(lb))[tid + kHcThreads * j] = buf.a[j];
         if (tid < 64) lds_r(lb)[tid] = buf.r;
         __syncthreads();
 
@@ -448,7 +465,6 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
 
         // epilogue: recombine the shift accumulators (in every unit, so the
         // store count stays static; only the tile's last K step stores)
-        uint64_t res[2][4];
         auto recombine_all = [&](auto small_tag) {
             constexpr bool SMALL = decltype(small_tag)::value;
 #pragma unroll
@@ -458,16 +474,20 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
                     res[rb][i] = recombine<SMALL>(acc[0][rb][i], acc[1][rb][i], acc[2][rb][i], acc[3][rb][i],
                                                   acc[4][rb][i], acc[5][rb][i], acc[6][rb][i], acc[7][rb][i]);
         };
-        if (P.Cin <= kSmallCin)
-            recombine_all(std::true_type{});
-        else
-            recombine_all(std::false_type{});
-        // HomShare: Delta * r on the b word (column n)
-        if (cur.jt * 64 + 64 > P.n && cur.jt * 64 + b_col == P.n) {
+        // only the tile's last K step recombines; the others issue the same
+        // (dropped) stores so that the wait counts stay static
+        if (last_ks) {
+            if (P.Cin <= kSmallCin)
+                recombine_all(std::true_type{});
+            else
+                recombine_all(std::false_type{});
+            // HomShare: Delta * r on the b word (column n)
+            if (cur.jt * 64 + 64 > P.n && cur.jt * 64 + b_col == P.n) {
 #pragma unroll
-            for (int rb = 0; rb < 2; ++rb)
+                for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) res[rb][i] += delta * (uint64_t)lds_r(lb)[out_row + 4 * rb + i];
+                    for (int i = 0; i < 4; ++i) res[rb][i] += delta * (uint64_t)lds_r(lb)[out_row + 4 * rb + i];
+            }
         }
         store_out(res, last_ks);
         advance(cur);
