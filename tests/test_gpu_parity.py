@@ -84,7 +84,7 @@ def test_weight_prep(ctx, orc, Cout, Cin, kh, kw, H, W):
 
 
 @pytest.mark.parametrize("n,num_ct,c0", [(1, 5, 0), (16, 77, 3), (63, 130, 0), (64, 64, 2**40), (65, 257, 11),
-                                         (512, 300, 0), (1024, 1000, 123456)])
+                                         (512, 300, 0), (1024, 1000, 123456), (16384, 70, 7)])
 def test_encrypt_decrypt(ctx, orc, n, num_ct, c0):
     m = synth.uniform_u32(n, num_ct, P)
     m[:2] = [0, P - 1]
@@ -175,7 +175,7 @@ def test_homconv_extreme_words(ctx, orc):
     assert np.array_equal(got, ref)
 
 
-@pytest.mark.parametrize("Cin", [169, 170, 300])
+@pytest.mark.parametrize("Cin", [169, 170, 300, 2048])
 def test_homconv_extreme_digits(ctx, orc, Cin):
     """Every ciphertext digit -128 and W^ = 0x8080 (limbs -128, -127, 1): the
     largest same-sign shift sums, on both sides of the kernel's bound for its
@@ -192,6 +192,33 @@ def test_homconv_extreme_digits(ctx, orc, Cin):
 
 
 # -------------------------------------------------------- argument checks ---
+
+
+def test_degenerate_sizes_are_rejected_before_launch(ctx):
+    from paper_2003_05328_amd.ensei import lib, _ptr
+
+    L, h = lib(), ctx._h
+    x = torch.zeros(64, dtype=torch.uint32, device="cuda:0")
+    ct = torch.zeros(64, dtype=torch.uint64, device="cuda:0")
+    s8 = torch.zeros(8, dtype=torch.int8, device="cuda:0")
+    # empty batches, empty grids, zero channels, zero LWE dimension: ENSEI_ERR_ARG / SHAPE, nothing launched
+    assert L.ensei_ntt2d(h, _ptr(x), _ptr(x), 0, 4, 4, None) == -1
+    assert L.ensei_ntt2d(h, _ptr(x), _ptr(x), 1, 0, 4, None) == -2
+    assert L.ensei_encrypt(h, _ptr(x), _ptr(s8), _ptr(x), 0, 1, 1, 8, 0, 0, _ptr(ct), None) == -1
+    assert L.ensei_encrypt(h, _ptr(x), _ptr(s8), _ptr(x), 1, 1, 1, 0, 0, 0, _ptr(ct), None) == -1
+    assert L.ensei_decrypt(h, _ptr(ct), _ptr(s8), 1, 0, 1, 8, _ptr(x), None) == -1
+    assert L.ensei_homconv(h, _ptr(ct), _ptr(s8), _ptr(x), 1, 0, 4, 1, 4, _ptr(ct), None) == -1
+    assert L.ensei_homconv(h, _ptr(ct), _ptr(s8), _ptr(x), 1, 4, 4, 1, 20000, _ptr(ct), None) == -6  # n > max
+    torch.cuda.synchronize()
+
+
+def test_binding_rejects_wrong_output_sizes(ctx):
+    x = torch.zeros((3, 8, 8), dtype=torch.uint32, device="cuda:0")
+    with pytest.raises(ValueError, match="elements"):
+        ctx.ntt2d(x, out=torch.empty(3 * 64 - 1, dtype=torch.uint32, device="cuda:0"))
+    with pytest.raises(ValueError, match="elements"):
+        ctx.intt2d(x.view(3, 64), 8, 8, out=torch.empty(10, dtype=torch.uint32, device="cuda:0"))
+
 
 
 def test_errors_are_reported(ctx):
@@ -242,10 +269,16 @@ def test_small_secure_conv_bit_exact(ctx, orc):
 
 
 FULL = [
+    "conv16x16_c3to8_k3_n512",
     "conv32x32_c64to64_k3_n1024",
     "conv32x32_c64to64_k3_n1024_hidden",
+    "conv64x64(56)_c64to64_k3_n1024",
     "conv128x128_c3to64_k7_n1024",
+    "stack8_L1_32x32_c3to64",
+    "stack8_L4_16x16_c128to128",
+    "stack8_L6_8x8_c256to256",
     "stack8_L7_4x4_c256to512",
+    "stack8bin_L5_8x8_c128to256",
 ]
 
 
