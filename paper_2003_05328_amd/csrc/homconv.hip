@@ -513,32 +513,46 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
 // of W^ (bytes of W^ + 0x808080, each xor 0x80).
 __device__ __forceinline__ int frag_row(int rbg, int m) { return 32 * (rbg >> 1) + 8 * (m >> 2) + 4 * (rbg & 1) + (m & 3); }
 
+// One thread per (f, unit, 16 channels of one row): it reads those 16 values of
+// W^ once and writes every item built from them (3 limbs, or 4 limb slots).
 __global__ void pack_weights_kernel(const uint32_t *__restrict__ w_hat, int Cout, int Cin, int64_t F, int n_ks,
                                     int n_ot, int n_items, int paired, int8_t *__restrict__ w_pack) {
-    const int64_t total = F * n_ks * n_ot * n_items;
+    const int per_unit = paired ? 256 : n_items / 4;  // threads per unit
+    const int64_t total = F * n_ks * n_ot * per_unit;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
         // f fastest: neighbouring threads read neighbouring W^ words
         const int64_t f = idx % F;
         int64_t rest = idx / F;
-        const int k = (int)(rest % n_items);
-        rest /= n_items;
+        const int j = (int)(rest % per_unit);
+        rest /= per_unit;
         const int ot = (int)(rest % n_ot), ks = (int)(rest / n_ot);
-        const int ln = k & 63, rbg = (k >> 6) & 3, hi = k >> 8;
-        const int row = ot * 64 + frag_row(rbg, ln & 15);
-        const int group = paired ? ks * 4 + (ln >> 4) : hi;
-        const int limb = paired ? hi : (ln >> 4);
-        uint32_t dig[4] = {0, 0, 0, 0};
+        // paired: j = (row block, lane), 3 limbs at k = limb * 256 + j;
+        // folded: j = (group, row block, m), 4 slots at k = group * 256 + rbg * 64 + slot * 16 + m
+        const int rbg = paired ? (j >> 6) : ((j >> 4) & 3);
+        const int m = paired ? (j & 15) : (j & 15);
+        const int group = paired ? ks * 4 + ((j & 63) >> 4) : (j >> 6);
+        const int row = ot * 64 + frag_row(rbg, m);
+        uint32_t dig[4][4] = {};
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
             const int i = group * 16 + c;
             uint32_t w = 0;
             if (row < Cout && i < Cin) w = w_hat[((int64_t)row * Cin + i) * F + f];
             const uint32_t u = (w + 0x808080u) ^ 0x808080u;  // balanced digits as bytes (byte 3 is 0)
-            dig[c >> 2] |= ((u >> (8 * limb)) & 0xffu) << (8 * (c & 3));
+#pragma unroll
+            for (int l = 0; l < 4; ++l) dig[l][c >> 2] |= ((u >> (8 * l)) & 0xffu) << (8 * (c & 3));
         }
         const int64_t unit = ((int64_t)f * n_ks + ks) * n_ot + ot;
-        reinterpret_cast<uint4 *>(w_pack)[unit * n_items + k] = make_uint4(dig[0], dig[1], dig[2], dig[3]);
+        uint4 *dst = reinterpret_cast<uint4 *>(w_pack) + unit * n_items;
+        if (paired) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l) dst[l * 256 + j] = make_uint4(dig[l][0], dig[l][1], dig[l][2], dig[l][3]);
+        } else {
+            const int k0 = (j >> 6) * 256 + rbg * 64 + m;
+#pragma unroll
+            for (int l = 0; l < 4; ++l) dst[k0 + l * 16] = make_uint4(dig[l][0], dig[l][1], dig[l][2], dig[l][3]);
+        }
     }
 }
 
@@ -626,7 +640,7 @@ int pack_weights_as(const ensei_ctx *ctx, const uint32_t *w_hat, int Cout, int C
     if (overlaps(w_pack, wpack_bytes_as(Cout, Cin, F, paired), w_hat, (size_t)Cout * Cin * F * 4))
         return ENSEI_ERR_OVERLAP;
     const int n_ks = (Cin + 63) / 64, n_ot = (Cout + 63) / 64, n_items = frag_items(Cin, paired);
-    const int64_t total = F * n_ks * n_ot * n_items;
+    const int64_t total = F * n_ks * n_ot * (paired ? 256 : n_items / 4);
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(pack_weights_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, w_hat, Cout, Cin, F, n_ks,

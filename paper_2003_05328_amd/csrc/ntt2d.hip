@@ -1,5 +1,5 @@
 // Cyclic 2D NTT / INTT over Z_p for H x W grids (H, W powers of two <= 128),
-// the server's share INTT2D(-r), and the filter weight prep (pad + NTT2D).
+// the server's share INTT2D(-r), and the filter weight prep (padding fused into the NTT2D's staging).
 //
 // Layout: one workgroup transforms T whole channels. The channels are staged
 // from HBM into LDS with 16-byte loads (rows padded to W+1 words so that
@@ -95,11 +95,15 @@ struct NttShape {
 };
 
 // MODE 0: forward. MODE 1: inverse, output times `scale` (= (HW)^-1 for
-// INTT2D, -(HW)^-1 for the server share).
+// INTT2D, -(HW)^-1 for the server share). MODE 2: forward transform of
+// filters wsrc [batch][kh][kw] (int32), reduced mod p and zero-padded into
+// the top-left of the grid while being staged into LDS.
 template <int LOGH, int LOGW, int MODE>
 __global__ __launch_bounds__((NttShape<LOGH, LOGW>::NT)) void ntt2d_kernel(const uint32_t *in, uint32_t *out,
                                                                          int64_t batch, const uint2 *__restrict__ tw,
-                                                                         uint32_t p, uint32_t scale, uint32_t scale_q) {
+                                                                         uint32_t p, uint32_t scale, uint32_t scale_q,
+                                                                         const int32_t *__restrict__ wsrc, int kh,
+                                                                         int kw) {
     using S = NttShape<LOGH, LOGW>;
     constexpr int H = S::H, W = S::W, F = S::F, T = S::T, NT = S::NT, STR = S::STRIDE;
     extern __shared__ uint32_t lds[];
@@ -109,9 +113,21 @@ __global__ __launch_bounds__((NttShape<LOGH, LOGW>::NT)) void ntt2d_kernel(const
     const int nt = (int)((batch - first) < T ? (batch - first) : T);
     const uint32_t *src = in + first * F;
 
+    if constexpr (MODE == 2) {
+        // filters: every grid point written once, the taps reduced mod p
+        for (int e = tid; e < T * F; e += NT) {
+            const int ch = e / F, f = e % F, r = f / W, c = f % W;
+            uint32_t v = 0;
+            if (ch < nt && r < kh && c < kw) {
+                const int32_t x = wsrc[((first + ch) * kh + r) * kw + c] % (int32_t)p;
+                v = (uint32_t)(x < 0 ? x + (int32_t)p : x);
+            }
+            lds[(ch * H + r) * STR + c] = v;
+        }
+    }
     // HBM -> LDS, 16-byte loads (channels are 16-byte aligned since F >= 4).
     constexpr int VEC = W >= 4 ? 4 : W;
-    for (int e = tid * VEC; e < T * F; e += NT * VEC) {
+    for (int e = tid * VEC; MODE != 2 && e < T * F; e += NT * VEC) {
         const int row = e / W, col = e % W;
         if (e < nt * F) {
             if constexpr (VEC == 4) {
@@ -133,7 +149,7 @@ __global__ __launch_bounds__((NttShape<LOGH, LOGW>::NT)) void ntt2d_kernel(const
     }
     __syncthreads();
 
-    const uint2 *twd = tw + MODE * kTwPerDir;
+    const uint2 *twd = tw + (MODE == 1 ? kTwPerDir : 0);
     {  // rows: half h of row tid % (T H); every thread meets the same barriers
         const bool active = tid < 2 * T * H;
         const int h = tid / (T * H), row = tid % (T * H);
@@ -167,7 +183,7 @@ __global__ __launch_bounds__((NttShape<LOGH, LOGW>::NT)) void ntt2d_kernel(const
 
 template <int LOGH, int LOGW, int MODE>
 static int launch_ntt(const uint32_t *in, uint32_t *out, int64_t batch, const ensei_ctx *ctx, uint32_t scale,
-                      hipStream_t st) {
+                      hipStream_t st, const int32_t *w, int kh, int kw) {
     using S = NttShape<LOGH, LOGW>;
     const size_t lds = (size_t)S::LDS_WORDS * 4;
     auto kern = ntt2d_kernel<LOGH, LOGW, MODE>;
@@ -181,11 +197,12 @@ static int launch_ntt(const uint32_t *in, uint32_t *out, int64_t batch, const en
     if (blocks > 0x7fffffff) return ENSEI_ERR_LIMIT;
     const uint32_t scale_q = (uint32_t)(((uint64_t)scale << 24) / ctx->p);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(S::NT), lds, st, in, out, batch, ctx->d_tw, ctx->p, scale,
-                       scale_q);
+                       scale_q, w, kh, kw);
     return launch_status();
 }
 
-using LaunchFn = int (*)(const uint32_t *, uint32_t *, int64_t, const ensei_ctx *, uint32_t, hipStream_t);
+using LaunchFn = int (*)(const uint32_t *, uint32_t *, int64_t, const ensei_ctx *, uint32_t, hipStream_t,
+                        const int32_t *, int, int);
 
 template <int MODE>
 struct NttTable {
@@ -236,26 +253,7 @@ static int run_ntt(const ensei_ctx *ctx, const uint32_t *in, uint32_t *out, int6
         if (negate) scale = (ctx->p - scale) % ctx->p;
     }
     LaunchFn fn = mode == 0 ? NttTable<0>::table[lh - 1][lw - 1] : NttTable<1>::table[lh - 1][lw - 1];
-    return fn(in, out, batch, ctx, scale, (hipStream_t)stream);
-}
-
-// Filter reduced mod p and zero-padded into the top-left of the H x W grid.
-__global__ void pad_filters_kernel(const int32_t *__restrict__ w, int64_t nfilt, int kh, int kw, int H, int W,
-                                   int32_t p, uint32_t *__restrict__ out) {
-    const int64_t F = (int64_t)H * W;
-    const int64_t total = nfilt * F;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t t = idx / F;
-        const int f = (int)(idx - t * F);
-        const int r = f / W, c = f % W;
-        uint32_t v = 0;
-        if (r < kh && c < kw) {
-            int32_t x = w[(t * kh + r) * kw + c] % p;
-            v = (uint32_t)(x < 0 ? x + p : x);
-        }
-        out[idx] = v;
-    }
+    return fn(in, out, batch, ctx, scale, (hipStream_t)stream, nullptr, 0, 0);
 }
 
 }  // namespace ensei
@@ -288,14 +286,8 @@ int ensei_weight_prep(ensei_ctx *ctx, const int32_t *w, int Cout, int Cin, int k
     if (((uintptr_t)w & 3) || ((uintptr_t)w_hat & 15)) return ENSEI_ERR_ALIGN;
     const int64_t nfilt = (int64_t)Cout * Cin;
     if (overlaps(w, (size_t)nfilt * kh * kw * 4, w_hat, (size_t)nfilt * H * W * 4)) return ENSEI_ERR_OVERLAP;
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t total = nfilt * H * W;
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(pad_filters_kernel, dim3((unsigned)blocks), dim3(256), 0, s, w, nfilt, kh, kw, H, W,
-                       (int32_t)ctx->p, w_hat);
-    if ((st = launch_status())) return st;
-    return run_ntt(ctx, w_hat, w_hat, nfilt, H, W, 0, false, stream);
+    // one pass: taps reduced and padded while staged into LDS, then the forward transform
+    return NttTable<2>::table[lh - 1][lw - 1](nullptr, w_hat, nfilt, ctx, 1, (hipStream_t)stream, w, kh, kw);
 }
 
 }  // extern "C"
