@@ -23,58 +23,15 @@
 #include <vector>
 
 #include "ensei_internal.hpp"
+#include "sched.hpp"
 
 namespace ensei {
 namespace {
 
 using Clock = std::chrono::steady_clock;
 
-constexpr size_t kAlign = 256;
-
-// First-fit allocator over [0, size) with coalescing of free neighbours.
-class Arena {
-   public:
-    void reset(size_t size) {
-        free_.clear();
-        if (size) free_[0] = size;
-        used_ = 0;
-    }
-    bool alloc(size_t n, size_t *off) {
-        n = (n + kAlign - 1) / kAlign * kAlign;
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second < n) continue;
-            *off = it->first;
-            const size_t rest = it->second - n, at = it->first + n;
-            free_.erase(it);
-            if (rest) free_[at] = rest;
-            used_ += n;
-            return true;
-        }
-        return false;
-    }
-    void release(size_t off, size_t n) {
-        n = (n + kAlign - 1) / kAlign * kAlign;
-        used_ -= n;
-        auto next = free_.lower_bound(off);
-        if (next != free_.end() && off + n == next->first) {
-            n += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == off) {
-                prev->second += n;
-                return;
-            }
-        }
-        free_[off] = n;
-    }
-    size_t used() const { return used_; }
-
-   private:
-    std::map<size_t, size_t> free_;
-    size_t used_ = 0;
-};
+using sched::Arena;
+using sched::kAlign;
 
 struct Shape {
     ensei_shape d;
@@ -249,17 +206,18 @@ void worker_loop(ensei_server *S) {
         // per free launch slot
         while (!S->queue.empty() && !S->free_slots.empty()) {
             Batch b;
-            while (!S->queue.empty() && (int)b.tickets.size() < S->max_batch) {
-                Request &q = S->reqs[S->queue.front()];
-                size_t off;
-                if (!S->arena.alloc(S->shapes[q.shape].footprint, &off)) break;
-                q.off = off;
+            const auto admitted = sched::next_batch(S->queue, S->arena, S->max_batch, [&](uint64_t t) {
+                return S->shapes[S->reqs[t].shape].footprint;
+            });
+            if (admitted.empty()) break;
+            const auto now = Clock::now();
+            for (const sched::Admitted &a : admitted) {
+                Request &q = S->reqs[a.ticket];
+                q.off = a.off;
                 q.state = kRunning;
-                q.t_start = Clock::now();
-                b.tickets.push_back(q.ticket);
-                S->queue.pop_front();
+                q.t_start = now;
+                b.tickets.push_back(a.ticket);
             }
-            if (b.tickets.empty()) break;
             if (S->arena.used() > S->peak_used) S->peak_used = S->arena.used();
             b.slot = S->free_slots.back();
             S->free_slots.pop_back();
