@@ -86,6 +86,105 @@ __device__ __forceinline__ void transpose4(uint32_t x0, uint32_t x1, uint32_t x2
     y3 = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
 }
 
+// Stores the 8 words res[rb][i] a lane holds after the contraction: rows
+// row0 + 8 g + 4 rb + i of output column col (g = lane / 16), into the block
+// rs addresses as [column][Cout]. Rows at or past Cout are not written.
+// WIDE_STORE (Cout even): 16-byte chunk c of lane row g (lanes 16 g + l16) is
+// X[c]; a 4 x 4 transpose across the lane rows (swap halves, then odd/even
+// rows) leaves X[q] = rows 8 q + 2 g, 8 q + 2 g + 1, so the four lane rows of
+// one column hold 64 contiguous bytes in each X[q], and store q writes them.
+// FULL_LINES: neighbouring lanes (the columns 2 p, 2 p + 1) first trade one
+// chunk per pair (X[2 m], X[2 m + 1]):
+// afterwards the even lane holds rows 16 m .. 16 m + 7 and the odd lane rows
+// 16 m + 8 .. 16 m + 15 of column 2 p for one store, and of column 2 p + 1
+// for the next, so every store instruction writes whole 128-byte lines
+// (half-line stores interleaved with a wave's own loads stream markedly
+// slower; where a kernel is not store-bound the exchange costs more than it
+// gains). col's parity must be the lane's. shuffle = false skips the
+// exchanges (for stores that the range check drops anyway).
+template <bool WIDE_STORE, bool FULL_LINES>
+__device__ __forceinline__ void store_lane_words(const uint64_t (&res)[2][4], __amdgpu_buffer_rsrc_t rs, int col,
+                                                 int row0, int g, int Cout, bool shuffle) {
+    const uint32_t col_off = (uint32_t)(col * Cout * 8);
+    if (WIDE_STORE) {
+        uint32_t X[4][4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint64_t w0 = res[c >> 1][2 * (c & 1)], w1 = res[c >> 1][2 * (c & 1) + 1];
+            X[c][0] = (uint32_t)w0;
+            X[c][1] = (uint32_t)(w0 >> 32);
+            X[c][2] = (uint32_t)w1;
+            X[c][3] = (uint32_t)(w1 >> 32);
+        }
+        if (shuffle) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const auto t = __builtin_amdgcn_permlane32_swap(X[c][d], X[c + 2][d], false, false);
+                    X[c][d] = t[0];
+                    X[c + 2][d] = t[1];
+                }
+#pragma unroll
+                for (int c = 0; c < 4; c += 2) {
+                    const auto t = __builtin_amdgcn_permlane16_swap(X[c][d], X[c + 1][d], false, false);
+                    X[c][d] = t[0];
+                    X[c + 1][d] = t[1];
+                }
+            }
+        }
+        if (!FULL_LINES) {
+            const int o = row0 + 2 * g;  // + 8 q: rows of store q
+            const uint32_t off = col_off + (uint32_t)(o * 8);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const u32x4 d = {X[q][0], X[q][1], X[q][2], X[q][3]};
+                __builtin_amdgcn_raw_buffer_store_b128(d, rs, (int)(o + 8 * q < Cout ? off + 64 * q : 0x80000000u), 0,
+                                                       0);
+            }
+            return;
+        }
+        const bool odd = col & 1;
+        if (shuffle) {
+#pragma unroll
+            for (int m = 0; m < 2; ++m)
+#pragma unroll
+                for (int d = 0; d < 4; ++d) {
+                    // even lane sends X[2m + 1] and receives the odd lane's X[2m]
+                    const uint32_t send = odd ? X[2 * m][d] : X[2 * m + 1][d];
+                    const uint32_t recv = (uint32_t)__builtin_amdgcn_mov_dpp((int)send, 0xB1, 0xF, 0xF, false);
+                    if (odd)
+                        X[2 * m][d] = recv;
+                    else
+                        X[2 * m + 1][d] = recv;
+                }
+        }
+        // store 2 m + h: column (col & ~1) + h, rows 16 m + 8 (col & 1) + 2 g, + 1
+        const int o = row0 + 8 * (int)odd + 2 * g;
+        const uint32_t pair_off = (uint32_t)((col & ~1) * Cout * 8) + (uint32_t)(o * 8);
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                // X[2m + h] holds column (col & ~1) + h in both lanes of the pair
+                const int q = 2 * m + h;
+                const u32x4 d = {X[q][0], X[q][1], X[q][2], X[q][3]};
+                __builtin_amdgcn_raw_buffer_store_b128(
+                    d, rs,
+                    (int)(o + 16 * m < Cout ? pair_off + (uint32_t)(h * Cout * 8) + 128u * m : 0x80000000u), 0, 0);
+            }
+    } else {
+        const int o = row0 + 8 * g;
+        const uint32_t off = col_off + (uint32_t)(o * 8);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const uint64_t w = res[q >> 2][q & 3];
+            const u32x2 d = {(unsigned)w, (unsigned)(w >> 32)};
+            __builtin_amdgcn_raw_buffer_store_b64(d, rs, (int)(o + q < Cout ? off + 8 * q : 0x80000000u), 0, 0);
+        }
+    }
+}
+
 // Position of one work unit: layer L, global tile t, and within the layer's
 // tile the row tile ot, column tile jt, K step ks, frequency f and image b.
 struct HcCoord {
@@ -337,63 +436,13 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
     // 8 output words of this lane: tile rows out_row + 4 rb + i of column b_col
     auto store_out = [&](const uint64_t (&res)[2][4], bool valid) {
         const HcLayer P = layer(cur.L);
-        const int Cout = P.Cout;
         const int64_t F = P.F, rowlen = (int64_t)P.n + 1;
-        const uint32_t out_col_bytes = (uint32_t)(Cout * 8);  // one output word index j
-        const uint64_t *blk = P.ct_out + ((cur.b * F + cur.f) * rowlen + cur.jt * 64) * Cout;
+        const uint64_t *blk = P.ct_out + ((cur.b * F + cur.f) * rowlen + cur.jt * 64) * P.Cout;
         // columns past n fall outside the block and are dropped
-        const uint32_t nbytes = valid ? (uint32_t)((rowlen - cur.jt * 64) * Cout * 8) : 0u;
+        const uint32_t nbytes = valid ? (uint32_t)((rowlen - cur.jt * 64) * P.Cout * 8) : 0u;
         const __amdgpu_buffer_rsrc_t rs =
             make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(blk)), __builtin_amdgcn_readfirstlane(nbytes));
-        if (WIDE_STORE) {
-            // 16-byte chunk c of lane row g (lanes 16 g + l16) is X[c]; a 4 x 4
-            // transpose across the lane rows (swap halves, then odd/even rows)
-            // leaves X[q] = chunk g of lane row q, so store q of the four lane
-            // rows of one column covers 64 contiguous bytes
-            uint32_t X[4][4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const uint64_t w0 = res[c >> 1][2 * (c & 1)], w1 = res[c >> 1][2 * (c & 1) + 1];
-                X[c][0] = (uint32_t)w0;
-                X[c][1] = (uint32_t)(w0 >> 32);
-                X[c][2] = (uint32_t)w1;
-                X[c][3] = (uint32_t)(w1 >> 32);
-            }
-            if (valid) {  // (a unit that stores nothing skips the shuffle; its stores are dropped)
-#pragma unroll
-            for (int d = 0; d < 4; ++d) {
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    const auto t = __builtin_amdgcn_permlane32_swap(X[c][d], X[c + 2][d], false, false);
-                    X[c][d] = t[0];
-                    X[c + 2][d] = t[1];
-                }
-#pragma unroll
-                for (int c = 0; c < 4; c += 2) {
-                    const auto t = __builtin_amdgcn_permlane16_swap(X[c][d], X[c + 1][d], false, false);
-                    X[c][d] = t[0];
-                    X[c + 1][d] = t[1];
-                }
-            }
-            }
-            const int o = cur.ot * 64 + 32 * rg + 2 * g;  // + 8 q: rows of store q
-            const uint32_t off = (uint32_t)(b_col * out_col_bytes + o * 8);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const u32x4 d = {X[q][0], X[q][1], X[q][2], X[q][3]};
-                __builtin_amdgcn_raw_buffer_store_b128(d, rs, (int)(o + 8 * q < Cout ? off + 64 * q : 0x80000000u), 0,
-                                                       0);
-            }
-        } else {
-            const int o = cur.ot * 64 + out_row;
-            const uint32_t off = (uint32_t)(b_col * out_col_bytes + o * 8);
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const uint64_t w = res[q >> 2][q & 3];
-                const u32x2 d = {(unsigned)w, (unsigned)(w >> 32)};
-                __builtin_amdgcn_raw_buffer_store_b64(d, rs, (int)(o + q < Cout ? off + 8 * q : 0x80000000u), 0, 0);
-            }
-        }
+        store_lane_words<WIDE_STORE, false>(res, rs, b_col, cur.ot * 64 + 32 * rg, g, P.Cout, valid);
     };
 
     // two units in flight from the start; the entry issues the same load and
@@ -498,6 +547,208 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
         body(buf1, 1);
     }
     if (n_units & 1) body(buf0, 0);
+}
+
+// Narrow-input HomConv (Cin <= kNarrowCin, folded weight fragments): with so
+// few input channels the launch is a write stream (8 (n+1) Cout bytes out per
+// 8 (n+1) Cin in), so nothing here waits on other waves. Each wave walks its
+// own units (b, f, row tile ot, 16 columns j): it loads the Cin words of its
+// lane's column itself, forms the MFMA's digit operand in registers (lane
+// group g needs digit plane s - g of each channel for shift s, which is byte s
+// of the balanced digits shifted up by g bytes), and contracts all 64 rows of
+// the tile, 32 at a time. The words and mask of the next DEPTH - 1 units are
+// in flight meanwhile: a wave's memory counter retires in issue order, so
+// waiting for a unit's words also waits for every store issued before them,
+// and the depth sets how many units of stores stay in flight. Weight
+// fragments stay in registers while the unit's (f, ot) does not change;
+// masks are fetched one per lane and handed to the lanes holding the b word
+// by a cross-lane read. No LDS, no barrier.
+constexpr int kNarrowThreads = 256;
+constexpr int kNarrowCin = 8;     // widest input the narrow kernel takes
+constexpr int kNarrowDepth = 4;  // units in flight per wave
+
+template <int NCH, int DEPTH, bool WIDE_STORE>
+__global__ __launch_bounds__(kNarrowThreads) void homconv_narrow_kernel(HcLayer P, uint64_t delta) {
+    static_assert(NCH % 4 == 0 && NCH <= 16 && DEPTH >= 2, "one 16-channel group");
+    constexpr int kWaves = kNarrowThreads / 64;
+    constexpr uint64_t kBias = 0x8080808080808080ull;
+    const int lane = threadIdx.x & 63, g = lane >> 4, l16 = lane & 15;
+    const int64_t W = (int64_t)gridDim.x * kWaves;
+    const int64_t gw = (int64_t)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int Cin = P.Cin, Cout = P.Cout, n_ot = P.n_ot;
+    const int64_t F = P.F, rowlen = (int64_t)P.n + 1;
+    const int n_jb = (int)((rowlen + 15) / 16);
+    const int64_t total = P.B * F * n_ot * n_jb;
+
+    // this wave's units: one contiguous range (its output is one contiguous
+    // stretch of ct_out when Cout <= 64)
+    const int64_t per = total / W, extra = total % W;
+    const int64_t u_lo = gw * per + (gw < extra ? gw : extra);
+    const int64_t n_units = per + (gw < extra ? 1 : 0);
+    if (n_units <= 0) return;
+
+    struct Coord {
+        int jb, ot;
+        int64_t f, b;
+    };
+    // units in order: columns fastest, then row tiles, frequencies, images
+    auto seek = [&](Coord &c, int64_t u) {
+        c.jb = (int)(u % n_jb);
+        int64_t x = u / n_jb;
+        c.ot = (int)(x % n_ot);
+        x /= n_ot;
+        c.f = x % F;
+        c.b = x / F;
+    };
+    auto advance = [&](Coord &c) {
+        if (++c.jb < n_jb) return;
+        c.jb = 0;
+        if (++c.ot < n_ot) return;
+        c.ot = 0;
+        if (++c.f < F) return;
+        c.f = 0;
+        ++c.b;
+    };
+
+    // a unit in flight: the lane's input words and one mask word
+    struct Buf {
+        uint64_t v[NCH];
+        uint32_t r;
+    };
+    auto issue = [&](const Coord &c, Buf &buf) {
+        const uint8_t *blk =
+            uniform_ptr(reinterpret_cast<const uint8_t *>(P.ct_in + (c.b * F + c.f) * rowlen * Cin));
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(blk, (uint32_t)(rowlen * Cin * 8));
+        const uint32_t col = (uint32_t)(c.jb * 16 + l16);
+        // lane group 3 pairs the zero weight limb: it needs no words; columns
+        // past n read zero
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch) {
+            const uint32_t off = ch < Cin && g < 3 ? (col * (uint32_t)Cin + ch) * 8 : 0x80000000u;
+            const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
+            buf.v[ch] = (uint64_t)t.y << 32 | t.x;
+        }
+        // masks: only the column block holding the b word (j = n) reads them
+        const int o = c.ot * 64 + lane;
+        const __amdgpu_buffer_rsrc_t rr =
+            make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(P.r + c.b * Cout * F + c.f)),
+                      c.jb == n_jb - 1 ? (uint32_t)(((int64_t)(Cout - 1) * F + 1) * 4) : 0u);
+        buf.r = __builtin_amdgcn_raw_buffer_load_b32(rr, (int)(o < Cout ? (uint32_t)(o * F * 4) : 0x80000000u), 0, 0);
+    };
+
+    Coord cur, nx;
+    seek(cur, u_lo);
+    v4i A[4];
+    int64_t a_key = -1;  // (f, ot) whose weight fragments A holds
+
+    // DEPTH units in flight from the start; the entry issues the same loads
+    // and stores as every unit (stores out of range) so that the waits at the
+    // loop head see one static count on both incoming paths
+    Buf bufs[DEPTH];
+    const uint64_t none[2][4] = {};
+    const __amdgpu_buffer_rsrc_t no_store = make_rsrc(P.ct_out, 0u);
+    nx = cur;
+    int64_t issued = 1;
+#pragma unroll
+    for (int k = 0; k < DEPTH; ++k) {
+        if (k > 0 && issued < n_units) {
+            advance(nx);
+            ++issued;
+        }
+        issue(nx, bufs[k]);
+        store_lane_words<WIDE_STORE, true>(none, no_store, 0, 0, g, Cout, false);
+        store_lane_words<WIDE_STORE, true>(none, no_store, 0, 0, g, Cout, false);
+    }
+
+    auto body = [&](Buf &buf) {
+        // a new (f, ot): its weight fragments [row block 4][lane 64] x 16 B
+        const int64_t key = cur.f * n_ot + cur.ot;
+        if (key != a_key) {
+            const __amdgpu_buffer_rsrc_t ra = make_rsrc(
+                uniform_ptr(reinterpret_cast<const uint8_t *>(P.w_pack) + key * (int64_t)P.n_items * 16), 4096u);
+#pragma unroll
+            for (int rbg = 0; rbg < 4; ++rbg) {
+                const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(ra, (rbg * 64 + lane) * 16, 0, 0);
+                A[rbg] = v4i{(int)t.x, (int)t.y, (int)t.z, (int)t.w};
+            }
+            // wait here, on this rare path: left pending past the branch, the
+            // fragments would make every unit wait for them (and for all
+            // stores issued before them)
+            __builtin_amdgcn_s_waitcnt(0);
+            a_key = key;
+        }
+        const uint32_t rv = buf.r;
+        // digit operand of shift s: dword q holds digit s - g of channels 4q..4q+3
+        uint32_t pl[NCH / 4][8];
+#pragma unroll
+        for (int q = 0; q < NCH / 4; ++q) {
+            uint32_t lo[4], hi[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const uint64_t d = ((buf.v[4 * q + i] + kBias) ^ kBias) << (8 * g);
+                lo[i] = (uint32_t)d;
+                hi[i] = (uint32_t)(d >> 32);
+            }
+            transpose4(lo[0], lo[1], lo[2], lo[3], pl[q][0], pl[q][1], pl[q][2], pl[q][3]);
+            transpose4(hi[0], hi[1], hi[2], hi[3], pl[q][4], pl[q][5], pl[q][6], pl[q][7]);
+        }
+
+        // the unit DEPTH ahead reuses this buffer (past the end: reissue the
+        // last one, keeping the load count static)
+        if (issued < n_units) {
+            advance(nx);
+            ++issued;
+        }
+        issue(nx, buf);
+
+        const uint64_t *blk = P.ct_out + ((cur.b * F + cur.f) * rowlen + cur.jb * 16) * Cout;
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(blk)),
+                                                    (uint32_t)((rowlen - cur.jb * 16) * Cout * 8));
+        const bool has_b = cur.jb == n_jb - 1;
+        const bool b_lane = cur.jb * 16 + l16 == P.n;
+        const v4i zero = {0, 0, 0, 0};
+#pragma unroll
+        for (int rg = 0; rg < 2; ++rg) {
+            v4i acc[8][2];
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const v4i B = {(int)pl[0][s], NCH > 4 ? (int)pl[NCH > 4 ? 1 : 0][s] : 0,
+                               NCH > 8 ? (int)pl[NCH > 8 ? 2 : 0][s] : 0, NCH > 12 ? (int)pl[NCH > 12 ? 3 : 0][s] : 0};
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb)
+                    acc[s][rb] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[2 * rg + rb], B, zero, 0, 0, 0);
+            }
+            uint64_t res[2][4];
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    res[rb][i] = recombine<true>(acc[0][rb][i], acc[1][rb][i], acc[2][rb][i], acc[3][rb][i],
+                                                 acc[4][rb][i], acc[5][rb][i], acc[6][rb][i], acc[7][rb][i]);
+            // HomShare: Delta * r on the b word; the mask of tile row x is in lane x
+            if (has_b) {
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const uint32_t m =
+                            (uint32_t)__builtin_amdgcn_ds_bpermute((32 * rg + 8 * g + 4 * rb + i) * 4, (int)rv);
+                        if (b_lane) res[rb][i] += delta * (uint64_t)m;
+                    }
+            }
+            store_lane_words<WIDE_STORE, true>(res, rs, l16, cur.ot * 64 + 32 * rg, g, Cout, true);
+        }
+        advance(cur);
+    };
+
+    for (int64_t it = 0; it < n_units / DEPTH; ++it) {
+#pragma unroll
+        for (int k = 0; k < DEPTH; ++k) body(bufs[k]);
+    }
+    const int rem = (int)(n_units % DEPTH);
+#pragma unroll
+    for (int k = 0; k < DEPTH - 1; ++k)
+        if (k < rem) body(bufs[k]);
 }
 
 // Weight-fragment item k (16 bytes) of the unit (f, ks, ot): the operand one
@@ -672,9 +923,36 @@ int homconv_problem(const ensei_ctx *ctx, HcLayer *P, const uint64_t *ct_in, con
     return ENSEI_OK;
 }
 
+// Narrow kernel launch: enough 4-wave workgroups to fill every CU at the
+// kernel's occupancy (each wave walks its own contiguous range of units).
+template <int NCH>
+static int launch_narrow(const ensei_ctx *ctx, const HcLayer &P, HcSchedule sched, hipStream_t stream) {
+    const bool wide = P.Cout % 2 == 0;
+    auto kernel = wide ? homconv_narrow_kernel<NCH, kNarrowDepth, true> : homconv_narrow_kernel<NCH, kNarrowDepth, false>;
+    static int resident[2] = {0, 0};  // workgroups per CU, by store width
+    int per_cu = resident[wide];
+    if (per_cu == 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kNarrowThreads, 0) != hipSuccess || per_cu < 1)
+            per_cu = 1;
+        resident[wide] = per_cu;
+    }
+    const int64_t units = P.B * P.F * P.n_ot * ((P.n + 1 + 15) / 16);
+    int64_t blocks = sched.blocks > 0 ? sched.blocks : (int64_t)ctx->num_cus * per_cu;
+    const int64_t needed = (units + kNarrowThreads / 64 - 1) / (kNarrowThreads / 64);
+    if (blocks > needed) blocks = needed;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kNarrowThreads), 0, stream, P, ctx->delta);
+    return launch_status();
+}
+
 int homconv_launch(const ensei_ctx *ctx, const HcLayer *problems, const HcLayer *dev_table, int nlayers, bool paired,
                    HcSchedule sched, hipStream_t stream) {
     if (nlayers < 1 || (nlayers > 1 && (!dev_table || !paired))) return ENSEI_ERR_ARG;
+    if (sched.chunk < 0) return ENSEI_ERR_ARG;
+    if (nlayers == 1 && !paired && problems[0].Cin <= kNarrowCin) {
+        const int Cin = problems[0].Cin;
+        return Cin <= 4 ? launch_narrow<4>(ctx, problems[0], sched, stream)
+                        : launch_narrow<8>(ctx, problems[0], sched, stream);
+    }
     int64_t total = 0;
     bool wide = true;
     for (int L = 0; L < nlayers; ++L) {
@@ -685,7 +963,6 @@ int homconv_launch(const ensei_ctx *ctx, const HcLayer *problems, const HcLayer 
     int64_t blocks = sched.blocks > 0 ? sched.blocks : ctx->num_cus;
     if (blocks > ctx->num_cus) blocks = ctx->num_cus;
     if (sched.chunk == 0 && total < blocks) blocks = total;
-    if (sched.chunk < 0) return ENSEI_ERR_ARG;
     if (nlayers > 1) {
         auto kernel = wide ? homconv_mfma_kernel<true, true, true> : homconv_mfma_kernel<true, false, true>;
         hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kHcThreads), 0, stream, problems[0], dev_table, nlayers,

@@ -163,6 +163,50 @@ def test_homconv_valu(ctx, orc, B, Cin, Cout, F, n):
     assert np.array_equal(got, orc.homconv(ct, w, r, P))
 
 
+# Inputs of at most 16 channels take the narrow kernel (one wave per unit of
+# 16 words, no LDS): channel counts of each of its widths, odd Cout (8-byte
+# stores), several row tiles, the b word first, last or alone in its 16-word
+# block, and wave ranges long enough to cross frequency and image boundaries
+# (the weight fragments held in registers must be replaced there).
+NARROW_CASES = [
+    # B, Cin, Cout, F, n
+    (1, 1, 64, 3, 15),
+    (1, 2, 7, 2, 16),
+    (2, 3, 64, 5, 100),
+    (1, 4, 130, 3, 47),
+    (1, 5, 33, 4, 64),
+    (2, 8, 64, 7, 31),
+    (1, 9, 20, 3, 200),
+    (1, 16, 96, 2, 70),
+    (1, 3, 64, 1024, 255),
+    (4, 3, 64, 256, 1024),
+    (3, 7, 10, 600, 33),
+]
+
+
+@pytest.mark.parametrize("B,Cin,Cout,F,n", NARROW_CASES)
+def test_homconv_narrow(ctx, orc, B, Cin, Cout, F, n):
+    ct, w, r = _homconv_inputs(B, Cin, Cout, F, n, 41 * Cin + Cout + n)
+    ref = orc.homconv(ct, w, r, P)
+    got = host(ctx.homconv(dev(ct), ctx.pack_weights(dev(w)), dev(r), Cout))
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("Cin", [3, 16])
+def test_homconv_narrow_extreme_digits(ctx, orc, Cin):
+    """Digits -128 and +127 against limbs -128, -127, 1 and p - 1 on the narrow kernel."""
+    B, Cout, F, n = 2, 64, 3, 40
+    ct = np.full((B, F, n + 1, Cin), 0x7F7F7F7F7F7F7F80, dtype=np.uint64)
+    ct[:, :, 1::2, : (Cin + 1) // 2] = 0x7F7F7F7F7F7F7F7F
+    ct[:, :, ::5, :] = 2**64 - 1
+    w = np.full((Cout, Cin, F), 0x8080, dtype=np.uint32)
+    w[1::3] = P - 1
+    r = np.full((B, Cout, F), P - 1, dtype=np.uint32)
+    ref = orc.homconv(ct, w, r, P)
+    got = host(ctx.homconv(dev(ct), ctx.pack_weights(dev(w)), dev(r), Cout))
+    assert np.array_equal(got, ref)
+
+
 def test_homconv_extreme_words(ctx, orc):
     """All-ones words and W^ = p-1 maximise every limb sum."""
     B, Cin, Cout, F, n = 1, 70, 20, 2, 66
