@@ -40,8 +40,8 @@ HOMCONV_SRC = os.path.join(ROOT, "paper_2003_05328_amd", "csrc", "homconv.hip")
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--homconv", choices=["mfma", "valu"], default="mfma",
                     help="HomConv kernel: matrix-core (ensei_homconv) or vector-ALU comparison (ensei_homconv_valu)")

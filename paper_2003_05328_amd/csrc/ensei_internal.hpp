@@ -83,6 +83,10 @@ struct HcSchedule {
 };
 
 constexpr int kPairedCin = 48;  // ensei_homconv's paired limb scheme from this many input channels on
+// Inputs this narrow run on their own barrier-free kernel (folded fragments),
+// launched as a single problem; batched launches keep them out of the
+// multi-problem table.
+constexpr int kNarrowCin = 8;
 
 // 16-byte weight-fragment items per (f, K step, row tile) unit of each scheme
 inline int frag_items(int Cin, bool paired) { return paired ? 768 : 256 * ((Cin + 15) / 16); }

@@ -43,6 +43,10 @@ typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kPlaneBytes = 64 * 4 * 16;  // one digit plane: 64 columns x 4 channel groups x 16 bytes
 constexpr uint32_t kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9 family)
+// Cache policy of a streaming store: non-temporal (the line is not kept in
+// the caches for reuse). A write stream issued this way no longer delays the
+// reads that the same waves interleave with it.
+constexpr int kStoreStream = 2;
 
 // Raw buffer descriptor over [base, base + nbytes): accesses at or past nbytes
 // read zero / are dropped by the hardware range check.
@@ -101,8 +105,9 @@ __device__ __forceinline__ void transpose4(uint32_t x0, uint32_t x1, uint32_t x2
 // (half-line stores interleaved with a wave's own loads stream markedly
 // slower; where a kernel is not store-bound the exchange costs more than it
 // gains). col's parity must be the lane's. shuffle = false skips the
-// exchanges (for stores that the range check drops anyway).
-template <bool WIDE_STORE, bool FULL_LINES>
+// exchanges (for stores that the range check drops anyway). CPOL is the
+// stores' cache policy (kStoreStream: non-temporal).
+template <bool WIDE_STORE, bool FULL_LINES, int CPOL>
 __device__ __forceinline__ void store_lane_words(const uint64_t (&res)[2][4], __amdgpu_buffer_rsrc_t rs, int col,
                                                  int row0, int g, int Cout, bool shuffle) {
     const uint32_t col_off = (uint32_t)(col * Cout * 8);
@@ -140,7 +145,7 @@ __device__ __forceinline__ void store_lane_words(const uint64_t (&res)[2][4], __
             for (int q = 0; q < 4; ++q) {
                 const u32x4 d = {X[q][0], X[q][1], X[q][2], X[q][3]};
                 __builtin_amdgcn_raw_buffer_store_b128(d, rs, (int)(o + 8 * q < Cout ? off + 64 * q : 0x80000000u), 0,
-                                                       0);
+                                                       CPOL);
             }
             return;
         }
@@ -171,7 +176,7 @@ __device__ __forceinline__ void store_lane_words(const uint64_t (&res)[2][4], __
                 const u32x4 d = {X[q][0], X[q][1], X[q][2], X[q][3]};
                 __builtin_amdgcn_raw_buffer_store_b128(
                     d, rs,
-                    (int)(o + 16 * m < Cout ? pair_off + (uint32_t)(h * Cout * 8) + 128u * m : 0x80000000u), 0, 0);
+                    (int)(o + 16 * m < Cout ? pair_off + (uint32_t)(h * Cout * 8) + 128u * m : 0x80000000u), 0, CPOL);
             }
     } else {
         const int o = row0 + 8 * g;
@@ -180,7 +185,7 @@ __device__ __forceinline__ void store_lane_words(const uint64_t (&res)[2][4], __
         for (int q = 0; q < 8; ++q) {
             const uint64_t w = res[q >> 2][q & 3];
             const u32x2 d = {(unsigned)w, (unsigned)(w >> 32)};
-            __builtin_amdgcn_raw_buffer_store_b64(d, rs, (int)(o + q < Cout ? off + 8 * q : 0x80000000u), 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b64(d, rs, (int)(o + q < Cout ? off + 8 * q : 0x80000000u), 0, CPOL);
         }
     }
 }
@@ -442,7 +447,7 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
         const uint32_t nbytes = valid ? (uint32_t)((rowlen - cur.jt * 64) * P.Cout * 8) : 0u;
         const __amdgpu_buffer_rsrc_t rs =
             make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(blk)), __builtin_amdgcn_readfirstlane(nbytes));
-        store_lane_words<WIDE_STORE, false>(res, rs, b_col, cur.ot * 64 + 32 * rg, g, P.Cout, valid);
+        store_lane_words<WIDE_STORE, false, 0>(res, rs, b_col, cur.ot * 64 + 32 * rg, g, P.Cout, valid);
     };
 
     // two units in flight from the start; the entry issues the same load and
@@ -564,7 +569,6 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
 // masks are fetched one per lane and handed to the lanes holding the b word
 // by a cross-lane read. No LDS, no barrier.
 constexpr int kNarrowThreads = 256;
-constexpr int kNarrowCin = 8;     // widest input the narrow kernel takes
 constexpr int kNarrowDepth = 4;  // units in flight per wave
 
 template <int NCH, int DEPTH, bool WIDE_STORE>
@@ -656,8 +660,8 @@ __global__ __launch_bounds__(kNarrowThreads) void homconv_narrow_kernel(HcLayer 
             ++issued;
         }
         issue(nx, bufs[k]);
-        store_lane_words<WIDE_STORE, true>(none, no_store, 0, 0, g, Cout, false);
-        store_lane_words<WIDE_STORE, true>(none, no_store, 0, 0, g, Cout, false);
+        store_lane_words<WIDE_STORE, true, kStoreStream>(none, no_store, 0, 0, g, Cout, false);
+        store_lane_words<WIDE_STORE, true, kStoreStream>(none, no_store, 0, 0, g, Cout, false);
     }
 
     auto body = [&](Buf &buf) {
@@ -736,7 +740,7 @@ __global__ __launch_bounds__(kNarrowThreads) void homconv_narrow_kernel(HcLayer 
                         if (b_lane) res[rb][i] += delta * (uint64_t)m;
                     }
             }
-            store_lane_words<WIDE_STORE, true>(res, rs, l16, cur.ot * 64 + 32 * rg, g, Cout, true);
+            store_lane_words<WIDE_STORE, true, kStoreStream>(res, rs, l16, cur.ot * 64 + 32 * rg, g, Cout, true);
         }
         advance(cur);
     };

@@ -14,7 +14,8 @@ struct ensei_plan {
     std::vector<ensei_layer> layers;
     std::vector<uint32_t *> w_hat;
     std::vector<int8_t *> w_pack;
-    std::vector<ensei::HcLayer> problems;
+    std::vector<ensei::HcLayer> problems;  // in the one persistent launch
+    std::vector<ensei::HcLayer> narrow;    // narrow-input layers, each on its own kernel
     ensei::HcLayer *d_table = nullptr;
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -70,10 +71,16 @@ int run_back(ensei_plan *P, hipStream_t st) {
 }
 
 int run_homconv(ensei_plan *P, HcSchedule s, hipStream_t st) {
-    return homconv_launch(P->ctx, P->problems.data(), P->d_table, (int)P->problems.size(), true, s, st);
+    int rc = P->problems.empty()
+                 ? ENSEI_OK
+                 : homconv_launch(P->ctx, P->problems.data(), P->d_table, (int)P->problems.size(), true, s, st);
+    for (const HcLayer &h : P->narrow)
+        if (!rc) rc = homconv_launch(P->ctx, &h, nullptr, 1, false, HcSchedule{0, 0}, st);
+    return rc;
 }
 
-// Cache key: device, modulus and every layer's HomConv shape.
+// Cache key: device, modulus and the HomConv shape of every layer in the
+// shared persistent launch.
 std::string plan_key(const ensei_plan *P) {
     hipDeviceProp_t prop;
     char buf[160];
@@ -161,7 +168,7 @@ int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, co
         return ENSEI_ERR_HIP;
     }
     // server setup: transformed and packed filters (paired layout for every
-    // layer, so that all of them run in the same persistent kernel)
+    // layer of the shared persistent launch, folded for narrow inputs)
     int64_t tile0 = 0;
     for (const ensei_layer &l : P->layers) {
         if (l.H <= 0 || l.W <= 0 || l.Cin <= 0 || l.Cout <= 0 || l.batch <= 0) {
@@ -169,9 +176,10 @@ int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, co
             return ENSEI_ERR_ARG;
         }
         const int64_t F = (int64_t)l.H * l.W;
+        const bool narrow = l.Cin <= kNarrowCin;
         uint32_t *wh = nullptr;
         int8_t *wp = nullptr;
-        const size_t wpb = wpack_bytes_as(l.Cout, l.Cin, F, true);
+        const size_t wpb = wpack_bytes_as(l.Cout, l.Cin, F, !narrow);
         if (hipMalloc(&wh, (size_t)l.Cout * l.Cin * F * 4) != hipSuccess) wh = nullptr;
         if (wh && hipMalloc(&wp, wpb) != hipSuccess) wp = nullptr;
         if (wh) P->w_hat.push_back(wh);
@@ -181,12 +189,16 @@ int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, co
             return ENSEI_ERR_HIP;
         }
         rc = ensei_weight_prep(ctx, l.w, l.Cout, l.Cin, l.kh, l.kw, l.H, l.W, wh, P->stream);
-        if (!rc) rc = pack_weights_as(ctx, wh, l.Cout, l.Cin, F, true, wp, P->stream);
+        if (!rc) rc = pack_weights_as(ctx, wh, l.Cout, l.Cin, F, !narrow, wp, P->stream);
         HcLayer h;
         if (!rc) rc = homconv_problem(ctx, &h, l.ct_in, wp, l.r, l.batch, l.Cin, l.Cout, F, l.n, l.ct_out, wpb);
         if (rc) {
             release(P);
             return rc;
+        }
+        if (narrow) {
+            P->narrow.push_back(h);
+            continue;
         }
         h.n_items = frag_items(l.Cin, true);
         h.tile0 = tile0;
@@ -194,12 +206,12 @@ int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, co
         P->problems.push_back(h);
     }
     const size_t tb = P->problems.size() * sizeof(HcLayer);
-    if (hipMalloc(&P->d_table, tb) != hipSuccess) {
+    if (tb && hipMalloc(&P->d_table, tb) != hipSuccess) {
         P->d_table = nullptr;
         release(P);
         return ENSEI_ERR_HIP;
     }
-    if (hipMemcpyAsync(P->d_table, P->problems.data(), tb, hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+    if ((tb && hipMemcpyAsync(P->d_table, P->problems.data(), tb, hipMemcpyHostToDevice, P->stream) != hipSuccess) ||
         hipStreamSynchronize(P->stream) != hipSuccess) {
         release(P);
         return ENSEI_ERR_HIP;
@@ -219,7 +231,14 @@ int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, co
     const std::string key = plan_key(P);
     HcSchedule best{ctx->num_cus, 0};
     double best_us = 0;
-    if (tune_cache && cache_lookup(tune_cache, key, &best)) {
+    if (P->problems.empty()) {
+        // nothing to schedule: narrow-input layers only
+        rc = time_schedule(P, best, &best_us);
+        if (rc) {
+            release(P);
+            return rc;
+        }
+    } else if (tune_cache && cache_lookup(tune_cache, key, &best)) {
         P->info.from_cache = 1;
     } else {
         const int64_t chunks[] = {0, 1, 4, 16, 64, 256};

@@ -40,6 +40,7 @@ struct Shape {
     int8_t *w_pack = nullptr;
     size_t wpack_bytes = 0;
     size_t footprint = 0;  // arena bytes of one request
+    bool narrow = false;   // HomConv on the narrow-input kernel, outside the batch's shared launch
 };
 
 enum ReqState { kQueued = 0, kRunning = 1, kDone = 2, kFailed = 3 };
@@ -139,7 +140,9 @@ int launch_batch(ensei_server *S, Batch &b) {
         if (!rc)
             rc = homconv_problem(S->ctx, &h, ct_in, sh.w_pack, q.io.r, 1, d.Cin, d.Cout, sh.F, d.n, ct_out,
                                  sh.wpack_bytes);
+        if (!rc && sh.narrow) rc = homconv_launch(S->ctx, &h, nullptr, 1, false, HcSchedule{0, 0}, st);
         if (rc) break;
+        if (sh.narrow) continue;
         h.n_items = frag_items(d.Cin, true);
         h.tile0 = tile0;
         tile0 += h.n_tiles;
@@ -150,7 +153,7 @@ int launch_batch(ensei_server *S, Batch &b) {
         if (hipMemcpyAsync(dtab, tab, np * sizeof(HcLayer), hipMemcpyHostToDevice, st) != hipSuccess)
             rc = ENSEI_ERR_HIP;
         if (!rc) rc = homconv_launch(S->ctx, tab, dtab, np, true, HcSchedule{0, 0}, st);
-    } else if (!rc) {
+    } else if (!rc && np == 1) {
         rc = homconv_launch(S->ctx, tab, nullptr, 1, true, HcSchedule{0, 0}, st);
     }
     for (uint64_t t : b.tickets) {
@@ -336,7 +339,8 @@ int ensei_server_add_shape(ensei_server *S, const ensei_shape *shape, const int3
     sh.F = (int64_t)d.H * d.W;
     sh.footprint = parts_of(d).total;
     if (sh.footprint > S->budget) return ENSEI_ERR_LIMIT;
-    sh.wpack_bytes = wpack_bytes_as(d.Cout, d.Cin, sh.F, true);
+    sh.narrow = d.Cin <= kNarrowCin;
+    sh.wpack_bytes = wpack_bytes_as(d.Cout, d.Cin, sh.F, !sh.narrow);
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(S->ctx->device);
@@ -350,7 +354,7 @@ int ensei_server_add_shape(ensei_server *S, const ensei_shape *shape, const int3
         rc = ENSEI_ERR_HIP;
     }
     if (!rc) rc = ensei_weight_prep(S->ctx, w, d.Cout, d.Cin, d.kh, d.kw, d.H, d.W, sh.w_hat, st);
-    if (!rc) rc = pack_weights_as(S->ctx, sh.w_hat, d.Cout, d.Cin, sh.F, true, sh.w_pack, st);
+    if (!rc) rc = pack_weights_as(S->ctx, sh.w_hat, d.Cout, d.Cin, sh.F, !sh.narrow, sh.w_pack, st);
     if (st) {
         if (!rc && hipStreamSynchronize(st) != hipSuccess) rc = ENSEI_ERR_HIP;
         (void)hipStreamDestroy(st);

@@ -13,7 +13,7 @@ from tests.gpu_helpers import P, dev, host
 
 pytestmark = pytest.mark.gpu
 
-# uneven shapes: narrow input (folded-size Cin run through the paired layout),
+# uneven shapes: a narrow input (its own kernel beside the shared launch),
 # several K steps, several row tiles, a ragged column tile
 STACK = [
     LayerShape(H=8, W=8, Cin=3, Cout=16, kh=3, kw=3, n=70, B=2),
@@ -23,6 +23,11 @@ STACK = [
 STACK_ODD = [
     LayerShape(H=8, W=4, Cin=5, Cout=17, kh=2, kw=3, n=33, B=1),
     LayerShape(H=4, W=4, Cin=48, Cout=9, kh=3, kw=3, n=129, B=3),
+]
+# narrow inputs only: no layer in the shared persistent launch
+STACK_NARROW = [
+    LayerShape(H=8, W=8, Cin=3, Cout=64, kh=3, kw=3, n=70, B=2),
+    LayerShape(H=4, W=4, Cin=8, Cout=130, kh=3, kw=3, n=40, B=1),
 ]
 
 
@@ -93,6 +98,17 @@ def test_plan_matches_single_calls_and_oracle(ctx, orc, tmp_path, stack):
     plan2 = Plan(ctx, [l for _, l in layers], tune_cache=str(tmp_path / "tune.txt"))
     assert plan2.schedule()["from_cache"] and plan2.schedule()["chunk"] == sch["chunk"]
     plan2.close()
+    plan.close()
+
+
+def test_plan_of_narrow_layers_only(ctx, orc, tmp_path):
+    layers = [_layer(ctx, S, 150 + i) for i, S in enumerate(STACK_NARROW)]
+    plan = Plan(ctx, [l for _, l in layers], tune_cache=str(tmp_path / "tune.txt"))
+    assert not plan.schedule()["from_cache"]
+    plan.run()
+    torch.cuda.synchronize()
+    for S, (inp, l) in zip(STACK_NARROW, layers):
+        _check_layer(orc, S, inp, l, _single_calls(ctx, S, l))
     plan.close()
 
 
