@@ -249,10 +249,11 @@ typedef struct ensei_layer {
 /* The HomConv schedule a plan runs: persistent workgroups, chunk (0 =
  * contiguous tile ranges), the measured time of its HomConv launches in
  * microseconds (0 when taken from the cache), and whether it came from the
- * cache (1) or from tuning (0). Layers of at most 8 input channels run on
- * their own narrow-input kernel after the shared persistent launch of the
- * others; the schedule concerns the shared launch (a plan of narrow layers
- * only has nothing to tune and reports from_cache = 0). */
+ * cache (1) or from tuning (0). Layers of at most 8 input channels, and
+ * layers with several 64-row output tiles and at most 256 input channels, run
+ * on their own kernels after the shared persistent launch of the others; the
+ * schedule concerns the shared launch (a plan of such layers only has nothing
+ * to tune and reports from_cache = 0). */
 typedef struct ensei_schedule {
     int blocks;
     int from_cache;

@@ -98,6 +98,9 @@ int homconv_sizes(int64_t batch, int Cin, int Cout, int64_t F, int n);
 // Checks one problem's sizes and fills its derived fields (tile0 = 0).
 int homconv_problem(const ensei_ctx *ctx, HcLayer *P, const uint64_t *ct_in, const int8_t *w_pack, const uint32_t *r,
                     int64_t B, int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, size_t wbytes);
+// Whether a single problem (paired fragments) runs on the deep-layer kernel;
+// batched launches keep such layers out of the multi-problem table.
+bool homconv_deep_fits(const HcLayer &P);
 // Launches the matrix-core HomConv over problems[0..nlayers) (host copies;
 // dev_table holds the same array in device memory when nlayers > 1).
 int homconv_launch(const ensei_ctx *ctx, const HcLayer *problems, const HcLayer *dev_table, int nlayers, bool paired,

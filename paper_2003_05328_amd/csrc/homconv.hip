@@ -554,6 +554,186 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
     if (n_units & 1) body(buf0, 0);
 }
 
+// Deep-layer HomConv (paired fragments, Cin <= 64 kDeepMaxKs, several
+// 64-row output tiles): a block is (b, f, 32 columns j). The block's words of
+// every input channel are converted to digit planes in LDS once (up to 64 KB),
+// then every (row tile, K step) phase of the block contracts from there with
+// no barrier in between: the conversion is shared by all Cout rows instead of
+// being repeated per row tile, and each phase's fixed cost is a few fragment
+// loads per wave. Four waves hold 16 columns x 32 rows each (as in
+// homconv_mfma_kernel) and load their own weight fragments from the packed
+// layout one phase ahead; every phase issues the same loads and stores
+// (dropped ones where the K step is not the tile's last), so the waits see
+// static counts. Two workgroups share a CU, so one contracts while the other
+// waits for its next block's words; each walks a contiguous range of blocks.
+constexpr int kDeepThreads = 256;
+constexpr int kDeepCols = 32;                        // columns per block
+constexpr int kDeepPlane = kDeepCols * 4 * 16;       // one digit plane of a block's K step
+constexpr int kDeepMaxKs = 4;
+
+template <bool WIDE_STORE>
+__global__ __launch_bounds__(kDeepThreads, 2) void homconv_deep_kernel(HcLayer P, uint64_t delta) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t dlds[];  // [ks][plane 8] planes, then masks [n_ot 64]
+    const int n_ks = P.n_ks, n_ot = P.n_ot, Cin = P.Cin, Cout = P.Cout;
+    const int64_t F = P.F, rowlen = (int64_t)P.n + 1;
+    const int n_jt = (int)((rowlen + kDeepCols - 1) / kDeepCols);
+    uint32_t *lds_r = reinterpret_cast<uint32_t *>(dlds + (size_t)n_ks * 8 * kDeepPlane);
+    auto planes = [&](int ks) { return dlds + ks * 8 * kDeepPlane; };
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane >> 4, l16 = lane & 15, cg = wave & 1, rg = wave >> 1;
+    const int ld_col = tid >> 3, ld_sc = (tid >> 1) & 3, ld_h = tid & 1;  // load role: 8 channels of a column
+    const int b_col = cg * 16 + l16, out_row = 32 * rg + 8 * g;
+    const int b_base = plane_slot(b_col, g) * 16;  // this lane's 16 channels of a plane
+
+    const int64_t total = P.B * F * n_jt, G = gridDim.x;
+    const int64_t per = total / G, extra = total % G;
+    const int64_t blo = (int64_t)blockIdx.x * per + ((int64_t)blockIdx.x < extra ? blockIdx.x : extra);
+    const int64_t bhi = blo + per + ((int64_t)blockIdx.x < extra ? 1 : 0);
+    const int n_ph = n_ot * n_ks;
+
+    // this wave's fragments of unit (f, ks, ot): items [limb][row block][lane]
+    auto load_frags = [&](int64_t f, int ks, int ot, v4i (&A)[3][2]) {
+        const int64_t unit = (f * n_ks + ks) * n_ot + ot;
+        const __amdgpu_buffer_rsrc_t ra =
+            make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(P.w_pack) + unit * 768 * 16), 768u * 16u);
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(ra, ((l * 4 + rg * 2 + rb) * 64 + lane) * 16, 0, 0);
+                A[l][rb] = v4i{(int)t.x, (int)t.y, (int)t.z, (int)t.w};
+            }
+    };
+
+    v4i acc[8][2];
+    uint64_t res[2][4] = {};
+    for (int64_t blk = blo; blk < bhi; ++blk) {
+        const int jt = (int)(blk % n_jt);
+        const int64_t fb = blk / n_jt, f = fb % F, b = fb / F;
+
+        // the block's words of every K step (8 channels of one column per thread)
+        const uint8_t *src = uniform_ptr(reinterpret_cast<const uint8_t *>(P.ct_in + (b * F + f) * rowlen * Cin));
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, (uint32_t)(rowlen * Cin * 8));
+        const int col = jt * kDeepCols + ld_col;
+        u32x4 w[kDeepMaxKs][4];
+#pragma unroll
+        for (int ks = 0; ks < kDeepMaxKs; ++ks) {
+            if (ks >= n_ks) break;
+            // columns past n read zero; 8-channel groups past Cin are not read
+            const bool any = ld_sc * 16 + ld_h * 8 < Cin - ks * 64;
+            const uint32_t off =
+                any ? (uint32_t)(((int64_t)col * Cin + ks * 64 + ld_sc * 16 + ld_h * 8) * 8) : 0x80000000u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) w[ks][q] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16 * q), 0, 0);
+        }
+        // masks of the block holding the b word (j = n)
+        if (jt == n_jt - 1) {
+            const uint32_t *rsrc = P.r + b * Cout * F + f;
+            for (int o = tid; o < n_ot * 64; o += kDeepThreads) lds_r[o] = o < Cout ? rsrc[(int64_t)o * F] : 0u;
+        }
+        v4i A[3][2];
+        load_frags(f, 0, 0, A);
+#pragma unroll
+        for (int ks = 0; ks < kDeepMaxKs; ++ks) {
+            if (ks >= n_ks) break;
+            uint32_t lo[8], hi[8], pl[8][2];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint64_t v0 = ((uint64_t)w[ks][q].y << 32 | w[ks][q].x) + 0x8080808080808080ull;
+                const uint64_t v1 = ((uint64_t)w[ks][q].w << 32 | w[ks][q].z) + 0x8080808080808080ull;
+                lo[2 * q] = (uint32_t)v0;
+                hi[2 * q] = (uint32_t)(v0 >> 32);
+                lo[2 * q + 1] = (uint32_t)v1;
+                hi[2 * q + 1] = (uint32_t)(v1 >> 32);
+            }
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                transpose4(lo[4 * d], lo[4 * d + 1], lo[4 * d + 2], lo[4 * d + 3], pl[0][d], pl[1][d], pl[2][d],
+                           pl[3][d]);
+                transpose4(hi[4 * d], hi[4 * d + 1], hi[4 * d + 2], hi[4 * d + 3], pl[4][d], pl[5][d], pl[6][d],
+                           pl[7][d]);
+            }
+            const int pslot = plane_slot(ld_col, ld_sc) * 16 + ld_h * 8;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                *reinterpret_cast<u32x2 *>(planes(ks) + k * kDeepPlane + pslot) =
+                    u32x2{pl[k][0] ^ 0x80808080u, pl[k][1] ^ 0x80808080u};
+        }
+        __syncthreads();
+
+        const uint64_t *oblk = P.ct_out + ((b * F + f) * rowlen + jt * kDeepCols) * Cout;
+        const uint32_t obytes = (uint32_t)((rowlen - jt * kDeepCols) * Cout * 8);
+        const bool b_lane = jt * kDeepCols + b_col == P.n;
+        int ot = 0, ks = 0;
+        for (int ph = 0; ph < n_ph; ++ph) {
+            // the next phase's fragments (past the block's end: this phase's again)
+            const int ks2 = ks + 1 < n_ks ? ks + 1 : 0;
+            const int ot2 = ks + 1 < n_ks ? ot : (ot + 1 < n_ot ? ot + 1 : ot);
+            v4i An[3][2];
+            load_frags(f, ph + 1 < n_ph ? ks2 : ks, ph + 1 < n_ph ? ot2 : ot, An);
+
+            auto contract = [&](auto fresh_tag) {
+                constexpr bool FRESH = decltype(fresh_tag)::value;
+                const v4i zero = {0, 0, 0, 0};
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const v4i B = *reinterpret_cast<const v4i *>(planes(ks) + b_base + k * kDeepPlane);
+#pragma unroll
+                    for (int l = 0; l < 3; ++l) {
+                        if (k + l >= 8) break;
+                        const bool first = FRESH && (k == 0 || l == 2);
+#pragma unroll
+                        for (int rb = 0; rb < 2; ++rb)
+                            acc[k + l][rb] =
+                                __builtin_amdgcn_mfma_i32_16x16x64_i8(A[l][rb], B, first ? zero : acc[k + l][rb], 0, 0, 0);
+                    }
+                }
+            };
+            if (ks == 0)
+                contract(std::true_type{});
+            else
+                contract(std::false_type{});
+
+            // the tile's last K step: recombine, HomShare on the b word, store
+            // (other phases issue the same stores, dropped)
+            const bool last = ks == n_ks - 1;
+            if (last) {
+                auto recombine_all = [&](auto small_tag) {
+                    constexpr bool SMALL = decltype(small_tag)::value;
+#pragma unroll
+                    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            res[rb][i] = recombine<SMALL>(acc[0][rb][i], acc[1][rb][i], acc[2][rb][i], acc[3][rb][i],
+                                                          acc[4][rb][i], acc[5][rb][i], acc[6][rb][i], acc[7][rb][i]);
+                };
+                if (Cin <= kSmallCin)
+                    recombine_all(std::true_type{});
+                else
+                    recombine_all(std::false_type{});
+                if (b_lane) {
+#pragma unroll
+                    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) res[rb][i] += delta * (uint64_t)lds_r[ot * 64 + out_row + 4 * rb + i];
+                }
+            }
+            const __amdgpu_buffer_rsrc_t rso = make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(oblk)),
+                                                         __builtin_amdgcn_readfirstlane(last ? obytes : 0u));
+            store_lane_words<WIDE_STORE, false, 0>(res, rso, b_col, ot * 64 + 32 * rg, g, Cout, last);
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb) A[l][rb] = An[l][rb];
+            ks = ks2;
+            ot = ot2;
+        }
+        __syncthreads();  // planes and masks are rewritten by the next block
+    }
+}
+
 // Narrow-input HomConv (Cin <= kNarrowCin, folded weight fragments): with so
 // few input channels the launch is a write stream (8 (n+1) Cout bytes out per
 // 8 (n+1) Cin in), so nothing here waits on other waves. Each wave walks its
@@ -948,10 +1128,45 @@ static int launch_narrow(const ensei_ctx *ctx, const HcLayer &P, HcSchedule sche
     return launch_status();
 }
 
+// Deep kernel launch, if the layer suits it (homconv_deep_fits). Returns
+// ENSEI_ERR_LIMIT (nothing launched) otherwise.
+constexpr int kLdsBytes = 160 * 1024;
+static size_t deep_lds_bytes(const HcLayer &P) { return (size_t)P.n_ks * 8 * kDeepPlane + (size_t)P.n_ot * 64 * 4; }
+
+bool homconv_deep_fits(const HcLayer &P) {
+    // all K steps of a block in half the LDS, several row tiles, and at least
+    // four (row tile, K step) phases per block to share the conversion
+    return P.Cin >= kPairedCin && P.n_ks <= kDeepMaxKs && P.n_ot >= 2 && P.n_ot * P.n_ks >= 4 &&
+           deep_lds_bytes(P) <= (size_t)kLdsBytes / 2;
+}
+
+static int launch_deep(const ensei_ctx *ctx, const HcLayer &P, hipStream_t stream) {
+    if (!homconv_deep_fits(P)) return ENSEI_ERR_LIMIT;
+    const size_t lds = deep_lds_bytes(P);
+    const bool wide = P.Cout % 2 == 0;
+    auto kernel = wide ? homconv_deep_kernel<true> : homconv_deep_kernel<false>;
+    static bool attr[2] = {false, false};
+    if (!attr[wide]) {
+        if (hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes / 2) !=
+            hipSuccess)
+            return ENSEI_ERR_HIP;
+        attr[wide] = true;
+    }
+    // two resident workgroups per CU
+    const int64_t blocks_total = P.B * P.F * ((P.n + 1 + kDeepCols - 1) / kDeepCols);
+    const int64_t grid = blocks_total < 2 * (int64_t)ctx->num_cus ? blocks_total : 2 * (int64_t)ctx->num_cus;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(kDeepThreads), lds, stream, P, ctx->delta);
+    return launch_status();
+}
+
 int homconv_launch(const ensei_ctx *ctx, const HcLayer *problems, const HcLayer *dev_table, int nlayers, bool paired,
                    HcSchedule sched, hipStream_t stream) {
     if (nlayers < 1 || (nlayers > 1 && (!dev_table || !paired))) return ENSEI_ERR_ARG;
     if (sched.chunk < 0) return ENSEI_ERR_ARG;
+    if (nlayers == 1 && paired && sched.blocks == 0) {
+        const int rc = launch_deep(ctx, problems[0], stream);
+        if (rc != ENSEI_ERR_LIMIT) return rc;
+    }
     if (nlayers == 1 && !paired && problems[0].Cin <= kNarrowCin) {
         const int Cin = problems[0].Cin;
         return Cin <= 4 ? launch_narrow<4>(ctx, problems[0], sched, stream)

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "ensei_internal.hpp"
@@ -15,7 +16,9 @@ struct ensei_plan {
     std::vector<uint32_t *> w_hat;
     std::vector<int8_t *> w_pack;
     std::vector<ensei::HcLayer> problems;  // in the one persistent launch
-    std::vector<ensei::HcLayer> narrow;    // narrow-input layers, each on its own kernel
+    // narrow-input and deep layers, each launched on its own kernel (with
+    // paired fragments or not)
+    std::vector<std::pair<ensei::HcLayer, bool>> single;
     ensei::HcLayer *d_table = nullptr;
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -74,8 +77,8 @@ int run_homconv(ensei_plan *P, HcSchedule s, hipStream_t st) {
     int rc = P->problems.empty()
                  ? ENSEI_OK
                  : homconv_launch(P->ctx, P->problems.data(), P->d_table, (int)P->problems.size(), true, s, st);
-    for (const HcLayer &h : P->narrow)
-        if (!rc) rc = homconv_launch(P->ctx, &h, nullptr, 1, false, HcSchedule{0, 0}, st);
+    for (const auto &hp : P->single)
+        if (!rc) rc = homconv_launch(P->ctx, &hp.first, nullptr, 1, hp.second, HcSchedule{0, 0}, st);
     return rc;
 }
 
@@ -167,8 +170,9 @@ int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, co
         release(P);
         return ENSEI_ERR_HIP;
     }
-    // server setup: transformed and packed filters (paired layout for every
-    // layer of the shared persistent launch, folded for narrow inputs)
+    // server setup: transformed and packed filters (paired layout, folded for
+    // narrow inputs); narrow and deep layers run on their own kernels, the
+    // others share one persistent launch
     int64_t tile0 = 0;
     for (const ensei_layer &l : P->layers) {
         if (l.H <= 0 || l.W <= 0 || l.Cin <= 0 || l.Cout <= 0 || l.batch <= 0) {
@@ -196,8 +200,8 @@ int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, co
             release(P);
             return rc;
         }
-        if (narrow) {
-            P->narrow.push_back(h);
+        if (narrow || homconv_deep_fits(h)) {
+            P->single.emplace_back(h, !narrow);
             continue;
         }
         h.n_items = frag_items(l.Cin, true);
@@ -232,7 +236,7 @@ int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, co
     HcSchedule best{ctx->num_cus, 0};
     double best_us = 0;
     if (P->problems.empty()) {
-        // nothing to schedule: narrow-input layers only
+        // nothing to schedule: every layer runs on its own kernel
         rc = time_schedule(P, best, &best_us);
         if (rc) {
             release(P);

@@ -40,7 +40,7 @@ struct Shape {
     int8_t *w_pack = nullptr;
     size_t wpack_bytes = 0;
     size_t footprint = 0;  // arena bytes of one request
-    bool narrow = false;   // HomConv on the narrow-input kernel, outside the batch's shared launch
+    bool narrow = false;   // HomConv on the narrow-input kernel (folded fragments), outside the shared launch
 };
 
 enum ReqState { kQueued = 0, kRunning = 1, kDone = 2, kFailed = 3 };
@@ -140,9 +140,11 @@ int launch_batch(ensei_server *S, Batch &b) {
         if (!rc)
             rc = homconv_problem(S->ctx, &h, ct_in, sh.w_pack, q.io.r, 1, d.Cin, d.Cout, sh.F, d.n, ct_out,
                                  sh.wpack_bytes);
-        if (!rc && sh.narrow) rc = homconv_launch(S->ctx, &h, nullptr, 1, false, HcSchedule{0, 0}, st);
+        // narrow and deep shapes run on their own kernels, the others share one launch
+        const bool alone = !rc && (sh.narrow || homconv_deep_fits(h));
+        if (alone) rc = homconv_launch(S->ctx, &h, nullptr, 1, !sh.narrow, HcSchedule{0, 0}, st);
         if (rc) break;
-        if (sh.narrow) continue;
+        if (alone) continue;
         h.n_items = frag_items(d.Cin, true);
         h.tile0 = tile0;
         tile0 += h.n_tiles;

@@ -163,6 +163,46 @@ def test_homconv_valu(ctx, orc, B, Cin, Cout, F, n):
     assert np.array_equal(got, orc.homconv(ct, w, r, P))
 
 
+# Layers with several 64-row output tiles, at most 256 input channels and at
+# least four (row tile, K step) pairs take the deep kernel (a block's digit
+# planes of every K step held in LDS, all row tiles contracted from them): one
+# to four K steps, ragged channel groups and columns, odd Cout, more blocks
+# than workgroups; Cin = 257 falls back to the streaming kernel.
+DEEP_CASES = [
+    # B, Cin, Cout, F, n
+    (1, 48, 300, 3, 70),
+    (2, 100, 128, 256, 64),
+    (1, 100, 129, 4, 90),
+    (2, 256, 130, 5, 129),
+    (1, 200, 256, 17, 63),
+    (1, 130, 512, 2, 40),
+    (1, 257, 70, 2, 40),
+]
+
+
+@pytest.mark.parametrize("B,Cin,Cout,F,n", DEEP_CASES)
+def test_homconv_deep(ctx, orc, B, Cin, Cout, F, n):
+    ct, w, r = _homconv_inputs(B, Cin, Cout, F, n, 43 * Cin + Cout + n)
+    ref = orc.homconv(ct, w, r, P)
+    got = host(ctx.homconv(dev(ct), ctx.pack_weights(dev(w)), dev(r), Cout))
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("Cin", [169, 170])
+def test_homconv_deep_extreme_digits(ctx, orc, Cin):
+    """Largest same-sign shift sums on the deep kernel, both sides of the
+    32-bit partial recombination bound."""
+    B, Cout, F, n = 1, 130, 2, 70
+    ct = np.full((B, F, n + 1, Cin), 0x7F7F7F7F7F7F7F80, dtype=np.uint64)
+    ct[:, :, 1::2, : Cin // 2] = 0x7F7F7F7F7F7F7F7F
+    w = np.full((Cout, Cin, F), 0x8080, dtype=np.uint32)
+    w[1::2] = P - 1
+    r = np.full((B, Cout, F), 12345, dtype=np.uint32)
+    ref = orc.homconv(ct, w, r, P)
+    got = host(ctx.homconv(dev(ct), ctx.pack_weights(dev(w)), dev(r), Cout))
+    assert np.array_equal(got, ref)
+
+
 # Inputs of at most 16 channels take the narrow kernel (one wave per unit of
 # 16 words, no LDS): channel counts of each of its widths, odd Cout (8-byte
 # stores), several row tiles, the b word first, last or alone in its 16-word

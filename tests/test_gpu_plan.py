@@ -13,12 +13,14 @@ from tests.gpu_helpers import P, dev, host
 
 pytestmark = pytest.mark.gpu
 
-# uneven shapes: a narrow input (its own kernel beside the shared launch),
+# uneven shapes: a narrow input and a deep layer (each on its own kernel
+# beside the shared launch), two layers in the shared persistent launch,
 # several K steps, several row tiles, a ragged column tile
 STACK = [
     LayerShape(H=8, W=8, Cin=3, Cout=16, kh=3, kw=3, n=70, B=2),
     LayerShape(H=4, W=8, Cin=130, Cout=70, kh=3, kw=3, n=64, B=1),
     LayerShape(H=16, W=16, Cin=64, Cout=64, kh=3, kw=3, n=100, B=2, hidden=True),
+    LayerShape(H=8, W=8, Cin=48, Cout=70, kh=3, kw=3, n=40, B=1),
 ]
 STACK_ODD = [
     LayerShape(H=8, W=4, Cin=5, Cout=17, kh=2, kw=3, n=33, B=1),

@@ -21,6 +21,7 @@ SHAPES = [
     LayerShape(H=8, W=8, Cin=64, Cout=70, kh=3, kw=3, n=100),
     LayerShape(H=4, W=8, Cin=130, Cout=17, kh=2, kw=3, n=33),
     LayerShape(H=32, W=32, Cin=5, Cout=32, kh=5, kw=5, n=129),
+    LayerShape(H=4, W=4, Cin=130, Cout=130, kh=3, kw=3, n=33),
 ]
 
 
