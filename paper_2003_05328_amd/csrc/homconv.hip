@@ -567,6 +567,7 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
 // static counts. Two workgroups share a CU, so one contracts while the other
 // waits for its next block's words; each walks a contiguous range of blocks.
 constexpr int kDeepThreads = 256;
+constexpr int kXcds = 8;                             // accelerator dies (each with its own L2)
 constexpr int kDeepCols = 32;                        // columns per block
 constexpr int kDeepPlane = kDeepCols * 4 * 16;       // one digit plane of a block's K step
 constexpr int kDeepMaxKs = 4;
@@ -587,10 +588,17 @@ __global__ __launch_bounds__(kDeepThreads, 2) void homconv_deep_kernel(HcLayer P
     const int b_col = cg * 16 + l16, out_row = 32 * rg + 8 * g;
     const int b_base = plane_slot(b_col, g) * 16;  // this lane's 16 channels of a plane
 
+    // Blocks in (f, b, column) order, so that a frequency's weight fragments
+    // serve B * n_jt consecutive blocks. Workgroups are dealt to the XCDs
+    // round-robin; renumbering them so that each XCD's workgroups take one
+    // contiguous stretch of blocks keeps the fragments of few frequencies in
+    // each XCD's L2.
     const int64_t total = P.B * F * n_jt, G = gridDim.x;
+    const int64_t wg = G % kXcds == 0 ? (int64_t)(blockIdx.x % kXcds) * (G / kXcds) + blockIdx.x / kXcds
+                                      : (int64_t)blockIdx.x;
     const int64_t per = total / G, extra = total % G;
-    const int64_t blo = (int64_t)blockIdx.x * per + ((int64_t)blockIdx.x < extra ? blockIdx.x : extra);
-    const int64_t bhi = blo + per + ((int64_t)blockIdx.x < extra ? 1 : 0);
+    const int64_t blo = wg * per + (wg < extra ? wg : extra);
+    const int64_t bhi = blo + per + (wg < extra ? 1 : 0);
     const int n_ph = n_ot * n_ks;
 
     // this wave's fragments of unit (f, ks, ot): items [limb][row block][lane]
@@ -611,7 +619,7 @@ __global__ __launch_bounds__(kDeepThreads, 2) void homconv_deep_kernel(HcLayer P
     uint64_t res[2][4] = {};
     for (int64_t blk = blo; blk < bhi; ++blk) {
         const int jt = (int)(blk % n_jt);
-        const int64_t fb = blk / n_jt, f = fb % F, b = fb / F;
+        const int64_t fb = blk / n_jt, b = fb % P.B, f = fb / P.B;
 
         // the block's words of every K step (8 channels of one column per thread)
         const uint8_t *src = uniform_ptr(reinterpret_cast<const uint8_t *>(P.ct_in + (b * F + f) * rowlen * Cin));

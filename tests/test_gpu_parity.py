@@ -54,7 +54,21 @@ def test_ntt2d_intt2d(ctx, orc, H, W):
     assert np.array_equal(y, orc.ntt2d(Y.reshape(batch, H, W), P, inverse=True))
 
 
+@pytest.mark.parametrize("H,W", [(8, 8), (16, 16), (32, 32), (64, 64), (8, 64), (64, 16)])
+def test_ntt2d_group_boundaries(ctx, orc, H, W):
+    """A workgroup transforms T grids: batches that end inside a workgroup's
+    group, on a whole number of groups, and a single grid."""
+    T = max(1, 256 // max(H, W))
+    for batch in (3 * T + 1, 4 * T, 1):
+        x = synth.uniform_u32(3000 + H * 7 + W + batch, (batch, H, W), P)
+        assert np.array_equal(host(ctx.ntt2d(dev(x))).reshape(batch, H, W), orc.ntt2d(x, P)), batch
+        Y = synth.uniform_u32(4000 + H * 7 + W + batch, (batch, H * W), P)
+        y = host(ctx.intt2d(dev(Y), H, W))
+        assert np.array_equal(y, orc.ntt2d(Y.reshape(batch, H, W), P, inverse=True)), batch
+
+
 def test_ntt2d_in_place_and_roundtrip(ctx, orc):
+    # 37 grids of 32 x 32: groups of 4 channels per workgroup, the last ragged
     x = synth.uniform_u32(7, (37, 32, 32), P)
     t = dev(x)
     ctx.ntt2d(t, out=t.view(37, 1024))
