@@ -177,6 +177,43 @@ def test_homconv_valu(ctx, orc, B, Cin, Cout, F, n):
     assert np.array_equal(got, orc.homconv(ct, w, r, P))
 
 
+# One K step and one row tile (48 <= Cin <= 64, Cout <= 64), the shape of the
+# 64 -> 64 layers: channel groups straddling Cin, odd Cout, one output row,
+# the b word first, last or alone in its column tile, and workgroup ranges
+# that cross frequencies and images.
+SINGLE_STEP_CASES = [
+    # B, Cin, Cout, F, n
+    (1, 48, 64, 5, 100),
+    (2, 64, 64, 7, 31),
+    (1, 57, 33, 4, 64),
+    (1, 64, 1, 2, 16),
+    (3, 50, 17, 300, 40),
+    (1, 64, 64, 1024, 255),
+]
+
+
+@pytest.mark.parametrize("B,Cin,Cout,F,n", SINGLE_STEP_CASES)
+def test_homconv_single_step(ctx, orc, B, Cin, Cout, F, n):
+    ct, w, r = _homconv_inputs(B, Cin, Cout, F, n, 47 * Cin + Cout + n)
+    ref = orc.homconv(ct, w, r, P)
+    got = host(ctx.homconv(dev(ct), ctx.pack_weights(dev(w)), dev(r), Cout))
+    assert np.array_equal(got, ref)
+
+
+def test_homconv_single_step_extreme_digits(ctx, orc):
+    """Digits -128 and +127 against limbs -128, -127, 1 and p - 1 with one K step of 64 channels."""
+    B, Cin, Cout, F, n = 2, 64, 64, 3, 40
+    ct = np.full((B, F, n + 1, Cin), 0x7F7F7F7F7F7F7F80, dtype=np.uint64)
+    ct[:, :, 1::2, :32] = 0x7F7F7F7F7F7F7F7F
+    ct[:, :, ::5, :] = 2**64 - 1
+    w = np.full((Cout, Cin, F), 0x8080, dtype=np.uint32)
+    w[1::3] = P - 1
+    r = np.full((B, Cout, F), P - 1, dtype=np.uint32)
+    ref = orc.homconv(ct, w, r, P)
+    got = host(ctx.homconv(dev(ct), ctx.pack_weights(dev(w)), dev(r), Cout))
+    assert np.array_equal(got, ref)
+
+
 # Layers with several 64-row output tiles, at most 256 input channels and at
 # least four (row tile, K step) pairs take the deep kernel (a block's digit
 # planes of every K step held in LDS, all row tiles contracted from them): one
