@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--stack-reps", type=int, default=5)
     ap.add_argument("--serve", action="store_true",
                     help="only the serving sweep (Poisson arrivals of mixed-shape requests), one JSON line")
-    ap.add_argument("--serve-rates", default="250,500,1000,2000", help="arrival rates, requests/s")
+    ap.add_argument("--serve-rates", default="250,500,750,1000,1250,2000", help="arrival rates, requests/s")
     ap.add_argument("--serve-requests", type=int, default=1000, help="requests per rate")
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
     ap.add_argument("--probe-copy", action="store_true",
@@ -93,6 +93,48 @@ def traffic_entry(launch_bytes: int):
         return int(rec["hbm_bytes_per_launch"])
     except (OSError, ValueError, KeyError):
         return None
+
+
+MFMA_I8_PEAK_MACS = 2.5e15  # dense i8 multiply-accumulates per second (5.0 POP/s)
+
+
+def homconv_layers(ctx, warm: int = 10, reps: int = 10):
+    """HomConv alone on every distinct workload layer shape (random words: the
+    kernels' cost does not depend on values), timed after `warm` launches as
+    the mean of `reps`: the algorithmic HBM rate, and the i8 multiply-
+    accumulate rate (21 per word-MAC) against the dense matrix-core peak."""
+    import torch
+    from paper_2003_05328_amd import configs
+
+    P = configs.P
+    rows = []
+    for name, S in configs.WORKLOADS.items():
+        if S.hidden or S.binary:  # same HomConv shape as another entry
+            continue
+        dv = "cuda:0"
+        ct = torch.empty((S.B, S.F, S.n + 1, S.Cin), dtype=torch.int64, device=dv).random_().view(torch.uint64)
+        w = torch.randint(0, P, (S.Cout, S.Cin, S.F), dtype=torch.int32, device=dv).view(torch.uint32)
+        r = torch.randint(0, P, (S.B, S.Cout, S.F), dtype=torch.int32, device=dv).view(torch.uint32)
+        pack = ctx.pack_weights(w)
+        out = torch.empty((S.B, S.F, S.n + 1, S.Cout), dtype=torch.uint64, device=dv)
+        for _ in range(warm):
+            ctx.homconv(ct, pack, r, S.Cout, out=out)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            ctx.homconv(ct, pack, r, S.Cout, out=out)
+        ev[1].record()
+        torch.cuda.synchronize()
+        us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+        nbytes = homconv_bytes(S, int(pack.numel()))
+        word_macs = S.B * S.Cout * S.Cin * S.F * (S.n + 1)
+        i8 = 21 * word_macs / (us * 1e-6)
+        rows.append({"layer": name, "us": us, "algorithmic_bytes": nbytes,
+                     "hbm_gbs": nbytes / (us * 1e-6) / 1e9, "frac_hbm": nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                     "word_mac_per_byte": word_macs / nbytes, "i8_mac_per_s": i8, "frac_mfma": i8 / MFMA_I8_PEAK_MACS})
+        del ct, w, r, pack, out
+        torch.cuda.empty_cache()
+    return rows
 
 
 def ntt_throughput(ctx, S, reps: int = 20):
@@ -565,6 +607,7 @@ def main():
         result["ntt2d"] = ntt_throughput(ctx, S)
         del ct_in, ct_out
         torch.cuda.empty_cache()
+        result["homconv_layers"] = homconv_layers(ctx)
         result["batched"] = stack_batched(ctx, args.stack_reps, args.seed)
         result["verified"] = result["verified"] and result["batched"]["bit_exact_vs_sequential"]
         torch.cuda.empty_cache()
