@@ -19,7 +19,6 @@ over its event-timed duration) and the CPU oracle's rate on the host.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -84,11 +83,12 @@ def homconv_bytes(S, pack_bytes: int) -> int:
 def traffic_entry(launch_bytes: int):
     """Measured HBM bytes per HomConv launch from rocprofv3 counters, if they
     were taken on the current kernel source; else None."""
+    from paper_2003_05328_amd.profile_summary import code_digest
+
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
-        src_sha = hashlib.sha256(open(HOMCONV_SRC, "rb").read()).hexdigest()
-        if rec.get("source_sha256") != src_sha:
+        if rec.get("code_sha256") != code_digest(HOMCONV_SRC):
             return None
         return int(rec["hbm_bytes_per_launch"])
     except (OSError, ValueError, KeyError):

@@ -19,18 +19,27 @@
 //   The kernel's two K layouts (limbs folded into K, or one limb pair per
 //   instruction) are described at the kernel.
 //
-// Work decomposition: a tile is (b, f, 64 rows o, 64 columns j) and a unit a
-// (tile, 64-channel K step). With C = 64 channels both the unit's input words
-// and the tile's output words are one contiguous 32 KB block, which is what
-// lets the kernel stream at HBM rate. One 8-wave workgroup per CU walks a
-// contiguous range of tiles (row tiles fastest, so extra row tiles of a
-// (b, f, columns) reuse its input from L2), two units ahead: the next two
-// units' words, weight fragments and masks are in flight while the current
-// unit is converted to digit planes and contracted on the MFMAs. Each wave
-// owns 16 columns x 32 rows and the eight shift accumulators in registers.
-// The rows of the MFMA's A operand are permuted so that every lane ends up
-// with 8 consecutive output rows of one column: after the recombination each
-// lane writes one 64-byte run of ct_out straight from its registers.
+// Three kernels share these operand layouts; ensei_homconv picks one per
+// layer (homconv_launch):
+//   - homconv_mfma_kernel, the streaming kernel (every layer, and every
+//     layer of a multi-problem launch): a tile is (b, f, 64 rows o, 64
+//     columns j) and a unit a (tile, 64-channel K step). With C = 64 channels
+//     both the unit's input words and the tile's output words are one
+//     contiguous 32 KB block, which is what lets the kernel stream at HBM
+//     rate. One 8-wave workgroup per CU walks a contiguous range of tiles (row
+//     tiles fastest, so extra row tiles of a (b, f, columns) reuse its input
+//     from L2), two units ahead: the next two units' words, weight fragments
+//     and masks are in flight while the current unit is converted to digit
+//     planes and contracted on the MFMAs. Each wave owns 16 columns x 32 rows
+//     and the eight shift accumulators in registers;
+//   - homconv_narrow_kernel (Cin <= 8): barrier-free waves for the
+//     write-bound narrow-input layers;
+//   - homconv_deep_kernel (several row tiles, Cin <= 256): the input of a
+//     32-column block converted once into LDS for all of its row tiles.
+// In all of them the rows of the MFMA's A operand are permuted so that every
+// lane ends up with 8 consecutive output rows of one column: after the
+// recombination each lane stores whole 64-byte runs of ct_out straight from
+// its registers.
 #include <type_traits>
 
 #include "ensei_internal.hpp"
