@@ -179,7 +179,9 @@ int ensei_encrypt(ensei_ctx *ctx, const uint32_t *m, const int8_t *s, const int3
  * of either side below 2^31 bytes ((n+1) * max(Cin, Cout) * 8) and one
  * image's masks below 2^31 bytes (Cout * F * 4), else ENSEI_ERR_LIMIT. Runs on the
  * i8 matrix cores (signed-byte limbs of both operands, exact i32 sums,
- * recombined mod 2^64). */
+ * recombined mod 2^64); the kernel is chosen by shape (narrow inputs, deep
+ * layers with several output tiles, or the streaming kernel), the results
+ * are the same bits. */
 int ensei_homconv(ensei_ctx *ctx, const uint64_t *ct_in, const int8_t *w_pack, const uint32_t *r, int64_t batch,
                   int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, void *stream);
 
@@ -202,9 +204,11 @@ int ensei_decrypt(ensei_ctx *ctx, const uint64_t *ct, const int8_t *s, int64_t b
  * A plan runs a stack of independent secure convolutions (Fig. 2's start
  * round for each layer; layers of uneven shapes, each over a batch of images
  * of one client) as one captured HIP graph: per layer NTT2D and Enc, then ONE
- * persistent matrix-core HomConv launch over the tiles of all layers, then
- * per layer Dec, INTT2D and the server share. The server's filters are
- * transformed and packed once, when the plan is created.
+ * persistent matrix-core HomConv launch over the tiles of all layers (those
+ * with at most 8 input channels, and those with several 64-row output tiles
+ * and at most 256 input channels, each run their own HomConv kernel after
+ * it), then per layer Dec, INTT2D and the server share. The server's filters
+ * are transformed and packed once, when the plan is created.
  *
  * The HomConv tile schedule (persistent workgroups; contiguous tile ranges
  * or chunks of 1..256 tiles dealt round-robin) is picked by timing the
