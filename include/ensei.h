@@ -292,7 +292,8 @@ int ensei_plan_destroy(ensei_plan *plan);
  * admits queued requests in arrival order while their ciphertext state fits
  * the free part of a device budget, groups them into a batch and enqueues it
  * on one of `nstreams` streams (default priority): per request NTT2D and Enc,
- * one persistent HomConv launch over the tiles of every request of the batch,
+ * one persistent HomConv launch over the tiles of every request of the batch
+ * (requests of narrow-input or deep shapes run their own HomConv kernels),
  * then per request Dec, INTT2D and the server's share. Batches on different
  * streams overlap on the device; when a batch completes, its memory returns
  * to the budget and waiting requests are admitted. A request's ciphertexts
