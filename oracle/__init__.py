@@ -38,6 +38,8 @@ _SIG = {
     "or_homconv": (None, [u64, i32, i32, i32, i64, i32, vp, vp, vp, vp]),
     "or_homconv_select": (None, [u64, i32, i32, i32, i64, i32, vp, vp, vp, i64, vp, vp]),
     "or_server_share": (None, [u64, i64, i32, i32, vp, vp]),
+    "or_homrec": (None, [u64, i64, i32, i64, i32, vp, vp]),
+    "or_reshare": (None, [u64, i64, vp, vp, vp, C.c_int, vp]),
     "or_set_threads": (C.c_int, [C.c_int]),
 }
 
@@ -188,6 +190,44 @@ class Oracle:
         out = np.empty(r.shape[:-1] + (H, W), dtype=np.uint32)
         self.lib.or_server_share(p, batch, H, W, _p(r), _p(out))
         return out
+
+    def homrec(self, ct, s_hat, p: int) -> np.ndarray:
+        """HomRec: ct[B][F][n+1][C] with Delta * s_hat[B][C][F] added to every b word (a new array)."""
+        ct = np.array(ct, dtype=np.uint64, copy=True, order="C")
+        s_hat = _c(s_hat, np.uint32)
+        B, F, n1, Cc = ct.shape
+        assert s_hat.shape == (B, Cc, F)
+        self.lib.or_homrec(p, B, Cc, F, n1 - 1, _p(ct), _p(s_hat))
+        return ct
+
+    def reshare(self, s_a, s_b, s_b_next, act: int, p: int) -> np.ndarray:
+        """The activation stand-in: s_a' = f(s_a + s_b) - s_b' mod p (act 0 identity, 1 square)."""
+        s_a, s_b, s_b_next = _c(s_a, np.uint32), _c(s_b, np.uint32), _c(s_b_next, np.uint32)
+        assert s_a.shape == s_b.shape == s_b_next.shape
+        out = np.empty_like(s_a)
+        self.lib.or_reshare(p, s_a.size, _p(s_a), _p(s_b), _p(s_b_next), act, _p(out))
+        return out
+
+    def fdsc_round1(self, r0: dict, inp1, s_b1, act: int, p: int):
+        """The next round of Fig. 2 (lines 7-13) after round r0 (fdsc_round0's
+        result), with the activation replaced by reshare in the clear.
+
+        inp1 holds the next layer (its filters w over Cin = the previous Cout,
+        the client's key s, errors e, masks r, seed_a); s_b1 is the server's
+        fresh share [B][Cin][H][W]. Returns the round's intermediates: s_a1
+        (client's share after the activation), ct_a (Enc of its transform),
+        ct_rec (after HomRec), ct_out, m, s_a and s_b (the round's shares).
+        """
+        S = inp1.shape
+        s_a1 = self.reshare(r0["s_a"], r0["s_b"], s_b1, act, p)
+        ct_a = self.encrypt(self.ntt2d(s_a1, p).reshape(S.B, S.Cin, S.F), inp1.s, inp1.e, inp1.seed_a, p)
+        ct_rec = self.homrec(ct_a, self.ntt2d(s_b1, p).reshape(S.B, S.Cin, S.F), p)
+        w_hat = self.weight_prep(inp1.w, S.H, S.W, p)
+        ct_out = self.homconv(ct_rec, w_hat, inp1.r, p)
+        m = self.decrypt(ct_out, inp1.s, p)
+        s_a = self.ntt2d(m.reshape(S.B, S.Cout, S.H, S.W), p, inverse=True)
+        s_b = self.server_share(inp1.r, S.H, S.W, p)
+        return dict(s_a1=s_a1, ct_a=ct_a, ct_rec=ct_rec, w_hat=w_hat, ct_out=ct_out, m=m, s_a=s_a, s_b=s_b)
 
     def fdsc_round0(self, inp, p: int):
         """The whole secure convolution of one layer (Fig. 2, round 0) on the CPU.

@@ -322,6 +322,34 @@ void or_server_share(uint64_t p, int64_t batch, int H, int W, const uint32_t *r,
     or_ntt2d(p, batch, H, W, s_b, s_b, 1);
 }
 
+/* ------------------------------------------------- chained rounds --- */
+
+/* HomRec (Eq. (homrec); Fig. 2 lines 11-13, Eq. (dft_convolution0)): the
+ * server adds its transformed share to the client's ciphertexts as a
+ * plaintext, [s_A] (+) s_B = [s_A + s_B mod p]: Delta * s_hat[b][c][f] is
+ * added to the b word of ciphertext (b, c, f) of ct [B][F][n+1][C], in place.
+ * (Delta p = 2^64 - 1, so a sum that wraps past p costs -1 of noise.) */
+void or_homrec(uint64_t p, int64_t B, int C, int64_t F, int n, uint64_t *ct, const uint32_t *s_hat) {
+    const uint64_t delta = or_delta(p);
+    for (int64_t b = 0; b < B; ++b)
+        for (int64_t f = 0; f < F; ++f)
+            for (int c = 0; c < C; ++c)
+                ct[((b * F + f) * (int64_t)(n + 1) + n) * C + c] += delta * (uint64_t)s_hat[(b * C + c) * F + f];
+}
+
+/* Stand-in for the oblivious activation of Fig. 2 lines 7-8, computed in the
+ * clear: y = s_A + s_B mod p, u = f(y) (act 0: identity, 1: square mod p),
+ * and the client's next share s_A' = u - s_B' mod p for the server's fresh
+ * share s_B'. All arrays hold count residues in [0, p). */
+void or_reshare(uint64_t p, int64_t count, const uint32_t *s_a, const uint32_t *s_b, const uint32_t *s_b_next,
+                int act, uint32_t *s_a_next) {
+    for (int64_t k = 0; k < count; ++k) {
+        uint64_t y = ((uint64_t)s_a[k] + s_b[k]) % p;
+        uint64_t u = act == 1 ? mulmod(y, y, p) : y;
+        s_a_next[k] = (uint32_t)((u + p - s_b_next[k]) % p);
+    }
+}
+
 /* ------------------------------------------------------------ threads --- */
 #ifdef _OPENMP
 #include <omp.h>

@@ -347,6 +347,69 @@ def check_end_to_end(orc):
         assert np.array_equal(conv, _fft_conv(inp.x, inp.w, inp.shape.H, inp.shape.W, P))
 
 
+def check_homrec(orc):
+    """HomRec (Eq. homrec; Fig. 2 lines 11-13): Dec(HomRec(Enc(m), s)) = m + s
+    mod p at edge residues and inside; since Delta p = 2^64 - 1 the phase is
+    Delta ((m + s) mod p) plus the encryption error, minus 1 exactly when
+    m + s wraps past p; the a-words are untouched. Ciphertexts of several
+    channels and frequencies check that each share lands on its own b word."""
+    vals = np.array([0, 1, 2, 32767, 32768, 32769, P - 2, P - 1], dtype=np.int64)
+    m = np.repeat(vals, vals.size)
+    s = np.tile(vals, vals.size)
+    n, Cc, F = 16, 4, 16  # 64 ciphertexts as [1][F][n+1][C]
+    g = _rng(18)
+    key = g.integers(-1, 2, size=n).astype(np.int8)
+    e = g.integers(-40, 41, size=(1, Cc, F)).astype(np.int32)
+    mm = m.reshape(1, Cc, F).astype(np.uint32)
+    ct = orc.encrypt(mm, key, e, 91, P)
+    rec = orc.homrec(ct, s.reshape(1, Cc, F).astype(np.uint32), P)
+    assert np.array_equal(rec[:, :, :n, :], ct[:, :, :n, :])
+    ss = s.reshape(1, Cc, F)
+    assert np.array_equal(orc.decrypt(rec, key, P).astype(np.int64), (mm.astype(np.int64) + ss) % P)
+    D = bf.brute_delta(P)
+    for c in range(Cc):
+        for f in range(F):
+            tot = int(mm[0, c, f]) + int(ss[0, c, f])
+            phase = orc.phase(rec[0, f, :, c], key)
+            assert phase == (D * (tot % P) + int(e[0, c, f]) - int(tot >= P)) % M64
+
+
+def check_reshare(orc):
+    """The stand-in for the oblivious activation (Fig. 2 lines 7-8, in the
+    clear): the shares after it add up to f(s_A + s_B) mod p, f the identity
+    or the square, edge residues included."""
+    g = _rng(19)
+    s_a = g.integers(0, P, size=300).astype(np.uint32)
+    s_b = g.integers(0, P, size=300).astype(np.uint32)
+    s_b2 = g.integers(0, P, size=300).astype(np.uint32)
+    s_a[:3], s_b[:3], s_b2[:3] = P - 1, P - 1, [0, P - 1, 1]
+    for act in (0, 1):
+        out = orc.reshare(s_a, s_b, s_b2, act, P)
+        assert int(out.max()) < P
+        for k in range(300):
+            y = (int(s_a[k]) + int(s_b[k])) % P
+            assert (int(out[k]) + int(s_b2[k])) % P == (y if act == 0 else y * y % P)
+
+
+def check_chained_rounds(orc):
+    """Round 0, the activation stand-in, Enc of the client's new share,
+    HomRec with the server's transformed share, and round 1: the final shares
+    add up to conv(f(conv(x, w0)), w1) mod p (Fig. 2 lines 1-13; Eq.
+    dft_convolution)."""
+    S0 = synth.LayerShape(H=8, W=4, Cin=2, Cout=3, kh=3, kw=2, n=24, B=2)
+    S1 = synth.LayerShape(H=8, W=4, Cin=3, Cout=2, kh=2, kw=3, n=24, B=2, hidden=True)
+    inp0, inp1 = synth.generate(S0, P, 31), synth.generate(S1, P, 32)
+    r0 = orc.fdsc_round0(inp0, P)
+    s_b1 = synth.uniform_u32(33, (S1.B, S1.Cin, S1.H, S1.W), P)
+    conv0 = orc.cyclic_conv(inp0.x, inp0.w, P).astype(np.int64)
+    for act in (0, 1):
+        r1 = orc.fdsc_round1(r0, inp1, s_b1, act, P)
+        u1 = conv0 if act == 0 else conv0 * conv0 % P
+        want = _fft_conv(u1.astype(np.uint32), inp1.w, S1.H, S1.W, P)
+        got = (r1["s_a"].astype(np.int64) + r1["s_b"]) % P
+        assert np.array_equal(got.reshape(want.shape), want), act
+
+
 ALL_CHECKS = [
     check_roots,
     check_delta,
@@ -365,4 +428,7 @@ ALL_CHECKS = [
     check_homconv_special,
     check_noise_identity,
     check_end_to_end,
+    check_homrec,
+    check_reshare,
+    check_chained_rounds,
 ]

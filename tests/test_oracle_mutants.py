@@ -45,6 +45,11 @@ MUTANTS = {
     "homconv_mask_missing_delta": ("out[n * ostride] += or_delta(p) * (uint64_t)r", "out[n * ostride] += (uint64_t)r"),
     "homconv_wrong_word_stride": ("blk[(int64_t)j * Cin + i]", "blk[(int64_t)i * (n + 1) + j]"),
     "server_share_not_negated": ("s_b[k] = (uint32_t)((p - r[k] % p) % p);", "s_b[k] = (uint32_t)(r[k] % p);"),
+    "homrec_on_word0": ("ct[((b * F + f) * (int64_t)(n + 1) + n) * C + c] += delta", "ct[((b * F + f) * (int64_t)(n + 1)) * C + c] += delta"),
+    "homrec_missing_delta": ("+= delta * (uint64_t)s_hat[(b * C + c) * F + f];", "+= (uint64_t)s_hat[(b * C + c) * F + f];"),
+    "homrec_share_index_transposed": ("s_hat[(b * C + c) * F + f]", "s_hat[(b * F + f) * C + c]"),
+    "reshare_share_added": ("s_a_next[k] = (uint32_t)((u + p - s_b_next[k]) % p);", "s_a_next[k] = (uint32_t)((u + s_b_next[k]) % p);"),
+    "reshare_square_dropped": ("uint64_t u = act == 1 ? mulmod(y, y, p) : y;", "uint64_t u = y;"),
 }
 
 
