@@ -200,6 +200,31 @@ int ensei_homconv_valu(ensei_ctx *ctx, const uint64_t *ct_in, const uint32_t *w_
 int ensei_decrypt(ensei_ctx *ctx, const uint64_t *ct, const int8_t *s, int64_t batch, int C, int64_t F, int n,
                   uint32_t *m, void *stream);
 
+/* ----------------------------------------------------- chained rounds --
+ * HomRec (Eq. (homrec) in Sec. 3.2; Fig. 2 lines 11-13, Eq.
+ * (dft_convolution0)): the server adds its transformed share to the client's
+ * ciphertexts as a plaintext, [s_A] (+) s_B = [s_A + s_B mod p], so that the
+ * next round's HomConv runs on an encryption of the whole activation. In
+ * place: the b word of ciphertext (b, c, f) of ct: uint64 [batch][F][n+1][C]
+ * (word-major) gains Delta * s_hat[b][c][f] mod 2^64, s_hat: uint32
+ * [batch][C][F] with values < p (the server's share, transformed by
+ * ensei_ntt2d). Since Delta * p = 2^64 - 1, a sum that wraps past p adds -1
+ * to the ciphertext's noise. The a-words are not touched. 1 <= n <=
+ * ENSEI_MAX_LWE_N, 1 <= C <= ENSEI_MAX_COUT; ct 8-byte and s_hat 4-byte
+ * aligned and not overlapping. */
+int ensei_homrec(ensei_ctx *ctx, uint64_t *ct, const uint32_t *s_hat, int64_t batch, int C, int64_t F, int n,
+                 void *stream);
+
+/* A stand-in for the oblivious activation between rounds (Fig. 2 lines 7-8),
+ * computed in the clear so that chained rounds can run on one device (the
+ * garbled-circuit or triplet evaluation itself is outside this library):
+ *   s_a_next[k] = f((s_a[k] + s_b[k]) mod p) - s_b_next[k]  mod p,
+ * f the identity (act 0) or the square mod p (act 1), for count residues
+ * < p in each array (uint32); s_b_next is the server's fresh share. The
+ * output may alias any input. ENSEI_ERR_ARG for another act. */
+int ensei_reshare(ensei_ctx *ctx, const uint32_t *s_a, const uint32_t *s_b, const uint32_t *s_b_next, int64_t count,
+                  int act, uint32_t *s_a_next, void *stream);
+
 /* ------------------------------------------------------ batched plans --
  * A plan runs a stack of independent secure convolutions (Fig. 2's start
  * round for each layer; layers of uneven shapes, each over a batch of images

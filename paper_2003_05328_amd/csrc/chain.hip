@@ -1,0 +1,74 @@
+// Chained rounds of the frequency-domain secure convolution (Fig. 2, lines
+// 7-13): HomRec, the server's plaintext addition of its transformed share to
+// the client's ciphertexts (Eq. (homrec), Eq. (dft_convolution0)), and a
+// stand-in for the oblivious activation computed in the clear, so that a
+// round's output shares can feed the next round on one device.
+#include "ensei_internal.hpp"
+
+namespace ensei {
+
+// ct [B][F][n+1][C]: the b word of ciphertext (b, c, f) gains
+// Delta * s_hat[b][c][f] mod 2^64. Threads run over (b, f, c) with c fastest,
+// so a wave's b words are one contiguous run of a (b, f) block's word row n.
+__global__ __launch_bounds__(256) void homrec_kernel(uint64_t *__restrict__ ct, const uint32_t *__restrict__ s_hat,
+                                                     int64_t B, int C, int64_t F, int n, uint64_t delta) {
+    const int64_t total = B * F * C;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int c = (int)(t % C);
+        const int64_t x = t / C, f = x % F, b = x / F;
+        ct[((b * F + f) * (n + 1) + n) * C + c] += delta * (uint64_t)s_hat[(b * C + c) * F + f];
+    }
+}
+
+// s_a_next = f((s_a + s_b) mod p) - s_b_next mod p, f the identity (act 0)
+// or the square (act 1); every input a residue < p.
+__global__ __launch_bounds__(256) void reshare_kernel(const uint32_t *s_a, const uint32_t *s_b,
+                                                      const uint32_t *s_b_next, int64_t count, int act, uint32_t p,
+                                                      uint32_t *s_a_next) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < count;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t y = reduce_once(s_a[k] + s_b[k], p);
+        const uint32_t u = act == 1 ? (uint32_t)((uint64_t)y * y % p) : y;
+        s_a_next[k] = reduce_once(u + p - s_b_next[k], p);
+    }
+}
+
+static int64_t grid_for(int64_t items) {
+    const int64_t blocks = (items + 255) / 256;
+    return blocks < 65536 ? blocks : 65536;
+}
+
+}  // namespace ensei
+
+using namespace ensei;
+
+extern "C" {
+
+int ensei_homrec(ensei_ctx *ctx, uint64_t *ct, const uint32_t *s_hat, int64_t batch, int C, int64_t F, int n,
+                 void *stream) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!ct || !s_hat || batch <= 0 || C <= 0 || F <= 0 || n <= 0) return ENSEI_ERR_ARG;
+    if (n > ENSEI_MAX_LWE_N || C > ENSEI_MAX_COUT) return ENSEI_ERR_LIMIT;
+    if (((uintptr_t)ct & 7) || ((uintptr_t)s_hat & 3)) return ENSEI_ERR_ALIGN;
+    const size_t num = (size_t)batch * C * F;
+    if (overlaps(ct, num * (size_t)(n + 1) * 8, s_hat, num * 4)) return ENSEI_ERR_OVERLAP;
+    hipLaunchKernelGGL(homrec_kernel, dim3((unsigned)grid_for((int64_t)num)), dim3(256), 0, (hipStream_t)stream, ct,
+                       s_hat, batch, C, F, n, ctx->delta);
+    return launch_status();
+}
+
+int ensei_reshare(ensei_ctx *ctx, const uint32_t *s_a, const uint32_t *s_b, const uint32_t *s_b_next, int64_t count,
+                  int act, uint32_t *s_a_next, void *stream) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!s_a || !s_b || !s_b_next || !s_a_next || count <= 0 || (act != 0 && act != 1)) return ENSEI_ERR_ARG;
+    if (((uintptr_t)s_a & 3) || ((uintptr_t)s_b & 3) || ((uintptr_t)s_b_next & 3) || ((uintptr_t)s_a_next & 3))
+        return ENSEI_ERR_ALIGN;
+    hipLaunchKernelGGL(reshare_kernel, dim3((unsigned)grid_for(count)), dim3(256), 0, (hipStream_t)stream, s_a, s_b,
+                       s_b_next, count, act, ctx->p, s_a_next);
+    return launch_status();
+}
+
+}  // extern "C"

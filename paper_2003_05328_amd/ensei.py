@@ -52,6 +52,8 @@ SIGNATURES = {
     "ensei_homconv": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
     "ensei_homconv_valu": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
     "ensei_decrypt": (_i32, [_vp, _vp, _vp, _i64, _i32, _i64, _i32, _vp, _vp]),
+    "ensei_homrec": (_i32, [_vp, _vp, _vp, _i64, _i32, _i64, _i32, _vp]),
+    "ensei_reshare": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _vp, _vp]),
     "ensei_plan_create": (_i32, [_vp, _vp, _i32, C.c_char_p, C.POINTER(_vp)]),
     "ensei_plan_run": (_i32, [_vp, _vp]),
     "ensei_plan_schedule": (_i32, [_vp, _vp]),
@@ -290,6 +292,29 @@ class Context:
         shape = (F,) if flat else (B, C, F)
         out = self._out(out, shape, torch.uint32)
         self._call("ensei_decrypt", _ptr(ct), _ptr(s), B, C, F, n, _ptr(out))
+        return out
+
+    # -- chained rounds ---------------------------------------------------------
+    def homrec(self, ct, s_hat) -> torch.Tensor:
+        """In place: ct uint64 [B][F][n+1][C] gains Delta * s_hat[b][c][f] on
+        every b word, s_hat uint32 [B][C][F] (ensei_homrec); returns ct."""
+        self._dev(ct, "ct", torch.uint64)
+        self._dev(s_hat, "s_hat", torch.uint32)
+        B, F, n1, Cc = tuple(ct.shape)
+        if tuple(s_hat.shape) != (B, Cc, F):
+            raise ValueError(f"s_hat must be [B][C][F] = {(B, Cc, F)}")
+        self._call("ensei_homrec", _ptr(ct), _ptr(s_hat), B, Cc, F, n1 - 1)
+        return ct
+
+    def reshare(self, s_a, s_b, s_b_next, act: int, out=None) -> torch.Tensor:
+        """The activation stand-in: f((s_a + s_b) mod p) - s_b_next mod p,
+        f the identity (act 0) or the square (act 1) (ensei_reshare)."""
+        for name, t in (("s_a", s_a), ("s_b", s_b), ("s_b_next", s_b_next)):
+            self._dev(t, name, torch.uint32)
+        if not (s_a.numel() == s_b.numel() == s_b_next.numel()):
+            raise ValueError("the shares must hold the same number of residues")
+        out = self._out(out, tuple(s_a.shape), torch.uint32)
+        self._call("ensei_reshare", _ptr(s_a), _ptr(s_b), _ptr(s_b_next), s_a.numel(), int(act), _ptr(out))
         return out
 
     # -- HomConv ---------------------------------------------------------------
