@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--serve-rates", default="250,500,750,1000,1250,2000", help="arrival rates, requests/s")
     ap.add_argument("--serve-requests", type=int, default=1000, help="requests per rate")
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
+    ap.add_argument("--chained", action="store_true",
+                    help="only two protocol rounds chained by HomRec (the stack's 32x32 pair), one JSON line")
     ap.add_argument("--probe-copy", action="store_true",
                     help="run only a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     return ap.parse_args()
@@ -172,6 +174,81 @@ def ntt_throughput(ctx, S, reps: int = 20):
             "bytes_per_point": 8,
             "alu": {"achieved": tops, "peak": ALU_PEAK_TOPS, "unit": "T int32 op/s", "frac": tops / ALU_PEAK_TOPS,
                     "ops_per_launch": ops}}
+
+
+def chained(ctx, reps: int, seed: int, act: int = 1):
+    """Two rounds of Fig. 2 chained on the device: the CIFAR stack's 32x32
+    3 -> 64 and 64 -> 64 layers (batch 8, n = 1024), joined by the activation
+    stand-in (square), the client's NTT2D and Enc of its new share, and the
+    server's HomRec with its transformed share. Each pass includes both layers'
+    filter preparation. Checked on the pass's own intermediates: round 0's and
+    round 1's plaintexts, and the shares after the activation."""
+    import numpy as np
+    import torch
+    from paper_2003_05328_amd import configs, synth
+
+    P = configs.P
+    S0 = configs.WORKLOADS["stack8_L1_32x32_c3to64"]
+    S1 = configs.WORKLOADS["stack8_L2_32x32_c64to64"]
+    inp0, inp1 = synth.generate(S0, P, seed), synth.generate(S1, P, seed + 1)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    x0, w0, s0, e0, r0 = d(inp0.x), d(inp0.w), d(inp0.s), d(inp0.e.reshape(S0.B, S0.Cin, S0.F)), d(inp0.r)
+    w1, s1, e1, r1 = d(inp1.w), d(inp1.s), d(inp1.e.reshape(S1.B, S1.Cin, S1.F)), d(inp1.r)
+    s_b1 = d(synth.uniform_u32(seed + 2, (S1.B, S1.Cin, S1.H, S1.W), P))
+    names = ["round0", "reshare", "client_ntt_enc", "homrec", "round1"]
+    keep = {}
+
+    def pass_(ev=None):
+        mark = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
+        mark(0)
+        x_hat0 = ctx.ntt2d(x0)
+        w_hat0 = ctx.weight_prep(w0, S0.H, S0.W)
+        ct0 = ctx.encrypt(x_hat0, s0, e0, inp0.seed_a)
+        m0 = ctx.decrypt(ctx.homconv(ct0, ctx.pack_weights(w_hat0), r0, S0.Cout), s0)
+        s_a0 = ctx.intt2d(m0, S0.H, S0.W)
+        s_b0 = ctx.server_share(r0, S0.H, S0.W)
+        mark(1)
+        s_a1 = ctx.reshare(s_a0, s_b0, s_b1, act)
+        mark(2)
+        x_hat1 = ctx.ntt2d(s_a1)
+        ct1 = ctx.encrypt(x_hat1, s1, e1, inp1.seed_a)
+        sb_hat = ctx.ntt2d(s_b1)
+        mark(3)
+        ctx.homrec(ct1, sb_hat)
+        mark(4)
+        w_hat1 = ctx.weight_prep(w1, S1.H, S1.W)
+        m1 = ctx.decrypt(ctx.homconv(ct1, ctx.pack_weights(w_hat1), r1, S1.Cout), s1)
+        s_a = ctx.intt2d(m1, S1.H, S1.W)
+        s_b = ctx.server_share(r1, S1.H, S1.W)
+        mark(5)
+        keep.update(x_hat0=x_hat0, w_hat0=w_hat0, m0=m0, s_a0=s_a0, s_b0=s_b0, s_a1=s_a1, x_hat1=x_hat1,
+                    sb_hat=sb_hat, w_hat1=w_hat1, m1=m1, s_a=s_a, s_b=s_b)
+
+    for _ in range(2):
+        pass_()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(reps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(reps):
+        pass_(events[k])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    part_us = {nm: float(np.mean([ev[i].elapsed_time(ev[i + 1]) for ev in events])) * 1e3 for i, nm in enumerate(names)}
+    h = {k: v.cpu().numpy().astype(np.int64) for k, v in keep.items()}
+    ok0 = np.array_equal(h["m0"], (np.einsum("oif,bif->bof", h["w_hat0"], h["x_hat0"]) + inp0.r) % P)
+    y0 = (h["s_a0"] + h["s_b0"]) % P
+    ok_act = np.array_equal((h["s_a1"] + s_b1.cpu().numpy()) % P, y0 if act == 0 else y0 * y0 % P)
+    u_hat = (h["x_hat1"] + h["sb_hat"]) % P  # the transform of the reconstructed activation
+    ok1 = np.array_equal(h["m1"], (np.einsum("oif,bif->bof", h["w_hat1"], u_hat) + inp1.r) % P)
+    macs = S0.B * S0.Cout * S0.Cin * S0.F + S1.B * S1.Cout * S1.Cin * S1.F
+    n_ct = S1.B * S1.Cin * S1.F
+    hr_bytes = n_ct * (4 + 8 + 8)  # the share read, each b word read and written
+    return {"workload": "CIFAR stack layers 1-2 chained: 32x32 3->64 then 64->64, 3x3, n=1024, batch 8, "
+                        f"activation {'square' if act else 'identity'} (stand-in, in the clear)",
+            "ms_per_pass": ms, "ct_mac_per_s": macs / (ms * 1e-3), "parts_us": part_us,
+            "homrec": {"ciphertexts": n_ct, "bytes": hr_bytes, "us": part_us["homrec"],
+                       "achieved_gbs": hr_bytes / (part_us["homrec"] * 1e-6) / 1e9},
+            "bit_exact": bool(ok0 and ok_act and ok1)}
 
 
 def stack_batched(ctx, reps: int, seed: int):
@@ -445,6 +522,17 @@ def main():
     if args.probe_copy:
         probe_copy()
         return
+    if args.chained:
+        from paper_2003_05328_amd.ensei import Context
+
+        res = chained(Context(65537, 0), args.steps, args.seed)
+        print(json.dumps({"metric": "chained secure-conv rounds: ciphertext-MACs/s over both rounds",
+                          "value": res["ct_mac_per_s"], "unit": "ct-MAC/s", "n_gpus": 1, "steps": args.steps,
+                          "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+                          "config": {"workload": res["workload"]}, "chained": res}), flush=True)
+        if not res["bit_exact"]:
+            sys.exit(3)
+        return
     if args.serve:
         from paper_2003_05328_amd.ensei import Context
 
@@ -610,6 +698,9 @@ def main():
         result["homconv_layers"] = homconv_layers(ctx)
         result["batched"] = stack_batched(ctx, args.stack_reps, args.seed)
         result["verified"] = result["verified"] and result["batched"]["bit_exact_vs_sequential"]
+        torch.cuda.empty_cache()
+        result["chained"] = chained(ctx, args.stack_reps, args.seed)
+        result["verified"] = result["verified"] and result["chained"]["bit_exact"]
         torch.cuda.empty_cache()
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         result["serving"] = serving(ctx, rates, args.serve_requests, args.serve_budget_gb, args.seed)

@@ -201,7 +201,7 @@ int ensei_decrypt(ensei_ctx *ctx, const uint64_t *ct, const int8_t *s, int64_t b
                   uint32_t *m, void *stream);
 
 /* ----------------------------------------------------- chained rounds --
- * HomRec (Eq. (homrec) in Sec. 3.2; Fig. 2 lines 11-13, Eq.
+ * HomRec (Eq. (homrec) in Sec. 3.2; Fig. 2's re-entry of the server's share, Eq.
  * (dft_convolution0)): the server adds its transformed share to the client's
  * ciphertexts as a plaintext, [s_A] (+) s_B = [s_A + s_B mod p], so that the
  * next round's HomConv runs on an encryption of the whole activation. In
@@ -215,7 +215,7 @@ int ensei_decrypt(ensei_ctx *ctx, const uint64_t *ct, const int8_t *s, int64_t b
 int ensei_homrec(ensei_ctx *ctx, uint64_t *ct, const uint32_t *s_hat, int64_t batch, int C, int64_t F, int n,
                  void *stream);
 
-/* A stand-in for the oblivious activation between rounds (Fig. 2 lines 7-8),
+/* A stand-in for the oblivious activation between the rounds of Fig. 2,
  * computed in the clear so that chained rounds can run on one device (the
  * garbled-circuit or triplet evaluation itself is outside this library):
  *   s_a_next[k] = f((s_a[k] + s_b[k]) mod p) - s_b_next[k]  mod p,

@@ -209,7 +209,7 @@ class Oracle:
         return out
 
     def fdsc_round1(self, r0: dict, inp1, s_b1, act: int, p: int):
-        """The next round of Fig. 2 (lines 7-13) after round r0 (fdsc_round0's
+        """The next round of Fig. 2 (activation, re-encryption, HomRec, convolution) after round r0 (fdsc_round0's
         result), with the activation replaced by reshare in the clear.
 
         inp1 holds the next layer (its filters w over Cin = the previous Cout,

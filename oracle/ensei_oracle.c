@@ -324,7 +324,7 @@ void or_server_share(uint64_t p, int64_t batch, int H, int W, const uint32_t *r,
 
 /* ------------------------------------------------- chained rounds --- */
 
-/* HomRec (Eq. (homrec); Fig. 2 lines 11-13, Eq. (dft_convolution0)): the
+/* HomRec (Eq. (homrec); Fig. 2's re-entry of the server's share, Eq. (dft_convolution0)): the
  * server adds its transformed share to the client's ciphertexts as a
  * plaintext, [s_A] (+) s_B = [s_A + s_B mod p]: Delta * s_hat[b][c][f] is
  * added to the b word of ciphertext (b, c, f) of ct [B][F][n+1][C], in place.
@@ -337,7 +337,7 @@ void or_homrec(uint64_t p, int64_t B, int C, int64_t F, int n, uint64_t *ct, con
                 ct[((b * F + f) * (int64_t)(n + 1) + n) * C + c] += delta * (uint64_t)s_hat[(b * C + c) * F + f];
 }
 
-/* Stand-in for the oblivious activation of Fig. 2 lines 7-8, computed in the
+/* Stand-in for the oblivious activation between the rounds of Fig. 2, computed in the
  * clear: y = s_A + s_B mod p, u = f(y) (act 0: identity, 1: square mod p),
  * and the client's next share s_A' = u - s_B' mod p for the server's fresh
  * share s_B'. All arrays hold count residues in [0, p). */

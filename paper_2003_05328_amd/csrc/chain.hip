@@ -1,5 +1,5 @@
-// Chained rounds of the frequency-domain secure convolution (Fig. 2, lines
-// 7-13): HomRec, the server's plaintext addition of its transformed share to
+// Chained rounds of the frequency-domain secure convolution (Fig. 2's later
+// rounds): HomRec, the server's plaintext addition of its transformed share to
 // the client's ciphertexts (Eq. (homrec), Eq. (dft_convolution0)), and a
 // stand-in for the oblivious activation computed in the clear, so that a
 // round's output shares can feed the next round on one device.
@@ -8,16 +8,40 @@
 namespace ensei {
 
 // ct [B][F][n+1][C]: the b word of ciphertext (b, c, f) gains
-// Delta * s_hat[b][c][f] mod 2^64. Threads run over (b, f, c) with c fastest,
-// so a wave's b words are one contiguous run of a (b, f) block's word row n.
-__global__ __launch_bounds__(256) void homrec_kernel(uint64_t *__restrict__ ct, const uint32_t *__restrict__ s_hat,
-                                                     int64_t B, int C, int64_t F, int n, uint64_t delta) {
-    const int64_t total = B * F * C;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int c = (int)(t % C);
-        const int64_t x = t / C, f = x % F, b = x / F;
-        ct[((b * F + f) * (n + 1) + n) * C + c] += delta * (uint64_t)s_hat[(b * C + c) * F + f];
+// Delta * s_hat[b][c][f] mod 2^64. The share is channel-major and the b words
+// frequency-major, so each block moves a tile of kHrC channels by kHrF
+// frequencies of one image through LDS: it reads the share along f (whole
+// 128-byte rows) and updates the b words along c (a wave's 64 words are one
+// contiguous 512-byte run of a (b, f) block's word row n). Reading the share
+// straight along c would touch one line per lane, and the blocks of
+// neighbouring f, spread over the XCDs, would fetch each line once per L2.
+// 1024 threads move two elements each per phase, so that a tile's few
+// dependent memory steps are overlapped by many waves.
+constexpr int kHrC = 64, kHrF = 32, kHrThreads = 1024;
+static_assert(kHrC * kHrF % kHrThreads == 0 && kHrThreads % kHrF == 0 && kHrThreads % kHrC == 0, "homrec tile");
+
+__global__ __launch_bounds__(kHrThreads) void homrec_kernel(uint64_t *__restrict__ ct,
+                                                            const uint32_t *__restrict__ s_hat, int64_t B, int C,
+                                                            int64_t F, int n, uint64_t delta) {
+    __shared__ uint32_t tile[kHrC][kHrF + 1];
+    const int t = threadIdx.x;
+    const int64_t c_tiles = (C + kHrC - 1) / kHrC, f_tiles = (F + kHrF - 1) / kHrF;
+    const int64_t tiles = B * c_tiles * f_tiles;
+    for (int64_t T = blockIdx.x; T < tiles; T += gridDim.x) {
+        const int64_t ft = T % f_tiles, rest = T / f_tiles;
+        const int c0 = (int)(rest % c_tiles) * kHrC;
+        const int64_t b = rest / c_tiles, f0 = ft * kHrF;
+        for (int k = 0; k < kHrC * kHrF / kHrThreads; ++k) {
+            const int cl = k * (kHrThreads / kHrF) + t / kHrF, fl = t % kHrF;
+            if (c0 + cl < C && f0 + fl < F) tile[cl][fl] = s_hat[(b * C + c0 + cl) * F + f0 + fl];
+        }
+        __syncthreads();
+        for (int k = 0; k < kHrC * kHrF / kHrThreads; ++k) {
+            const int cl = t % kHrC, fl = k * (kHrThreads / kHrC) + t / kHrC;
+            const int64_t f = f0 + fl;
+            if (c0 + cl < C && f < F) ct[((b * F + f) * (n + 1) + n) * C + c0 + cl] += delta * (uint64_t)tile[cl][fl];
+        }
+        __syncthreads();
     }
 }
 
@@ -54,8 +78,9 @@ int ensei_homrec(ensei_ctx *ctx, uint64_t *ct, const uint32_t *s_hat, int64_t ba
     if (((uintptr_t)ct & 7) || ((uintptr_t)s_hat & 3)) return ENSEI_ERR_ALIGN;
     const size_t num = (size_t)batch * C * F;
     if (overlaps(ct, num * (size_t)(n + 1) * 8, s_hat, num * 4)) return ENSEI_ERR_OVERLAP;
-    hipLaunchKernelGGL(homrec_kernel, dim3((unsigned)grid_for((int64_t)num)), dim3(256), 0, (hipStream_t)stream, ct,
-                       s_hat, batch, C, F, n, ctx->delta);
+    const int64_t tiles = batch * ((C + kHrC - 1) / kHrC) * ((F + kHrF - 1) / kHrF);
+    hipLaunchKernelGGL(homrec_kernel, dim3((unsigned)(tiles < 65536 ? tiles : 65536)), dim3(kHrThreads), 0,
+                       (hipStream_t)stream, ct, s_hat, batch, C, F, n, ctx->delta);
     return launch_status();
 }
 

@@ -348,7 +348,7 @@ def check_end_to_end(orc):
 
 
 def check_homrec(orc):
-    """HomRec (Eq. homrec; Fig. 2 lines 11-13): Dec(HomRec(Enc(m), s)) = m + s
+    """HomRec (Eq. homrec; Fig. 2's re-entry of the server's share): Dec(HomRec(Enc(m), s)) = m + s
     mod p at edge residues and inside; since Delta p = 2^64 - 1 the phase is
     Delta ((m + s) mod p) plus the encryption error, minus 1 exactly when
     m + s wraps past p; the a-words are untouched. Ciphertexts of several
@@ -375,7 +375,7 @@ def check_homrec(orc):
 
 
 def check_reshare(orc):
-    """The stand-in for the oblivious activation (Fig. 2 lines 7-8, in the
+    """The stand-in for the oblivious activation between the rounds of Fig. 2 (in the
     clear): the shares after it add up to f(s_A + s_B) mod p, f the identity
     or the square, edge residues included."""
     g = _rng(19)
@@ -394,7 +394,7 @@ def check_reshare(orc):
 def check_chained_rounds(orc):
     """Round 0, the activation stand-in, Enc of the client's new share,
     HomRec with the server's transformed share, and round 1: the final shares
-    add up to conv(f(conv(x, w0)), w1) mod p (Fig. 2 lines 1-13; Eq.
+    add up to conv(f(conv(x, w0)), w1) mod p (two rounds of Fig. 2; Eq.
     dft_convolution)."""
     S0 = synth.LayerShape(H=8, W=4, Cin=2, Cout=3, kh=3, kw=2, n=24, B=2)
     S1 = synth.LayerShape(H=8, W=4, Cin=3, Cout=2, kh=2, kw=3, n=24, B=2, hidden=True)

@@ -1,4 +1,4 @@
-"""GPU parity of chained rounds (Fig. 2 lines 7-13): HomRec and the
+"""GPU parity of chained rounds (Fig. 2's later rounds): HomRec and the
 in-the-clear activation stand-in against the oracle bit for bit, and two
 secure-convolution rounds joined by them on the device, every intermediate
 equal to the oracle's and the final shares adding up to the composed
@@ -30,7 +30,10 @@ def orc():
     return o
 
 
-@pytest.mark.parametrize("B,F,n,C", [(1, 1, 1, 1), (2, 5, 16, 64), (1, 3, 8, 7), (3, 64, 4, 130), (2, 256, 40, 3)])
+# shapes: single element, partial and several channel tiles, ragged frequency
+# tiles, and more tiles than the launch has blocks (the grid-stride loop)
+@pytest.mark.parametrize("B,F,n,C", [(1, 1, 1, 1), (2, 5, 16, 64), (1, 3, 8, 7), (3, 64, 4, 130), (2, 256, 40, 3),
+                                     (2, 100, 8, 70), (1, 65538 * 32 - 5, 1, 1)])
 def test_homrec(ctx, orc, B, F, n, C):
     ct = synth.uniform_u64(50 + C, (B, F, n + 1, C))
     s_hat = synth.uniform_u32(51 + C, (B, C, F), P)
