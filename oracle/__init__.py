@@ -35,6 +35,7 @@ _SIG = {
     "or_encrypt": (None, [u64, i64, i32, i64, i32, vp, vp, vp, u64, u64, vp]),
     "or_phase": (u64, [i32, vp, i64, vp]),
     "or_decrypt": (None, [u64, i64, i32, i64, i32, vp, vp, vp]),
+    "or_expand_seeded": (None, [i64, i32, i64, i32, u64, u64, vp, vp]),
     "or_homconv": (None, [u64, i32, i32, i32, i64, i32, vp, vp, vp, vp]),
     "or_homconv_select": (None, [u64, i32, i32, i32, i64, i32, vp, vp, vp, i64, vp, vp]),
     "or_server_share": (None, [u64, i64, i32, i32, vp, vp]),
@@ -158,6 +159,26 @@ class Oracle:
         m = np.empty((B, C, F), dtype=np.uint32)
         self.lib.or_decrypt(p, B, C, F, n, _p(ct), _p(s), _p(m))
         return m.reshape(F) if flat else m
+
+    def expand_seeded(self, bw, n: int, seed_a: int, ct_index0: int = 0) -> np.ndarray:
+        """Seeded ciphertexts (Sec. 5.1: the public constants generated
+        offline): b words bw[B][F][C] -> ct[B][F][n+1][C], word j < n of
+        ciphertext (b, c, f) the generator's output (ct_index0 + q) n + j + 1."""
+        bw = _c(bw, np.uint64)
+        B, F, C = bw.shape
+        ct = np.empty((B, F, n + 1, C), dtype=np.uint64)
+        self.lib.or_expand_seeded(B, C, F, n, seed_a % 2**64, ct_index0 % 2**64, _p(bw), _p(ct))
+        return ct
+
+    def encrypt_seeded(self, m, s, e, seed_a: int, p: int, ct_index0: int = 0) -> np.ndarray:
+        """What a client sends for seeded ciphertexts: the b words of Enc,
+        bw[B][F][C] = Enc(m)[b][f][n][c] (the a-words follow from seed_a)."""
+        n = np.asarray(s).shape[0]
+        return np.ascontiguousarray(self.encrypt(m, s, e, seed_a, p, ct_index0)[:, :, n, :])
+
+    def homconv_seeded(self, bw, n: int, seed_a: int, w_hat, r, p: int, ct_index0: int = 0) -> np.ndarray:
+        """HomConv of the seeded ciphertexts given by (seed_a, ct_index0, bw)."""
+        return self.homconv(self.expand_seeded(bw, n, seed_a, ct_index0), w_hat, r, p)
 
     def homconv(self, ct_in, w_hat, r, p: int) -> np.ndarray:
         """ct_in[B][F][n+1][Cin], w_hat[Cout][Cin][F], r[B][Cout][F] -> ct_out[B][F][n+1][Cout]."""

@@ -273,6 +273,27 @@ void or_decrypt(uint64_t p, int64_t B, int C, int64_t F, int n, const uint64_t *
             }
 }
 
+/* A seeded ciphertext: Sec. 5.1 notes that the public constants of a
+ * ciphertext can be generated offline. Here they are the a-words of the
+ * SplitMix64 stream above, so a batch of ciphertexts is fully given by seed_a,
+ * its first index and its b words, and only the b words travel. Expands
+ * bw[b][f][c] into ct [B][F][n+1][C]: word j < n of ciphertext
+ * q = (b F + f) C + c is output number (q0 + q) n + j + 1 of the generator
+ * seeded with seed_a (the words or_encrypt writes), word n is bw[b][f][c]. */
+void or_expand_seeded(int64_t B, int C, int64_t F, int n, uint64_t seed_a, uint64_t ct_index0, const uint64_t *bw,
+                      uint64_t *ct) {
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t b = 0; b < B; ++b)
+        for (int64_t f = 0; f < F; ++f)
+            for (int c = 0; c < C; ++c) {
+                uint64_t q = (uint64_t)((b * F + f) * C + c);
+                uint64_t *w = ct + (b * F + f) * (int64_t)(n + 1) * C + c;
+                for (int j = 0; j < n; ++j)
+                    w[(int64_t)j * C] = or_splitmix64(seed_a, (ct_index0 + q) * (uint64_t)n + (uint64_t)j + 1);
+                w[(int64_t)n * C] = bw[(b * F + f) * C + c];
+            }
+}
+
 /* --------------------------------------------------------- HomConv --- */
 
 /* One output ciphertext of HomConv for (image b, output channel o,

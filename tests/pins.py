@@ -410,6 +410,40 @@ def check_chained_rounds(orc):
         assert np.array_equal(got.reshape(want.shape), want), act
 
 
+def check_seeded(orc):
+    """Seeded ciphertexts (Sec. 5.1: the ciphertexts' public constants are
+    generated offline, so only the b words travel). The expansion's a-words
+    are the generator's stream at the stated counters (a stateful big-int
+    generator, independent of the oracle's); its b row is the given words; Enc
+    followed by dropping the a-words and expanding again is the identity; and
+    HomConv of the expansion decrypts to sum_i W^ m + r."""
+    g = _rng(23)
+    B, C, F, n, seed_a, c0 = 2, 3, 5, 16, 0x0F1E2D3C4B5A6978, 11
+    bw = synth.uniform_u64(24, (B, F, C))
+    ct = orc.expand_seeded(bw, n, seed_a, ct_index0=c0)
+    assert ct.shape == (B, F, n + 1, C)
+    stream = bf.splitmix64_stream(seed_a, (c0 + B * C * F) * n)
+    for b in range(B):
+        for c in range(C):
+            for f in range(F):
+                q = (b * F + f) * C + c
+                assert [int(v) for v in ct[b, f, :n, c]] == stream[(c0 + q) * n : (c0 + q + 1) * n]
+                assert int(ct[b, f, n, c]) == int(bw[b, f, c])
+    m = g.integers(0, P, size=(B, C, F)).astype(np.uint32)
+    s = synth.ternary(25, n)
+    e = synth.rounded_gaussian(26, (B, C, F))
+    full = orc.encrypt(m, s, e, seed_a, P, ct_index0=c0)
+    b_only = orc.encrypt_seeded(m, s, e, seed_a, P, ct_index0=c0)
+    assert b_only.shape == (B, F, C)
+    assert np.array_equal(orc.expand_seeded(b_only, n, seed_a, ct_index0=c0), full)
+    Cout = 4
+    w_hat = g.integers(0, P, size=(Cout, C, F)).astype(np.uint32)
+    r = g.integers(0, P, size=(B, Cout, F)).astype(np.uint32)
+    out = orc.homconv_seeded(b_only, n, seed_a, w_hat, r, P, ct_index0=c0)
+    want = (np.einsum("oif,bif->bof", w_hat.astype(np.int64), m.astype(np.int64)) + r) % P
+    assert np.array_equal(orc.decrypt(out, s, P).astype(np.int64), want)
+
+
 ALL_CHECKS = [
     check_roots,
     check_delta,
@@ -431,4 +465,5 @@ ALL_CHECKS = [
     check_homrec,
     check_reshare,
     check_chained_rounds,
+    check_seeded,
 ]

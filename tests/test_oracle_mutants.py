@@ -49,6 +49,11 @@ MUTANTS = {
     "homrec_missing_delta": ("+= delta * (uint64_t)s_hat[(b * C + c) * F + f];", "+= (uint64_t)s_hat[(b * C + c) * F + f];"),
     "homrec_share_index_transposed": ("s_hat[(b * C + c) * F + f]", "s_hat[(b * F + f) * C + c]"),
     "reshare_share_added": ("s_a_next[k] = (uint32_t)((u + p - s_b_next[k]) % p);", "s_a_next[k] = (uint32_t)((u + s_b_next[k]) % p);"),
+    "seeded_counter_off_by_one": ("w[(int64_t)j * C] = or_splitmix64(seed_a, (ct_index0 + q) * (uint64_t)n + (uint64_t)j + 1);",
+                                  "w[(int64_t)j * C] = or_splitmix64(seed_a, (ct_index0 + q) * (uint64_t)n + (uint64_t)j);"),
+    "seeded_index_offset_dropped": ("w[(int64_t)j * C] = or_splitmix64(seed_a, (ct_index0 + q) * (uint64_t)n",
+                                    "w[(int64_t)j * C] = or_splitmix64(seed_a, q * (uint64_t)n"),
+    "seeded_b_words_transposed": ("w[(int64_t)n * C] = bw[(b * F + f) * C + c];", "w[(int64_t)n * C] = bw[(b * C + c) * F + f];"),
     "reshare_square_dropped": ("uint64_t u = act == 1 ? mulmod(y, y, p) : y;", "uint64_t u = y;"),
 }
 
