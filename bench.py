@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--serve-rates", default="250,500,750,1000,1250,2000", help="arrival rates, requests/s")
     ap.add_argument("--serve-requests", type=int, default=1000, help="requests per rate")
     ap.add_argument("--serve-budget-gb", type=float, default=160.0)
+    ap.add_argument("--seeded", action="store_true",
+                    help="only the main workload's step with seeded ciphertexts, one JSON line")
     ap.add_argument("--chained", action="store_true",
                     help="only two protocol rounds chained by HomRec (the stack's 32x32 pair), one JSON line")
     ap.add_argument("--probe-copy", action="store_true",
@@ -174,6 +176,77 @@ def ntt_throughput(ctx, S, reps: int = 20):
             "bytes_per_point": 8,
             "alu": {"achieved": tops, "peak": ALU_PEAK_TOPS, "unit": "T int32 op/s", "frac": tops / ALU_PEAK_TOPS,
                     "ops_per_launch": ops}}
+
+
+def seeded_step(ctx, S, inp, steps: int, warmup: int):
+    """The whole step of the main workload with seeded ciphertexts (Sec. 5.1:
+    the ciphertexts' public constants are generated offline): Enc keeps only
+    the b words and HomConv regenerates the a-words. Checked like the main
+    step (exact decryption of every output)."""
+    import numpy as np
+    import torch
+    from paper_2003_05328_amd import configs
+    from paper_2003_05328_amd.ensei import lib
+
+    P = configs.P
+    dv = "cuda:0"
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dv)
+    x, w, s, e, r = d(inp.x), d(inp.w), d(inp.s), d(inp.e), d(inp.r)
+    pack_bytes = int(lib().ensei_wpack_bytes(S.Cout, S.Cin, S.F))
+    w_hat = torch.empty((S.Cout, S.Cin, S.F), dtype=torch.uint32, device=dv)
+    pack = torch.empty((pack_bytes,), dtype=torch.int8, device=dv)
+    x_hat = torch.empty((S.B, S.Cin, S.F), dtype=torch.uint32, device=dv)
+    b_in = torch.empty((S.B, S.F, S.Cin), dtype=torch.uint64, device=dv)
+    ct_out = torch.empty((S.B, S.F, S.n + 1, S.Cout), dtype=torch.uint64, device=dv)
+    m = torch.empty((S.B, S.Cout, S.F), dtype=torch.uint32, device=dv)
+    s_a = torch.empty((S.B, S.Cout, S.H, S.W), dtype=torch.uint32, device=dv)
+    s_b = torch.empty((S.B, S.Cout, S.H, S.W), dtype=torch.uint32, device=dv)
+    names = ["weight_prep", "pack_weights", "ntt2d", "encrypt_seeded", "homconv_seeded", "decrypt", "intt2d",
+             "server_share"]
+
+    def step(ev=None):
+        mark = (lambda i: ev[i].record()) if ev is not None else (lambda i: None)
+        mark(0)
+        ctx.weight_prep(w, S.H, S.W, out=w_hat)
+        mark(1)
+        ctx.pack_weights(w_hat, out=pack)
+        mark(2)
+        ctx.ntt2d(x, out=x_hat)
+        mark(3)
+        ctx.encrypt_seeded(x_hat, s, e, inp.seed_a, out=b_in)
+        mark(4)
+        ctx.homconv_seeded(b_in, S.n, inp.seed_a, pack, r, S.Cout, out=ct_out)
+        mark(5)
+        ctx.decrypt(ct_out, s, out=m)
+        mark(6)
+        ctx.intt2d(m, S.H, S.W, out=s_a)
+        mark(7)
+        ctx.server_share(r, S.H, S.W, out=s_b)
+        mark(8)
+
+    for _ in range(warmup):
+        step()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    xh = x_hat.cpu().numpy().astype(np.int64)
+    wh = w_hat.cpu().numpy().astype(np.int64)
+    ok = bool(np.array_equal(m.cpu().numpy().astype(np.int64), (np.einsum("oif,bif->bof", wh, xh) + inp.r) % P))
+    kernels_us = {nm: float(np.mean([ev[i].elapsed_time(ev[i + 1]) for ev in events])) * 1e3
+                  for i, nm in enumerate(names)}
+    hc_us = kernels_us["homconv_seeded"]
+    # algorithmic bytes of the seeded HomConv: b words in, ct_out out, weights, masks
+    hc_bytes = 8 * S.F * S.B * (S.Cin + (S.n + 1) * S.Cout) + pack_bytes + 4 * S.B * S.Cout * S.F
+    macs = S.B * S.Cout * S.Cin * S.F
+    return {"ms_per_step": ms, "ct_mac_per_s": macs / (ms * 1e-3), "kernels_us": kernels_us,
+            "homconv_seeded": {"algorithmic_bytes": hc_bytes, "avg_us": hc_us,
+                               "achieved_gbs": hc_bytes / (hc_us * 1e-6) / 1e9,
+                               "frac_hbm": hc_bytes / (hc_us * 1e-6) / 1e9 / HBM_PEAK_GBS},
+            "verified": ok}
 
 
 def chained(ctx, reps: int, seed: int, act: int = 1):
@@ -522,6 +595,19 @@ def main():
     if args.probe_copy:
         probe_copy()
         return
+    if args.seeded:
+        from paper_2003_05328_amd import configs, synth
+        from paper_2003_05328_amd.ensei import Context
+
+        S = configs.WORKLOADS[args.workload]
+        res = seeded_step(Context(configs.P, 0), S, synth.generate(S, configs.P, args.seed), args.steps, args.warmup)
+        print(json.dumps({"metric": "HomConv ciphertext-MACs/s, whole secure-conv step with seeded ciphertexts",
+                          "value": res["ct_mac_per_s"], "unit": "ct-MAC/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+                          "config": {"workload": args.workload}, "seeded": res}), flush=True)
+        if not res["verified"]:
+            sys.exit(3)
+        return
     if args.chained:
         from paper_2003_05328_amd.ensei import Context
 
@@ -694,6 +780,9 @@ def main():
     if not args.no_extras:
         result["ntt2d"] = ntt_throughput(ctx, S)
         del ct_in, ct_out
+        torch.cuda.empty_cache()
+        result["seeded"] = seeded_step(ctx, S, inp, args.steps, args.warmup)
+        result["verified"] = result["verified"] and result["seeded"]["verified"]
         torch.cuda.empty_cache()
         result["homconv_layers"] = homconv_layers(ctx)
         result["batched"] = stack_batched(ctx, args.stack_reps, args.seed)

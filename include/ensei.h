@@ -225,6 +225,32 @@ int ensei_homrec(ensei_ctx *ctx, uint64_t *ct, const uint32_t *s_hat, int64_t ba
 int ensei_reshare(ensei_ctx *ctx, const uint32_t *s_a, const uint32_t *s_b, const uint32_t *s_b_next, int64_t count,
                   int act, uint32_t *s_a_next, void *stream);
 
+/* --------------------------------------------------- seeded ciphertexts --
+ * The a-words of every ciphertext are the public stream of Enc above (the
+ * encryption constants that Sec. 5.1 generates offline), so a batch of
+ * ciphertexts is fully given by (seed_a, ct_index0) and its b words: only the
+ * b words need to be stored or sent, and the server regenerates the a-words
+ * inside HomConv instead of reading them.
+ *
+ * Enc that keeps only the b words: b_out: uint64 [B][F][C] with
+ * b_out[b][f][c] = word n of ensei_encrypt's ciphertext (b, c, f) for the same
+ * arguments (8-byte aligned, not overlapping m, s or e). Limits and errors as
+ * ensei_encrypt. */
+int ensei_encrypt_seeded(ensei_ctx *ctx, const uint32_t *m, const int8_t *s, const int32_t *e, int64_t batch, int C,
+                         int64_t F, int n, uint64_t seed_a, uint64_t ct_index0, uint64_t *b_out, void *stream);
+
+/* HomConv of seeded ciphertexts: the same ct_out, bit for bit, as
+ * ensei_homconv on the word-major ciphertexts whose word j < n of ciphertext
+ * (b, i, f) is SplitMix64 output number (ct_index0 + q)*n + j + 1 of seed_a
+ * (q = (b*F + f)*Cin + i, as ensei_encrypt) and whose word n is
+ * b_in[b][f][i]; b_in: uint64 [batch][F][Cin], 8-byte aligned.
+ * w_pack, r, ct_out, limits and errors as ensei_homconv; the input side
+ * moves 8 bytes per ciphertext instead of 8 (n+1). Runs the narrow-input
+ * kernel for Cin <= 8 and the streaming matrix-core kernel otherwise. */
+int ensei_homconv_seeded(ensei_ctx *ctx, const uint64_t *b_in, uint64_t seed_a, uint64_t ct_index0,
+                         const int8_t *w_pack, const uint32_t *r, int64_t batch, int Cin, int Cout, int64_t F, int n,
+                         uint64_t *ct_out, void *stream);
+
 /* ------------------------------------------------------ batched plans --
  * A plan runs a stack of independent secure convolutions (Fig. 2's start
  * round for each layer; layers of uneven shapes, each over a batch of images

@@ -61,10 +61,25 @@ __device__ __forceinline__ uint32_t reduce_once(uint32_t x, uint32_t m) {
     return y < x ? y : x;  // y < x exactly when x >= m
 }
 
+// --------------------------------------------------- a-word generator --
+constexpr uint64_t kGamma = 0x9e3779b97f4a7c15ull;
+
+// SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014): output number k
+// of the generator seeded with x is mix(x + k * gamma). Word j < n of
+// ciphertext q (q = (b F + f) C + c, counted from ct_index0) is output number
+// (ct_index0 + q) n + j + 1 of the generator seeded with seed_a.
+__device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
 // ------------------------------------------------------------ HomConv --
 // One HomConv problem of a launch; a multi-problem launch reads an array of
 // these from device memory. tile0 is the problem's first tile in the
 // launch's concatenated tile space (tiles of 64 rows x 64 words per (b, f)).
+// Seeded input (ensei_homconv_seeded): ct_in is unused; the b words are
+// b_in [B][F][Cin] and the a-words come from (seed_a, idx0).
 struct HcLayer {
     const uint64_t *ct_in;
     const int8_t *w_pack;
@@ -72,6 +87,8 @@ struct HcLayer {
     uint64_t *ct_out;
     int64_t F, B, tile0, n_tiles;
     int Cin, Cout, n, n_ot, n_jt, n_ks, n_items, pad;
+    const uint64_t *b_in;
+    uint64_t seed_a, idx0;
 };
 
 // Tile schedule of a HomConv launch: persistent workgroups, and chunk = 0
@@ -96,8 +113,11 @@ int pack_weights_as(const ensei_ctx *ctx, const uint32_t *w_hat, int Cout, int C
 // HomConv's size limits alone (ENSEI_ERR_ARG / ENSEI_ERR_LIMIT).
 int homconv_sizes(int64_t batch, int Cin, int Cout, int64_t F, int n);
 // Checks one problem's sizes and fills its derived fields (tile0 = 0).
+// seeded: ct_in points at the b words [B][F][Cin] of seeded ciphertexts
+// (the caller sets seed_a and idx0)
 int homconv_problem(const ensei_ctx *ctx, HcLayer *P, const uint64_t *ct_in, const int8_t *w_pack, const uint32_t *r,
-                    int64_t B, int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, size_t wbytes);
+                    int64_t B, int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, size_t wbytes,
+                    bool seeded = false);
 // Whether a single problem (paired fragments) runs on the deep-layer kernel;
 // batched launches keep such layers out of the multi-problem table.
 bool homconv_deep_fits(const HcLayer &P);

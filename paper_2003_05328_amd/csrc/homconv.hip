@@ -253,10 +253,13 @@ __device__ __forceinline__ uint64_t recombine(int a0, int a1, int a2, int a3, in
 // MULTI: the launch walks the concatenated tiles of several HomConv
 // problems (layers of uneven shapes) read from a device table; otherwise the
 // one problem comes in the kernel arguments.
+// SEEDED: the input ciphertexts are seeded (ensei_homconv_seeded): words
+// j < n are generated from the public stream where they would be loaded,
+// and only the b words (column n) are read, from b_in.
 // Tile schedule: with chunk == 0 each workgroup takes one contiguous range of
 // tiles; otherwise tiles are dealt out in chunks of `chunk` consecutive tiles,
 // chunk c to workgroup c mod gridDim.x.
-template <bool PAIRED, bool WIDE_STORE, bool MULTI>
+template <bool PAIRED, bool WIDE_STORE, bool MULTI, bool SEEDED>
 __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, const HcLayer *__restrict__ table,
                                                                   int nlayers, int64_t total_tiles, int64_t chunk,
                                                                   uint64_t delta) {
@@ -321,17 +324,31 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
         const int Cin = P.Cin, Cout = P.Cout;
         const int64_t F = P.F, rowlen = (int64_t)P.n + 1;
         const int col = u.jt * 64 + ld_col;
-        const uint8_t *blk =
-            uniform_ptr(reinterpret_cast<const uint8_t *>(P.ct_in + (u.b * F + u.f) * rowlen * Cin));
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc(blk, (uint32_t)(rowlen * Cin * 8));
         // columns past n read zero; an 8-channel group that starts past Cin
         // is not read at all (no traffic), one that straddles it reads the next
         // column's words, which meet zero weights
         const bool any = ld_sc * 16 + ld_h * 8 < Cin - u.ks * 64;
-        const uint32_t off =
-            any ? (uint32_t)(((int64_t)col * Cin + u.ks * 64 + ld_sc * 16 + ld_h * 8) * 8) : 0x80000000u;
+        if (SEEDED) {
+            // column n: the b words of the 8 channels from b_in [B][F][Cin]
+            // (outside the column tile holding it nothing is read); the words
+            // of columns below n are generated when the unit is converted
+            const int c0 = u.ks * 64 + ld_sc * 16 + ld_h * 8;
+            const uint8_t *bblk = uniform_ptr(reinterpret_cast<const uint8_t *>(P.b_in + (u.b * F + u.f) * Cin));
+            const __amdgpu_buffer_rsrc_t rb = make_rsrc(bblk, u.jt == P.n_jt - 1 ? (uint32_t)(Cin * 8) : 0u);
+            const uint32_t boff = any && col == P.n ? (uint32_t)(c0 * 8) : 0x80000000u;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) buf.w[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16 * q), 0, 0);
+            for (int q = 0; q < 4; ++q)
+                buf.w[q] = __builtin_amdgcn_raw_buffer_load_b128(rb, (int)(boff + 16 * q), 0, 0);
+        } else {
+            const uint8_t *blk =
+                uniform_ptr(reinterpret_cast<const uint8_t *>(P.ct_in + (u.b * F + u.f) * rowlen * Cin));
+            const __amdgpu_buffer_rsrc_t rs = make_rsrc(blk, (uint32_t)(rowlen * Cin * 8));
+            const uint32_t off =
+                any ? (uint32_t)(((int64_t)col * Cin + u.ks * 64 + ld_sc * 16 + ld_h * 8) * 8) : 0x80000000u;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                buf.w[q] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16 * q), 0, 0);
+        }
         // the unit's weight fragments: n_items contiguous 16-byte items, item k
         // read by thread k % 512 (items past n_items read zero, with no traffic)
         // Consecutive units mostly share them (same problem, f, K step and row
@@ -478,14 +495,36 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
         const HcLayer P = layer(cur.L);
         const bool last_ks = cur.ks == P.n_ks - 1;
 
+        // seeded input: this thread's words j = col < n of its 8 channels,
+        // from the public stream (zero where the words were loaded)
+        uint64_t gen[8];
+        if (SEEDED) {
+            const int col = cur.jt * 64 + ld_col, c0 = cur.ks * 64 + ld_sc * 16 + ld_h * 8;
+            const bool on = c0 < P.Cin && col < P.n;
+            const uint64_t q0 = P.idx0 + (uint64_t)((cur.b * P.F + cur.f) * P.Cin + c0);
+            uint64_t z = P.seed_a + (q0 * (uint64_t)P.n + (uint64_t)col + 1) * kGamma;
+            const uint64_t step = (uint64_t)P.n * kGamma;  // next channel, same word
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint64_t a = splitmix_mix(z);
+                gen[i] = on ? a : 0ull;
+                z += step;
+            }
+        }
         // digit planes of this unit's 8 words: 8 bytes of each plane
         uint32_t pl[8][2];
         {
             uint32_t lo[8], hi[8];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const uint64_t v0 = ((uint64_t)buf.w[q].y << 32 | buf.w[q].x) + 0x8080808080808080ull;
-                const uint64_t v1 = ((uint64_t)buf.w[q].w << 32 | buf.w[q].z) + 0x8080808080808080ull;
+                uint64_t v0 = (uint64_t)buf.w[q].y << 32 | buf.w[q].x;
+                uint64_t v1 = (uint64_t)buf.w[q].w << 32 | buf.w[q].z;
+                if (SEEDED) {  // a thread's words are either loaded or generated; the other part is zero
+                    v0 += gen[2 * q];
+                    v1 += gen[2 * q + 1];
+                }
+                v0 += 0x8080808080808080ull;
+                v1 += 0x8080808080808080ull;
                 lo[2 * q] = (uint32_t)v0;
                 hi[2 * q] = (uint32_t)(v0 >> 32);
                 lo[2 * q + 1] = (uint32_t)v1;
@@ -764,11 +803,13 @@ __global__ __launch_bounds__(kDeepThreads, 2) void homconv_deep_kernel(HcLayer P
 // and the depth sets how many units of stores stay in flight. Weight
 // fragments stay in registers while the unit's (f, ot) does not change;
 // masks are fetched one per lane and handed to the lanes holding the b word
-// by a cross-lane read. No LDS, no barrier.
+// by a cross-lane read. No LDS, no barrier. SEEDED: seeded input
+// (ensei_homconv_seeded): only the b words are loaded, from b_in; the other
+// words are generated from the public stream when the unit is converted.
 constexpr int kNarrowThreads = 256;
 constexpr int kNarrowDepth = 4;  // units in flight per wave
 
-template <int NCH, int DEPTH, bool WIDE_STORE>
+template <int NCH, int DEPTH, bool WIDE_STORE, bool SEEDED>
 __global__ __launch_bounds__(kNarrowThreads) void homconv_narrow_kernel(HcLayer P, uint64_t delta) {
     static_assert(NCH % 4 == 0 && NCH <= 16 && DEPTH >= 2, "one 16-channel group");
     constexpr int kWaves = kNarrowThreads / 64;
@@ -817,15 +858,19 @@ __global__ __launch_bounds__(kNarrowThreads) void homconv_narrow_kernel(HcLayer 
         uint32_t r;
     };
     auto issue = [&](const Coord &c, Buf &buf) {
-        const uint8_t *blk =
-            uniform_ptr(reinterpret_cast<const uint8_t *>(P.ct_in + (c.b * F + c.f) * rowlen * Cin));
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc(blk, (uint32_t)(rowlen * Cin * 8));
         const uint32_t col = (uint32_t)(c.jb * 16 + l16);
+        // seeded: the block of b words, read only by the column block holding column n
+        const uint8_t *blk = uniform_ptr(
+            SEEDED ? reinterpret_cast<const uint8_t *>(P.b_in + (c.b * F + c.f) * Cin)
+                   : reinterpret_cast<const uint8_t *>(P.ct_in + (c.b * F + c.f) * rowlen * Cin));
+        const __amdgpu_buffer_rsrc_t rs =
+            make_rsrc(blk, SEEDED ? (c.jb == n_jb - 1 ? (uint32_t)(Cin * 8) : 0u) : (uint32_t)(rowlen * Cin * 8));
         // lane group 3 pairs the zero weight limb: it needs no words; columns
         // past n read zero
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch) {
-            const uint32_t off = ch < Cin && g < 3 ? (col * (uint32_t)Cin + ch) * 8 : 0x80000000u;
+            const bool want = ch < Cin && g < 3 && (!SEEDED || col == (uint32_t)P.n);
+            const uint32_t off = want ? (SEEDED ? (uint32_t)ch * 8 : (col * (uint32_t)Cin + ch) * 8) : 0x80000000u;
             const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(rs, (int)off, 0, 0);
             buf.v[ch] = (uint64_t)t.y << 32 | t.x;
         }
@@ -879,6 +924,20 @@ __global__ __launch_bounds__(kNarrowThreads) void homconv_narrow_kernel(HcLayer 
             a_key = key;
         }
         const uint32_t rv = buf.r;
+        if (SEEDED) {
+            // words j = col < n of the lane's channels from the public stream
+            // (lane group 3 meets the zero limb and needs none)
+            const int col = cur.jb * 16 + l16;
+            const uint64_t q0 = P.idx0 + (uint64_t)((cur.b * F + cur.f) * Cin);
+            uint64_t z = P.seed_a + (q0 * (uint64_t)P.n + (uint64_t)col + 1) * kGamma;
+            const uint64_t step = (uint64_t)P.n * kGamma;  // next channel, same word
+#pragma unroll
+            for (int ch = 0; ch < NCH; ++ch) {
+                const uint64_t a = splitmix_mix(z);
+                if (ch < Cin && g < 3 && col < P.n) buf.v[ch] += a;
+                z += step;
+            }
+        }
         // digit operand of shift s: dword q holds digit s - g of channels 4q..4q+3
         uint32_t pl[NCH / 4][8];
 #pragma unroll
@@ -1061,15 +1120,16 @@ int homconv_sizes(int64_t batch, int Cin, int Cout, int64_t F, int n) {
     return ENSEI_OK;
 }
 
+// seeded: ct_in holds only the b words, [B][F][Cin]
 static int check_homconv(const ensei_ctx *ctx, const void *ct_in, const void *w, const void *r, int64_t batch,
-                         int Cin, int Cout, int64_t F, int n, const void *ct_out, size_t wbytes) {
+                         int Cin, int Cout, int64_t F, int n, const void *ct_out, size_t wbytes, bool seeded = false) {
     int st = check_ctx(ctx);
     if (st) return st;
     if (!ct_in || !w || !r || !ct_out) return ENSEI_ERR_ARG;
     st = homconv_sizes(batch, Cin, Cout, F, n);
     if (st) return st;
     if (((uintptr_t)ct_in & 7) || ((uintptr_t)ct_out & 7) || ((uintptr_t)r & 3)) return ENSEI_ERR_ALIGN;
-    const size_t inb = (size_t)batch * Cin * F * (n + 1) * 8, outb = (size_t)batch * Cout * F * (n + 1) * 8;
+    const size_t inb = (size_t)batch * Cin * F * (seeded ? 1 : n + 1) * 8, outb = (size_t)batch * Cout * F * (n + 1) * 8;
     if (overlaps(ct_out, outb, ct_in, inb) || overlaps(ct_out, outb, w, wbytes) ||
         overlaps(ct_out, outb, r, (size_t)batch * Cout * F * 4))
         return ENSEI_ERR_OVERLAP;
@@ -1101,11 +1161,13 @@ int pack_weights_as(const ensei_ctx *ctx, const uint32_t *w_hat, int Cout, int C
 }
 
 int homconv_problem(const ensei_ctx *ctx, HcLayer *P, const uint64_t *ct_in, const int8_t *w_pack, const uint32_t *r,
-                    int64_t B, int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, size_t wbytes) {
-    int st = check_homconv(ctx, ct_in, w_pack, r, B, Cin, Cout, F, n, ct_out, wbytes);
+                    int64_t B, int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, size_t wbytes, bool seeded) {
+    int st = check_homconv(ctx, ct_in, w_pack, r, B, Cin, Cout, F, n, ct_out, wbytes, seeded);
     if (st) return st;
     if ((uintptr_t)w_pack & 15) return ENSEI_ERR_ALIGN;
-    P->ct_in = ct_in;
+    P->ct_in = seeded ? nullptr : ct_in;
+    P->b_in = seeded ? ct_in : nullptr;
+    P->seed_a = P->idx0 = 0;
     P->w_pack = w_pack;
     P->r = r;
     P->ct_out = ct_out;
@@ -1126,10 +1188,11 @@ int homconv_problem(const ensei_ctx *ctx, HcLayer *P, const uint64_t *ct_in, con
 
 // Narrow kernel launch: enough 4-wave workgroups to fill every CU at the
 // kernel's occupancy (each wave walks its own contiguous range of units).
-template <int NCH>
+template <int NCH, bool SEEDED>
 static int launch_narrow(const ensei_ctx *ctx, const HcLayer &P, HcSchedule sched, hipStream_t stream) {
     const bool wide = P.Cout % 2 == 0;
-    auto kernel = wide ? homconv_narrow_kernel<NCH, kNarrowDepth, true> : homconv_narrow_kernel<NCH, kNarrowDepth, false>;
+    auto kernel = wide ? homconv_narrow_kernel<NCH, kNarrowDepth, true, SEEDED>
+                       : homconv_narrow_kernel<NCH, kNarrowDepth, false, SEEDED>;
     static int resident[2] = {0, 0};  // workgroups per CU, by store width
     int per_cu = resident[wide];
     if (per_cu == 0) {
@@ -1186,8 +1249,8 @@ int homconv_launch(const ensei_ctx *ctx, const HcLayer *problems, const HcLayer 
     }
     if (nlayers == 1 && !paired && problems[0].Cin <= kNarrowCin) {
         const int Cin = problems[0].Cin;
-        return Cin <= 4 ? launch_narrow<4>(ctx, problems[0], sched, stream)
-                        : launch_narrow<8>(ctx, problems[0], sched, stream);
+        return Cin <= 4 ? launch_narrow<4, false>(ctx, problems[0], sched, stream)
+                        : launch_narrow<8, false>(ctx, problems[0], sched, stream);
     }
     int64_t total = 0;
     bool wide = true;
@@ -1200,14 +1263,17 @@ int homconv_launch(const ensei_ctx *ctx, const HcLayer *problems, const HcLayer 
     if (blocks > ctx->num_cus) blocks = ctx->num_cus;
     if (sched.chunk == 0 && total < blocks) blocks = total;
     if (nlayers > 1) {
-        auto kernel = wide ? homconv_mfma_kernel<true, true, true> : homconv_mfma_kernel<true, false, true>;
+        auto kernel =
+            wide ? homconv_mfma_kernel<true, true, true, false> : homconv_mfma_kernel<true, false, true, false>;
         hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kHcThreads), 0, stream, problems[0], dev_table, nlayers,
                            total, sched.chunk, ctx->delta);
     } else {
         // one limb pair per MFMA once the 64-channel K steps are full enough;
         // limbs folded into K for narrow inputs
-        auto kernel = paired ? (wide ? homconv_mfma_kernel<true, true, false> : homconv_mfma_kernel<true, false, false>)
-                             : (wide ? homconv_mfma_kernel<false, true, false> : homconv_mfma_kernel<false, false, false>);
+        auto kernel =
+            paired ? (wide ? homconv_mfma_kernel<true, true, false, false> : homconv_mfma_kernel<true, false, false, false>)
+                   : (wide ? homconv_mfma_kernel<false, true, false, false>
+                           : homconv_mfma_kernel<false, false, false, false>);
         hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kHcThreads), 0, stream, problems[0], dev_table, 1,
                            total, sched.chunk, ctx->delta);
     }
@@ -1234,6 +1300,29 @@ int ensei_homconv(ensei_ctx *ctx, const uint64_t *ct_in, const int8_t *w_pack, c
                              ensei_wpack_bytes(Cout, Cin, F));
     if (st) return st;
     return homconv_launch(ctx, &P, nullptr, 1, Cin >= kPairedCin, HcSchedule{0, 0}, (hipStream_t)stream);
+}
+
+int ensei_homconv_seeded(ensei_ctx *ctx, const uint64_t *b_in, uint64_t seed_a, uint64_t ct_index0,
+                         const int8_t *w_pack, const uint32_t *r, int64_t batch, int Cin, int Cout, int64_t F, int n,
+                         uint64_t *ct_out, void *stream) {
+    HcLayer P;
+    int st = homconv_problem(ctx, &P, b_in, w_pack, r, batch, Cin, Cout, F, n, ct_out,
+                             ensei_wpack_bytes(Cout, Cin, F), true);
+    if (st) return st;
+    P.seed_a = seed_a;
+    P.idx0 = ct_index0;
+    if (Cin <= kNarrowCin)
+        return Cin <= 4 ? launch_narrow<4, true>(ctx, P, HcSchedule{0, 0}, (hipStream_t)stream)
+                        : launch_narrow<8, true>(ctx, P, HcSchedule{0, 0}, (hipStream_t)stream);
+    // otherwise the streaming kernel: one 8-wave workgroup per CU
+    const bool paired = Cin >= kPairedCin, wide = Cout % 2 == 0;
+    const int64_t blocks = P.n_tiles < ctx->num_cus ? P.n_tiles : ctx->num_cus;
+    auto kernel =
+        paired ? (wide ? homconv_mfma_kernel<true, true, false, true> : homconv_mfma_kernel<true, false, false, true>)
+               : (wide ? homconv_mfma_kernel<false, true, false, true> : homconv_mfma_kernel<false, false, false, true>);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kHcThreads), 0, (hipStream_t)stream, P, nullptr, 1,
+                       P.n_tiles, (int64_t)0, ctx->delta);
+    return launch_status();
 }
 
 int ensei_homconv_valu(ensei_ctx *ctx, const uint64_t *ct_in, const uint32_t *w_hat, const uint32_t *r,

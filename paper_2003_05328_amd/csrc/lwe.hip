@@ -17,16 +17,6 @@
 
 namespace ensei {
 
-constexpr uint64_t kGamma = 0x9e3779b97f4a7c15ull;
-
-// SplitMix64 finaliser (Steele, Lea and Flood, OOPSLA 2014): output number k
-// of the generator seeded with x is mix(x + k * gamma).
-__device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    return z ^ (z >> 31);
-}
-
 // Group geometry shared by Enc and Dec.
 struct LweGroups {
     int lanes_per_f;  // min(C, 64)
@@ -79,6 +69,9 @@ __device__ __forceinline__ uint64_t key_mask(uint32_t k4, int k, int sign) {
     return sj == sign ? ~0ull : 0ull;
 }
 
+// STORE_A = false (seeded ciphertexts): the a-words are only summed into
+// <a, s>, not stored, and the b words go to ct as [B][F][C].
+template <bool STORE_A>
 __global__ __launch_bounds__(256) void encrypt_kernel(const uint32_t *__restrict__ m, const int8_t *__restrict__ s,
                                                       const int32_t *__restrict__ e, int C, int64_t F, int n,
                                                       uint64_t seed_a, uint64_t ct_index0, uint64_t delta,
@@ -108,7 +101,7 @@ __global__ __launch_bounds__(256) void encrypt_kernel(const uint32_t *__restrict
             for (int k = 0; k < 4; ++k) {
                 const uint64_t a = splitmix_mix(z);
                 z += kGamma;
-                w[(int64_t)(j + k) * C] = a;
+                if (STORE_A) w[(int64_t)(j + k) * C] = a;
                 acc_p += a & key_mask(k4, k, 1);
                 acc_n += a & key_mask(k4, k, -1);
             }
@@ -116,7 +109,7 @@ __global__ __launch_bounds__(256) void encrypt_kernel(const uint32_t *__restrict
         for (; j < j1; ++j) {
             const uint64_t a = splitmix_mix(z);
             z += kGamma;
-            w[(int64_t)j * C] = a;
+            if (STORE_A) w[(int64_t)j * C] = a;
             const uint32_t k1 = __builtin_amdgcn_readfirstlane((uint32_t)(uint8_t)key[j]);
             acc_p += a & key_mask(k1, 0, 1);
             acc_n += a & key_mask(k1, 0, -1);
@@ -127,7 +120,11 @@ __global__ __launch_bounds__(256) void encrypt_kernel(const uint32_t *__restrict
     if (wave == 0 && L.ok) {
         const uint64_t dot = part[lane] + part[64 + lane] + part[128 + lane] + part[192 + lane];
         const int64_t mi = (L.b * C + L.c) * F + L.f;
-        w[(int64_t)n * C] = dot + (uint64_t)(int64_t)e[mi] + delta * (uint64_t)m[mi];
+        const uint64_t bword = dot + (uint64_t)(int64_t)e[mi] + delta * (uint64_t)m[mi];
+        if (STORE_A)
+            w[(int64_t)n * C] = bword;
+        else
+            ct[(L.b * F + L.f) * C + L.c] = bword;
     }
 }
 
@@ -219,8 +216,25 @@ int ensei_encrypt(ensei_ctx *ctx, const uint32_t *m, const int8_t *s, const int3
     if (overlaps(ct, ctb, m, num * 4) || overlaps(ct, ctb, e, num * 4) || overlaps(ct, ctb, s, (size_t)n))
         return ENSEI_ERR_OVERLAP;
     const size_t smem = ((n + 7) & ~7) + kWaves * 64 * 8;
-    hipLaunchKernelGGL(encrypt_kernel, dim3((unsigned)groups), dim3(256), smem, (hipStream_t)stream, m, s, e, C, F, n,
-                       seed_a, ct_index0, ctx->delta, ct, lwe_groups(C, F));
+    hipLaunchKernelGGL(encrypt_kernel<true>, dim3((unsigned)groups), dim3(256), smem, (hipStream_t)stream, m, s, e, C,
+                       F, n, seed_a, ct_index0, ctx->delta, ct, lwe_groups(C, F));
+    return launch_status();
+}
+
+int ensei_encrypt_seeded(ensei_ctx *ctx, const uint32_t *m, const int8_t *s, const int32_t *e, int64_t batch, int C,
+                         int64_t F, int n, uint64_t seed_a, uint64_t ct_index0, uint64_t *b_out, void *stream) {
+    int64_t groups;
+    int st = check_lwe(ctx, batch, C, F, n, &groups);
+    if (st) return st;
+    if (!m || !s || !e || !b_out) return ENSEI_ERR_ARG;
+    if (((uintptr_t)m & 3) || ((uintptr_t)e & 3) || ((uintptr_t)b_out & 7)) return ENSEI_ERR_ALIGN;
+    const size_t num = (size_t)batch * C * F;
+    if (overlaps(b_out, num * 8, m, num * 4) || overlaps(b_out, num * 8, e, num * 4) ||
+        overlaps(b_out, num * 8, s, (size_t)n))
+        return ENSEI_ERR_OVERLAP;
+    const size_t smem = ((n + 7) & ~7) + kWaves * 64 * 8;
+    hipLaunchKernelGGL(encrypt_kernel<false>, dim3((unsigned)groups), dim3(256), smem, (hipStream_t)stream, m, s, e, C,
+                       F, n, seed_a, ct_index0, ctx->delta, b_out, lwe_groups(C, F));
     return launch_status();
 }
 

@@ -50,6 +50,8 @@ SIGNATURES = {
     "ensei_pack_weights": (_i32, [_vp, _vp, _i32, _i32, _i64, _vp, _vp]),
     "ensei_encrypt": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i64, _i32, _u64, _u64, _vp, _vp]),
     "ensei_homconv": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
+    "ensei_encrypt_seeded": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i64, _i32, _u64, _u64, _vp, _vp]),
+    "ensei_homconv_seeded": (_i32, [_vp, _vp, _u64, _u64, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
     "ensei_homconv_valu": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
     "ensei_decrypt": (_i32, [_vp, _vp, _vp, _i64, _i32, _i64, _i32, _vp, _vp]),
     "ensei_homrec": (_i32, [_vp, _vp, _vp, _i64, _i32, _i64, _i32, _vp]),
@@ -276,6 +278,21 @@ class Context:
         self._call("ensei_encrypt", _ptr(m), _ptr(s), _ptr(e), B, C, F, n, seed_a % 2**64, ct_index0 % 2**64, _ptr(out))
         return out
 
+    def encrypt_seeded(self, m, s, e, seed_a: int, ct_index0: int = 0, out=None) -> torch.Tensor:
+        """Seeded ciphertexts: m uint32 [B][C][F], s, e as encrypt -> only the
+        b words, uint64 [B][F][C] (ensei_encrypt_seeded); the a-words follow
+        from (seed_a, ct_index0)."""
+        self._dev(m, "m", torch.uint32)
+        self._dev(s, "s", torch.int8)
+        self._dev(e, "e", torch.int32)
+        if m.dim() != 3 or e.numel() != m.numel():
+            raise ValueError("m must be [B][C][F] with one error per plaintext")
+        B, C, F = tuple(m.shape)
+        out = self._out(out, (B, F, C), torch.uint64)
+        self._call("ensei_encrypt_seeded", _ptr(m), _ptr(s), _ptr(e), B, C, F, s.numel(), seed_a % 2**64,
+                   ct_index0 % 2**64, _ptr(out))
+        return out
+
     def decrypt(self, ct, s, out=None) -> torch.Tensor:
         """Word-major ct uint64 [B][F][n+1][C] (or rows [N][n+1]), s int8 [n] ->
         m uint32 [B][C][F] (or [N]) (ensei_decrypt)."""
@@ -334,6 +351,24 @@ class Context:
             raise ValueError("w_pack is smaller than ensei_wpack_bytes(Cout, Cin, F)")
         out = self._out(out, (B, F, n + 1, Cout), torch.uint64)
         self._call("ensei_homconv", _ptr(ct_in), _ptr(w_pack), _ptr(r), B, Cin, Cout, F, n, _ptr(out))
+        return out
+
+    def homconv_seeded(self, b_in, n: int, seed_a: int, w_pack, r, Cout: int, ct_index0: int = 0,
+                       out=None) -> torch.Tensor:
+        """Seeded input: b words uint64 [B][F][Cin] and (seed_a, ct_index0) for
+        the a-words of LWE dimension n -> ct_out [B][F][n+1][Cout], the same
+        bits as homconv on the full ciphertexts (ensei_homconv_seeded)."""
+        self._dev(b_in, "b_in", torch.uint64)
+        self._dev(w_pack, "w_pack", torch.int8)
+        self._dev(r, "r", torch.uint32)
+        B, F, Cin = tuple(b_in.shape)
+        if tuple(r.shape) != (B, Cout, F):
+            raise ValueError(f"r must be [B][Cout][F] = {(B, Cout, F)}")
+        if w_pack.numel() < int(lib().ensei_wpack_bytes(Cout, Cin, F)):
+            raise ValueError("w_pack is smaller than ensei_wpack_bytes(Cout, Cin, F)")
+        out = self._out(out, (B, F, n + 1, Cout), torch.uint64)
+        self._call("ensei_homconv_seeded", _ptr(b_in), seed_a % 2**64, ct_index0 % 2**64, _ptr(w_pack), _ptr(r), B,
+                   Cin, Cout, F, n, _ptr(out))
         return out
 
     def homconv_valu(self, ct_in, w_hat, r, out=None) -> torch.Tensor:
