@@ -1024,46 +1024,89 @@ __global__ __launch_bounds__(kNarrowThreads) void homconv_narrow_kernel(HcLayer 
 // of W^ (bytes of W^ + 0x808080, each xor 0x80).
 __device__ __forceinline__ int frag_row(int rbg, int m) { return 32 * (rbg >> 1) + 8 * (m >> 2) + 4 * (rbg & 1) + (m & 3); }
 
-// One thread per (f, unit, 16 channels of one row): it reads those 16 values of
-// W^ once and writes every item built from them (3 limbs, or 4 limb slots).
-__global__ void pack_weights_kernel(const uint32_t *__restrict__ w_hat, int Cout, int Cin, int64_t F, int n_ks,
-                                    int n_ot, int n_items, int paired, int8_t *__restrict__ w_pack) {
-    const int per_unit = paired ? 256 : n_items / 4;  // threads per unit
-    const int64_t total = F * n_ks * n_ot * per_unit;
-    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (int64_t)gridDim.x * blockDim.x) {
-        // f fastest: neighbouring threads read neighbouring W^ words
-        const int64_t f = idx % F;
-        int64_t rest = idx / F;
-        const int j = (int)(rest % per_unit);
-        rest /= per_unit;
-        const int ot = (int)(rest % n_ot), ks = (int)(rest / n_ot);
-        // paired: j = (row block, lane), 3 limbs at k = limb * 256 + j;
-        // folded: j = (group, row block, m), 4 slots at k = group * 256 + rbg * 64 + slot * 16 + m
-        const int rbg = paired ? (j >> 6) : ((j >> 4) & 3);
-        const int m = paired ? (j & 15) : (j & 15);
-        const int group = paired ? ks * 4 + ((j & 63) >> 4) : (j >> 6);
-        const int row = ot * 64 + frag_row(rbg, m);
-        uint32_t dig[4][4] = {};
+// One block per (K step ks, row tile ot) and kPackF consecutive frequencies
+// (a "tile" here). The block first reads the tile's 64 x 64 slice of W^ into
+// LDS, 16 contiguous bytes (kPackF frequencies) per (row, channel) where W^
+// allows it. Then each thread builds the items of one (frequency, 16 channels
+// of one row) from LDS: consecutive lanes write consecutive 16-byte items,
+// 1 KB per wave store. Reading W^ straight by frequency instead scatters the
+// stores (the units of neighbouring frequencies are n_items * 16 bytes apart),
+// and every store then writes a piece of a different line. Workgroups are
+// renumbered so that each XCD takes a contiguous range of tiles: the tiles
+// that share a 128-byte line of W^ read it through one L2.
+constexpr int kPackF = 4, kPackThreads = 256;
+
+__global__ __launch_bounds__(kPackThreads) void pack_weights_kernel(const uint32_t *__restrict__ w_hat, int Cout,
+                                                                    int Cin, int64_t F, int n_ks, int n_ot,
+                                                                    int n_items, int paired, int vec,
+                                                                    int8_t *__restrict__ w_pack) {
+    __shared__ uint32_t tile[kPackF][64][65];  // [frequency][row][channel], rows padded against bank conflicts
+    const int t = threadIdx.x;
+    const int per_unit = paired ? 256 : n_items / 4;  // items' producers per unit
+    const int64_t f_tiles = (F + kPackF - 1) / kPackF, total = f_tiles * n_ks * n_ot, G = gridDim.x;
+    const int64_t wg = G % kXcds == 0 ? (int64_t)(blockIdx.x % kXcds) * (G / kXcds) + blockIdx.x / kXcds
+                                      : (int64_t)blockIdx.x;
+    const int64_t per = total / G, extra = total % G;
+    const int64_t lo = wg * per + (wg < extra ? wg : extra), hi = lo + per + (wg < extra ? 1 : 0);
+    for (int64_t T = lo; T < hi; ++T) {
+        const int64_t ft = T % f_tiles, u = T / f_tiles;
+        const int ot = (int)(u % n_ot), ks = (int)(u / n_ot);
+        const int64_t f0 = ft * kPackF;
+        const int nf = F - f0 < kPackF ? (int)(F - f0) : kPackF;
+        // the slice (rows past Cout and channels past Cin are zero): every
+        // thread's loads are issued before any of them is written to LDS
+        constexpr int kLoads = 64 * 64 / kPackThreads;
+        uint32_t v[kLoads][kPackF];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) {
-            const int i = group * 16 + c;
-            uint32_t w = 0;
-            if (row < Cout && i < Cin) w = w_hat[((int64_t)row * Cin + i) * F + f];
-            const uint32_t u = (w + 0x808080u) ^ 0x808080u;  // balanced digits as bytes (byte 3 is 0)
+        for (int i = 0; i < kLoads; ++i) {
+            const int q = t + i * kPackThreads, r = q >> 6, c = q & 63, row = ot * 64 + r, ch = ks * 64 + c;
+            const uint32_t *src = w_hat + ((int64_t)row * Cin + ch) * F + f0;
+            const bool in = row < Cout && ch < Cin;
+            if (vec && nf == kPackF) {
+                const uint4 x = in ? *reinterpret_cast<const uint4 *>(src) : make_uint4(0, 0, 0, 0);
+                v[i][0] = x.x;
+                v[i][1] = x.y;
+                v[i][2] = x.z;
+                v[i][3] = x.w;
+            } else {
 #pragma unroll
-            for (int l = 0; l < 4; ++l) dig[l][c >> 2] |= ((u >> (8 * l)) & 0xffu) << (8 * (c & 3));
+                for (int k = 0; k < kPackF; ++k) v[i][k] = in && k < nf ? src[k] : 0u;
+            }
         }
-        const int64_t unit = ((int64_t)f * n_ks + ks) * n_ot + ot;
-        uint4 *dst = reinterpret_cast<uint4 *>(w_pack) + unit * n_items;
-        if (paired) {
 #pragma unroll
-            for (int l = 0; l < 3; ++l) dst[l * 256 + j] = make_uint4(dig[l][0], dig[l][1], dig[l][2], dig[l][3]);
-        } else {
-            const int k0 = (j >> 6) * 256 + rbg * 64 + m;
+        for (int i = 0; i < kLoads; ++i) {
+            const int q = t + i * kPackThreads;
 #pragma unroll
-            for (int l = 0; l < 4; ++l) dst[k0 + l * 16] = make_uint4(dig[l][0], dig[l][1], dig[l][2], dig[l][3]);
+            for (int k = 0; k < kPackF; ++k) tile[k][q >> 6][q & 63] = v[i][k];
         }
+        __syncthreads();
+        for (int q = t; q < nf * per_unit; q += kPackThreads) {
+            const int fl = q / per_unit, j = q % per_unit;
+            // paired: j = (row block, lane), 3 limbs at k = limb * 256 + j;
+            // folded: j = (group, row block, m), 4 slots at k = group * 256 + rbg * 64 + slot * 16 + m
+            const int rbg = paired ? (j >> 6) : ((j >> 4) & 3);
+            const int m = j & 15;
+            const int lg = paired ? ((j & 63) >> 4) : (j >> 6);  // 16-channel group within the K step
+            const int lr = frag_row(rbg, m);
+            uint32_t dig[4][4] = {};
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const uint32_t uu = (tile[fl][lr][lg * 16 + c] + 0x808080u) ^ 0x808080u;  // balanced digits (byte 3 is 0)
+#pragma unroll
+                for (int l = 0; l < 4; ++l) dig[l][c >> 2] |= ((uu >> (8 * l)) & 0xffu) << (8 * (c & 3));
+            }
+            const int64_t unit = ((f0 + fl) * n_ks + ks) * n_ot + ot;
+            uint4 *dst = reinterpret_cast<uint4 *>(w_pack) + unit * n_items;
+            if (paired) {
+#pragma unroll
+                for (int l = 0; l < 3; ++l) dst[l * 256 + j] = make_uint4(dig[l][0], dig[l][1], dig[l][2], dig[l][3]);
+            } else {
+                const int k0 = (j >> 6) * 256 + rbg * 64 + m;
+#pragma unroll
+                for (int l = 0; l < 4; ++l) dst[k0 + l * 16] = make_uint4(dig[l][0], dig[l][1], dig[l][2], dig[l][3]);
+            }
+        }
+        __syncthreads();  // the slice is rewritten for the next tile
     }
 }
 
@@ -1152,11 +1195,13 @@ int pack_weights_as(const ensei_ctx *ctx, const uint32_t *w_hat, int Cout, int C
     if (overlaps(w_pack, wpack_bytes_as(Cout, Cin, F, paired), w_hat, (size_t)Cout * Cin * F * 4))
         return ENSEI_ERR_OVERLAP;
     const int n_ks = (Cin + 63) / 64, n_ot = (Cout + 63) / 64, n_items = frag_items(Cin, paired);
-    const int64_t total = F * n_ks * n_ot * (paired ? 256 : n_items / 4);
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(pack_weights_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, w_hat, Cout, Cin, F, n_ks,
-                       n_ot, n_items, (int)paired, w_pack);
+    const int64_t tiles = (F + kPackF - 1) / kPackF * n_ks * n_ot;
+    // two resident workgroups per CU; a multiple of the XCD count when there are enough tiles
+    int64_t blocks = 2 * (int64_t)ctx->num_cus;
+    if (tiles < blocks) blocks = tiles >= kXcds ? tiles / kXcds * kXcds : tiles;
+    const int vec = ((uintptr_t)w_hat & 15) == 0 && F % kPackF == 0;
+    hipLaunchKernelGGL(pack_weights_kernel, dim3((unsigned)blocks), dim3(kPackThreads), 0, stream, w_hat, Cout, Cin, F,
+                       n_ks, n_ot, n_items, (int)paired, vec, w_pack);
     return launch_status();
 }
 

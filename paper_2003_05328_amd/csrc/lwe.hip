@@ -156,11 +156,13 @@ __global__ __launch_bounds__(64 * kDecWaves) void decrypt_kernel(const uint64_t 
     uint64_t acc_p = 0, acc_n = 0;
     if (L.ok) {
         int j = j0;
-        // 16 words per lane in flight at once
+        // 16 words per lane in flight at once; the ciphertexts are read once,
+        // so the loads are non-temporal (in a step, Dec follows HomConv's
+        // write stream: temporal loads cost it a fifth of its time)
         for (; j + 16 <= j1; j += 16) {
             uint64_t x[16];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) x[k] = w[(int64_t)(j + k) * C];
+            for (int k = 0; k < 16; ++k) x[k] = __builtin_nontemporal_load(&w[(int64_t)(j + k) * C]);
 #pragma unroll
             for (int k4i = 0; k4i < 4; ++k4i) {
                 const uint32_t k4 = key4(key, j + 4 * k4i);
