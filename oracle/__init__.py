@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+from decimal import ROUND_FLOOR, Decimal, localcontext
 
 import numpy as np
 
@@ -36,6 +37,7 @@ _SIG = {
     "or_phase": (u64, [i32, vp, i64, vp]),
     "or_decrypt": (None, [u64, i64, i32, i64, i32, vp, vp, vp]),
     "or_expand_seeded": (None, [i64, i32, i64, i32, u64, u64, vp, vp]),
+    "or_sample_errors": (None, [vp, i32, u64, u64, i64, i32, i64, vp]),
     "or_homconv": (None, [u64, i32, i32, i32, i64, i32, vp, vp, vp, vp]),
     "or_homconv_select": (None, [u64, i32, i32, i32, i64, i32, vp, vp, vp, i64, vp, vp]),
     "or_server_share": (None, [u64, i64, i32, i32, vp, vp]),
@@ -180,6 +182,15 @@ class Oracle:
         """HomConv of the seeded ciphertexts given by (seed_a, ct_index0, bw)."""
         return self.homconv(self.expand_seeded(bw, n, seed_a, ct_index0), w_hat, r, p)
 
+    def sample_errors(self, seed_e: int, B: int, C: int, F: int, ct_index0: int = 0) -> np.ndarray:
+        """Errors e[B][C][F] of the rounded Gaussian (sigma 3.2) drawn from the
+        public generator seeded with seed_e (or_sample_errors, thresholds from
+        cdt_table)."""
+        T = np.array(cdt_table(), dtype=np.uint64)
+        e = np.empty((B, C, F), dtype=np.int32)
+        self.lib.or_sample_errors(_p(T), T.size, seed_e % 2**64, ct_index0 % 2**64, B, C, F, _p(e))
+        return e
+
     def homconv(self, ct_in, w_hat, r, p: int) -> np.ndarray:
         """ct_in[B][F][n+1][Cin], w_hat[Cout][Cin][F], r[B][Cout][F] -> ct_out[B][F][n+1][Cout]."""
         ct_in = _c(ct_in, np.uint64)
@@ -268,6 +279,55 @@ class Oracle:
 
 
 _default: Oracle | None = None
+
+
+CDT_BITS = 48  # grid of the error sampler's thresholds
+CDT_SIZE = 32  # thresholds: |e| <= 32
+SIGMA_NUM, SIGMA_DEN = 16, 5  # sigma = 3.2
+
+
+def _pi(prec_digits: int) -> Decimal:
+    """pi = 16 arctan(1/5) - 4 arctan(1/239) (Machin), each arctan by its
+    alternating series, in decimal arithmetic of the current precision."""
+    def arctan_inv(m: int) -> Decimal:
+        total, term, k, sign = Decimal(0), Decimal(1) / m, 1, 1
+        m2 = m * m
+        while term > Decimal(10) ** (-prec_digits - 5):
+            total += sign * term / k
+            term /= m2
+            k += 2
+            sign = -sign
+        return total
+
+    return 16 * arctan_inv(5) - 4 * arctan_inv(239)
+
+
+def _erf(x: Decimal, prec_digits: int) -> Decimal:
+    """erf(x) = 2/sqrt(pi) exp(-x^2) sum_n 2^n x^(2n+1) / (2n+1)!! (all terms
+    positive), summed until the terms fall below the working precision."""
+    term, total, n = x, Decimal(0), 0
+    x2 = x * x
+    while term > Decimal(10) ** (-prec_digits - 5) * (total + 1):
+        total += term
+        n += 1
+        term = term * 2 * x2 / (2 * n + 1)
+    return 2 / _pi(prec_digits).sqrt() * (-x2).exp() * total
+
+
+def cdt_table() -> list:
+    """T[k] = floor(2^48 P(|e| <= k)) for e the rounded N(0, sigma^2), i.e.
+    floor(2^48 erf((k + 1/2) / (sigma sqrt 2))), k < 32, in 80-digit decimal
+    arithmetic (far below the 2^-48 grid)."""
+    prec = 80
+    with localcontext() as ctx:
+        ctx.prec = prec
+        sigma = Decimal(SIGMA_NUM) / SIGMA_DEN
+        out = []
+        for k in range(CDT_SIZE):
+            x = (Decimal(k) + Decimal(1) / 2) / (sigma * Decimal(2).sqrt())
+            v = (Decimal(2) ** CDT_BITS * _erf(x, prec)).to_integral_value(rounding=ROUND_FLOOR)
+            out.append(min(int(v), 2**CDT_BITS - 1))
+        return out
 
 
 def default() -> Oracle:

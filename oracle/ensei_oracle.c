@@ -294,6 +294,30 @@ void or_expand_seeded(int64_t B, int C, int64_t F, int n, uint64_t seed_a, uint6
             }
 }
 
+/* Rounded-Gaussian errors drawn from the public generator (the on-device
+ * sampler's definition; the LWE error distribution of Sec. 3.1 with the
+ * sigma = 3.2 of the design notes). T holds K cumulative thresholds of |e| on
+ * a 2^48 grid, T[k] = floor(2^48 P(|e| <= k)); the error of ciphertext
+ * q = (b F + f) C + c comes from output number ct_index0 + q + 1 of the
+ * generator seeded with seed_e: its top bit is the sign, bits 15..62 a
+ * uniform v < 2^48, and |e| is the number of thresholds <= v. e is stored
+ * like the plaintexts, e[(b C + c) F + f]. */
+void or_sample_errors(const uint64_t *T, int K, uint64_t seed_e, uint64_t ct_index0, int64_t B, int C, int64_t F,
+                      int32_t *e) {
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int64_t b = 0; b < B; ++b)
+        for (int64_t f = 0; f < F; ++f)
+            for (int c = 0; c < C; ++c) {
+                uint64_t q = (uint64_t)((b * F + f) * C + c);
+                uint64_t u = or_splitmix64(seed_e, ct_index0 + q + 1);
+                uint64_t v = (u >> 15) & ((1ULL << 48) - 1);
+                int mag = 0;
+                for (int k = 0; k < K; ++k)
+                    if (T[k] <= v) ++mag;
+                e[(b * C + c) * F + f] = (u >> 63) && mag ? -mag : mag;
+            }
+}
+
 /* --------------------------------------------------------- HomConv --- */
 
 /* One output ciphertext of HomConv for (image b, output channel o,

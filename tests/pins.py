@@ -14,6 +14,7 @@ import os
 
 import numpy as np
 
+import oracle
 from tests import bruteforce as bf
 from paper_2003_05328_amd import synth
 
@@ -444,6 +445,43 @@ def check_seeded(orc):
     assert np.array_equal(orc.decrypt(out, s, P).astype(np.int64), want)
 
 
+def check_noise_sampler(orc):
+    """The rounded-Gaussian error sampler (sigma 3.2): its thresholds against
+    the library erf, its draws against a stateful big-int generator and a
+    plain lookup, and the moments and zero mass of 200,000 draws against the
+    rounded Gaussian's (variance sigma^2 + 1/12 to first order)."""
+    import math
+
+    T = oracle.cdt_table()
+    sigma = oracle.SIGMA_NUM / oracle.SIGMA_DEN
+    assert len(T) == oracle.CDT_SIZE and T[-1] == 2**oracle.CDT_BITS - 1
+    for k, t in enumerate(T):
+        assert abs(t / 2**oracle.CDT_BITS - math.erf((k + 0.5) / (sigma * math.sqrt(2)))) < 1e-14, k
+        if k:
+            assert t >= T[k - 1]
+    # indexing: error (b, c, f) from generator output ct_index0 + (b F + f) C + c + 1
+    B, C, F, seed_e, c0 = 2, 3, 5, 0xC0FFEE1234, 9
+    e = orc.sample_errors(seed_e, B, C, F, ct_index0=c0)
+    stream = bf.splitmix64_stream(seed_e, c0 + B * C * F)
+    for b in range(B):
+        for c in range(C):
+            for f in range(F):
+                u = stream[c0 + (b * F + f) * C + c]
+                v = (u >> 15) % 2**48
+                mag = sum(1 for t in T if t <= v)
+                assert int(e[b, c, f]) == (-mag if u >> 63 and mag else mag), (b, c, f)
+    # distribution
+    N = 200_000
+    x = orc.sample_errors(77, 1, 1, N).astype(np.float64).ravel()
+    var = sigma**2 + 1 / 12
+    assert abs(x.mean()) < 4 * math.sqrt(var / N)
+    assert abs(x.var() / var - 1) < 0.02
+    p0 = math.erf(0.5 / (sigma * math.sqrt(2)))
+    assert abs((x == 0).mean() - p0) < 4 * math.sqrt(p0 * (1 - p0) / N)
+    assert abs((x > 0).mean() - (x < 0).mean()) < 0.01
+    assert np.abs(x).max() <= 8 * sigma
+
+
 ALL_CHECKS = [
     check_roots,
     check_delta,
@@ -466,4 +504,5 @@ ALL_CHECKS = [
     check_reshare,
     check_chained_rounds,
     check_seeded,
+    check_noise_sampler,
 ]

@@ -54,6 +54,12 @@ MUTANTS = {
     "seeded_index_offset_dropped": ("w[(int64_t)j * C] = or_splitmix64(seed_a, (ct_index0 + q) * (uint64_t)n",
                                     "w[(int64_t)j * C] = or_splitmix64(seed_a, q * (uint64_t)n"),
     "seeded_b_words_transposed": ("w[(int64_t)n * C] = bw[(b * F + f) * C + c];", "w[(int64_t)n * C] = bw[(b * C + c) * F + f];"),
+    "noise_counter_off_by_one": ("uint64_t u = or_splitmix64(seed_e, ct_index0 + q + 1);",
+                                 "uint64_t u = or_splitmix64(seed_e, ct_index0 + q);"),
+    "noise_field_shift": ("uint64_t v = (u >> 15) & ((1ULL << 48) - 1);", "uint64_t v = (u >> 16) & ((1ULL << 48) - 1);"),
+    "noise_sign_from_low_bit": ("e[(b * C + c) * F + f] = (u >> 63) && mag ? -mag : mag;",
+                                "e[(b * C + c) * F + f] = (u & 1) && mag ? -mag : mag;"),
+    "noise_index_transposed": ("e[(b * C + c) * F + f] = (u >> 63)", "e[(b * F + f) * C + c] = (u >> 63)"),
     "reshare_square_dropped": ("uint64_t u = act == 1 ? mulmod(y, y, p) : y;", "uint64_t u = y;"),
 }
 
