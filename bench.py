@@ -238,6 +238,15 @@ def seeded_step(ctx, S, inp, steps: int, warmup: int):
     ok = bool(np.array_equal(m.cpu().numpy().astype(np.int64), (np.einsum("oif,bif->bof", wh, xh) + inp.r) % P))
     kernels_us = {nm: float(np.mean([ev[i].elapsed_time(ev[i + 1]) for ev in events])) * 1e3
                   for i, nm in enumerate(names)}
+    # the client's errors drawn on the device instead of on the host
+    e_dev = torch.empty((S.B, S.Cin, S.F), dtype=torch.int32, device=dv)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(20):
+        ctx.sample_errors(inp.seed_a ^ 0x5EED, S.B, S.Cin, S.F, out=e_dev)
+    ev[1].record()
+    torch.cuda.synchronize()
+    kernels_us["sample_errors (device-drawn e, not in the step)"] = ev[0].elapsed_time(ev[1]) * 1e3 / 20
     hc_us = kernels_us["homconv_seeded"]
     # algorithmic bytes of the seeded HomConv: b words in, ct_out out, weights, masks
     hc_bytes = 8 * S.F * S.B * (S.Cin + (S.n + 1) * S.Cout) + pack_bytes + 4 * S.B * S.Cout * S.F

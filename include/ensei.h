@@ -225,6 +225,21 @@ int ensei_homrec(ensei_ctx *ctx, uint64_t *ct, const uint32_t *s_hat, int64_t ba
 int ensei_reshare(ensei_ctx *ctx, const uint32_t *s_a, const uint32_t *s_b, const uint32_t *s_b_next, int64_t count,
                   int act, uint32_t *s_a_next, void *stream);
 
+/* Errors for Enc drawn on the device: e[b][c][f] (int32 [B][C][F], 4-byte
+ * aligned) from the rounded Gaussian of sigma = 3.2 (the LWE error of Sec.
+ * 3.1), one output of the public SplitMix64 generator seeded with seed_e per
+ * ciphertext: number ct_index0 + q + 1 for the ciphertext index
+ * q = (b*F + f)*C + c of ensei_encrypt. Its top bit is the sign and bits
+ * 15..62 a uniform v < 2^48; |e| is the number of thresholds
+ * T[k] = floor(2^48 erf((k + 1/2) / (sigma sqrt 2))), k < 32, with T[k] <= v
+ * (so |e| <= 32). The context computes the thresholds when it is created. */
+int ensei_sample_errors(ensei_ctx *ctx, uint64_t seed_e, uint64_t ct_index0, int64_t batch, int C, int64_t F,
+                        int32_t *e, void *stream);
+
+/* The sampler's 32 thresholds, copied to out (host memory, n >= 32 entries);
+ * returns 32, or ENSEI_ERR_ARG. */
+int ensei_error_table(const ensei_ctx *ctx, uint64_t *out, int n);
+
 /* --------------------------------------------------- seeded ciphertexts --
  * The a-words of every ciphertext are the public stream of Enc above (the
  * encryption constants that Sec. 5.1 generates offline), so a batch of

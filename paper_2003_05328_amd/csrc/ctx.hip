@@ -2,6 +2,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <math.h>
+
 #include "ensei_internal.hpp"
 
 namespace ensei {
@@ -127,13 +129,27 @@ int ensei_ctx_create(ensei_ctx **out, uint32_t p, int device) {
                 x = host_mulmod(x, w, p);
             }
         }
+    // Error sampler thresholds for the rounded Gaussian of sigma = 3.2:
+    // P(|e| <= k) = erf((k + 1/2) / (sigma sqrt 2)) = erf(5 (2k + 1) / (32 sqrt 2)),
+    // in long double (a 64-bit significand, far finer than the 2^-48 grid);
+    // erf < 1 keeps every entry below 2^48.
+    static_assert(sizeof(c->cdt) / sizeof(c->cdt[0]) == kCdtSize, "threshold count");
+    for (int k = 0; k < kCdtSize; ++k) {
+        const long double x = (long double)(5 * (2 * k + 1)) / (32.0L * sqrtl(2.0L));
+        const long double v = floorl(ldexpl(erfl(x), kCdtBits));
+        const uint64_t top = (1ull << kCdtBits) - 1;
+        c->cdt[k] = v >= (long double)top ? top : (uint64_t)v;
+    }
     int st = ENSEI_OK;
     if (hipMalloc(&c->d_tw, sizeof(tw)) != hipSuccess ||
-        hipMemcpy(c->d_tw, tw, sizeof(tw), hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(c->d_tw, tw, sizeof(tw), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMalloc(&c->d_cdt, sizeof(c->cdt)) != hipSuccess ||
+        hipMemcpy(c->d_cdt, c->cdt, sizeof(c->cdt), hipMemcpyHostToDevice) != hipSuccess)
         st = ENSEI_ERR_HIP;
     (void)hipSetDevice(prev);
     if (st != ENSEI_OK) {
         if (c->d_tw) (void)hipFree(c->d_tw);
+        if (c->d_cdt) (void)hipFree(c->d_cdt);
         free(c);
         return st;
     }
@@ -147,9 +163,17 @@ int ensei_ctx_destroy(ensei_ctx *ctx) {
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(ctx->device);
     hipError_t e = hipFree(ctx->d_tw);
+    const hipError_t e2 = hipFree(ctx->d_cdt);
+    if (e == hipSuccess) e = e2;
     (void)hipSetDevice(prev);
     free(ctx);
     return e == hipSuccess ? ENSEI_OK : ENSEI_ERR_HIP;
+}
+
+int ensei_error_table(const ensei_ctx *ctx, uint64_t *out, int n) {
+    if (!ctx || !out || n < kCdtSize) return ENSEI_ERR_ARG;
+    memcpy(out, ctx->cdt, sizeof(ctx->cdt));
+    return kCdtSize;
 }
 
 uint32_t ensei_ctx_modulus(const ensei_ctx *ctx) { return ctx ? ctx->p : 0; }

@@ -17,11 +17,16 @@ struct ensei_ctx {
     // length L = 2^l (1 <= l <= 7), L/2 entries (omega_L^j, floor(omega_L^j 2^24 / p))
     // starting at entry d * 127 + (L/2 - 1).
     uint2 *d_tw;
+    // Thresholds of the rounded-Gaussian error sampler (ensei_sample_errors),
+    // on the host and on the device: floor(2^48 P(|e| <= k)), k < 32.
+    uint64_t cdt[32];
+    uint64_t *d_cdt;
 };
 
 namespace ensei {
 
 constexpr int kTwPerDir = 127;
+constexpr int kCdtSize = 32, kCdtBits = 48;  // error sampler: thresholds, and their grid 2^-48
 
 // Host-side checks shared by the entry points.
 int check_ctx(const ensei_ctx *ctx);

@@ -190,6 +190,38 @@ __global__ __launch_bounds__(64 * kDecWaves) void decrypt_kernel(const uint64_t 
     }
 }
 
+// Rounded-Gaussian errors from the public generator: one thread per error
+// e[b][c][f] (f fastest, so the int32 stores are contiguous); the generator
+// output is number ct_index0 + q + 1 of seed_e for the ciphertext index
+// q = (b F + f) C + c; its top bit is the sign, bits 15..62 a uniform
+// v < 2^48, and |e| the number of thresholds <= v (binary search over the
+// non-decreasing table in LDS).
+__global__ __launch_bounds__(256) void sample_errors_kernel(const uint64_t *__restrict__ cdt, uint64_t seed_e,
+                                                            uint64_t ct_index0, int64_t B, int C, int64_t F,
+                                                            int32_t *__restrict__ e) {
+    __shared__ uint64_t T[kCdtSize];
+    if (threadIdx.x < kCdtSize) T[threadIdx.x] = cdt[threadIdx.x];
+    __syncthreads();
+    const int64_t total = B * C * F;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t f = i % F, bc = i / F, b = bc / C;
+        const int c = (int)(bc % C);
+        const uint64_t q = (uint64_t)((b * F + f) * C + c);
+        const uint64_t u = splitmix_mix(seed_e + (ct_index0 + q + 1) * kGamma);
+        const uint64_t v = (u >> 15) & ((1ull << kCdtBits) - 1);
+        int lo = 0, hi = kCdtSize;  // the count lies in [lo, hi]
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (T[mid] <= v)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        e[i] = (u >> 63) && lo ? -lo : lo;
+    }
+}
+
 static int check_lwe(const ensei_ctx *ctx, int64_t B, int C, int64_t F, int n, int64_t *groups) {
     int st = check_ctx(ctx);
     if (st) return st;
@@ -237,6 +269,18 @@ int ensei_encrypt_seeded(ensei_ctx *ctx, const uint32_t *m, const int8_t *s, con
     const size_t smem = ((n + 7) & ~7) + kWaves * 64 * 8;
     hipLaunchKernelGGL(encrypt_kernel<false>, dim3((unsigned)groups), dim3(256), smem, (hipStream_t)stream, m, s, e, C,
                        F, n, seed_a, ct_index0, ctx->delta, b_out, lwe_groups(C, F));
+    return launch_status();
+}
+
+int ensei_sample_errors(ensei_ctx *ctx, uint64_t seed_e, uint64_t ct_index0, int64_t batch, int C, int64_t F,
+                        int32_t *e, void *stream) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!e || batch <= 0 || C <= 0 || F <= 0) return ENSEI_ERR_ARG;
+    if ((uintptr_t)e & 3) return ENSEI_ERR_ALIGN;
+    const int64_t total = batch * C * F, blocks = (total + 255) / 256;
+    hipLaunchKernelGGL(sample_errors_kernel, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0,
+                       (hipStream_t)stream, ctx->d_cdt, seed_e, ct_index0, batch, C, F, e);
     return launch_status();
 }
 

@@ -50,6 +50,8 @@ SIGNATURES = {
     "ensei_pack_weights": (_i32, [_vp, _vp, _i32, _i32, _i64, _vp, _vp]),
     "ensei_encrypt": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i64, _i32, _u64, _u64, _vp, _vp]),
     "ensei_homconv": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
+    "ensei_sample_errors": (_i32, [_vp, _u64, _u64, _i64, _i32, _i64, _vp, _vp]),
+    "ensei_error_table": (_i32, [_vp, _vp, _i32]),
     "ensei_encrypt_seeded": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i64, _i32, _u64, _u64, _vp, _vp]),
     "ensei_homconv_seeded": (_i32, [_vp, _vp, _u64, _u64, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
     "ensei_homconv_valu": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
@@ -277,6 +279,21 @@ class Context:
             raise ValueError("ct has the wrong size")
         self._call("ensei_encrypt", _ptr(m), _ptr(s), _ptr(e), B, C, F, n, seed_a % 2**64, ct_index0 % 2**64, _ptr(out))
         return out
+
+    def sample_errors(self, seed_e: int, B: int, C: int, F: int, ct_index0: int = 0, out=None) -> torch.Tensor:
+        """Errors int32 [B][C][F] of the rounded Gaussian (sigma 3.2) from the
+        public generator seeded with seed_e (ensei_sample_errors)."""
+        out = self._out(out, (B, C, F), torch.int32)
+        self._call("ensei_sample_errors", seed_e % 2**64, ct_index0 % 2**64, B, C, F, _ptr(out))
+        return out
+
+    def error_table(self) -> list:
+        """The error sampler's 32 thresholds as computed by the library (ensei_error_table)."""
+        buf = (C.c_uint64 * 32)()
+        n = lib().ensei_error_table(self._h, buf, 32)
+        if n != 32:
+            raise EnseiError(n, "ensei_error_table")
+        return [int(x) for x in buf]
 
     def encrypt_seeded(self, m, s, e, seed_a: int, ct_index0: int = 0, out=None) -> torch.Tensor:
         """Seeded ciphertexts: m uint32 [B][C][F], s, e as encrypt -> only the
