@@ -210,8 +210,8 @@ int ensei_decrypt(ensei_ctx *ctx, const uint64_t *ct, const int8_t *s, int64_t b
  * [batch][C][F] with values < p (the server's share, transformed by
  * ensei_ntt2d). Since Delta * p = 2^64 - 1, a sum that wraps past p adds -1
  * to the ciphertext's noise. The a-words are not touched. 1 <= n <=
- * ENSEI_MAX_LWE_N, 1 <= C <= ENSEI_MAX_COUT; ct 8-byte and s_hat 4-byte
- * aligned and not overlapping. */
+ * ENSEI_MAX_LWE_N, 1 <= C <= ENSEI_MAX_COUT, batch*C*F <= 2^40 (else
+ * ENSEI_ERR_LIMIT); ct 8-byte and s_hat 4-byte aligned and not overlapping. */
 int ensei_homrec(ensei_ctx *ctx, uint64_t *ct, const uint32_t *s_hat, int64_t batch, int C, int64_t F, int n,
                  void *stream);
 
@@ -232,7 +232,8 @@ int ensei_reshare(ensei_ctx *ctx, const uint32_t *s_a, const uint32_t *s_b, cons
  * q = (b*F + f)*C + c of ensei_encrypt. Its top bit is the sign and bits
  * 15..62 a uniform v < 2^48; |e| is the number of thresholds
  * T[k] = floor(2^48 erf((k + 1/2) / (sigma sqrt 2))), k < 32, with T[k] <= v
- * (so |e| <= 32). The context computes the thresholds when it is created. */
+ * (so |e| <= 32). The context computes the thresholds when it is created.
+ * batch*C*F <= 2^40, else ENSEI_ERR_LIMIT. */
 int ensei_sample_errors(ensei_ctx *ctx, uint64_t seed_e, uint64_t ct_index0, int64_t batch, int C, int64_t F,
                         int32_t *e, void *stream);
 

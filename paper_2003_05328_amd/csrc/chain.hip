@@ -75,6 +75,7 @@ int ensei_homrec(ensei_ctx *ctx, uint64_t *ct, const uint32_t *s_hat, int64_t ba
     if (st) return st;
     if (!ct || !s_hat || batch <= 0 || C <= 0 || F <= 0 || n <= 0) return ENSEI_ERR_ARG;
     if (n > ENSEI_MAX_LWE_N || C > ENSEI_MAX_COUT) return ENSEI_ERR_LIMIT;
+    if (batch > ((int64_t)1 << 40) / C / F) return ENSEI_ERR_LIMIT;  // keeps the byte counts below in range
     if (((uintptr_t)ct & 7) || ((uintptr_t)s_hat & 3)) return ENSEI_ERR_ALIGN;
     const size_t num = (size_t)batch * C * F;
     if (overlaps(ct, num * (size_t)(n + 1) * 8, s_hat, num * 4)) return ENSEI_ERR_OVERLAP;

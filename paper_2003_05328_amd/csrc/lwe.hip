@@ -277,6 +277,7 @@ int ensei_sample_errors(ensei_ctx *ctx, uint64_t seed_e, uint64_t ct_index0, int
     int st = check_ctx(ctx);
     if (st) return st;
     if (!e || batch <= 0 || C <= 0 || F <= 0) return ENSEI_ERR_ARG;
+    if (batch > ((int64_t)1 << 40) / C / F) return ENSEI_ERR_LIMIT;
     if ((uintptr_t)e & 3) return ENSEI_ERR_ALIGN;
     const int64_t total = batch * C * F, blocks = (total + 255) / 256;
     hipLaunchKernelGGL(sample_errors_kernel, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0,

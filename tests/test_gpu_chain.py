@@ -124,6 +124,7 @@ def test_chain_argument_errors(ctx):
     assert L.ensei_homrec(h, _ptr(ct), _ptr(s_hat), 1, 3, 2, 0, st) == -1  # n = 0
     assert L.ensei_homrec(h, _ptr(ct), None, 1, 3, 2, 4, st) == -1
     assert L.ensei_homrec(h, _ptr(ct), _ptr(ct), 1, 3, 2, 4, st) == -5  # share inside the ciphertexts
+    assert L.ensei_homrec(h, _ptr(ct), _ptr(s_hat), 1 << 40, 3, 2, 4, st) == -6  # beyond 2^40 ciphertexts
     v = torch.zeros(8, dtype=torch.uint32, device="cuda:0")
     with pytest.raises(EnseiError, match="ARG"):
         ctx.reshare(v, v, v, 2)

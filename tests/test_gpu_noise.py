@@ -77,5 +77,6 @@ def test_sample_errors_argument_errors(ctx):
     assert L.ensei_sample_errors(h, 1, 0, 1, 1, 8, None, st) == -1
     assert L.ensei_sample_errors(h, 1, 0, 0, 1, 8, _ptr(e), st) == -1
     assert L.ensei_sample_errors(h, 1, 0, 1, 1, 1, e.data_ptr() + 2, st) == -4
+    assert L.ensei_sample_errors(h, 1, 0, 1 << 30, 1 << 10, 1 << 10, _ptr(e), st) == -6  # beyond 2^40 errors
     assert L.ensei_error_table(h, None, 32) == -1
     assert not host(e).any()
