@@ -278,7 +278,8 @@ int ensei_homconv_seeded(ensei_ctx *ctx, const uint64_t *b_in, uint64_t seed_a, 
  * are transformed and packed once, when the plan is created.
  *
  * The HomConv tile schedule (persistent workgroups; contiguous tile ranges
- * or chunks of 1..256 tiles dealt round-robin) is picked by timing the
+ * or chunks of 1..256 tiles dealt round-robin; or no shared launch at all,
+ * each of those layers in a launch of its own) is picked by timing the
  * candidates on the plan's own shapes and buffers at creation. With a
  * non-NULL tune_cache path the choice is looked up there first, keyed by the
  * device and the layer shapes, and appended after tuning (a text file, one
@@ -318,7 +319,8 @@ typedef struct ensei_layer {
 } ensei_layer;
 
 /* The HomConv schedule a plan runs: persistent workgroups, chunk (0 =
- * contiguous tile ranges), the measured time of its HomConv launches in
+ * contiguous tile ranges, -1 = a launch per layer instead of the shared
+ * one), the measured time of its HomConv launches in
  * microseconds (0 when taken from the cache), and whether it came from the
  * cache (1) or from tuning (0). Layers of at most 8 input channels, and
  * layers with several 64-row output tiles and at most 256 input channels, run

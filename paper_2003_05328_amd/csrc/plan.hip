@@ -73,10 +73,17 @@ int run_back(ensei_plan *P, hipStream_t st) {
     return ENSEI_OK;
 }
 
+// s.chunk = -1: the shared problems each in a launch of their own instead
 int run_homconv(ensei_plan *P, HcSchedule s, hipStream_t st) {
-    int rc = P->problems.empty()
-                 ? ENSEI_OK
-                 : homconv_launch(P->ctx, P->problems.data(), P->d_table, (int)P->problems.size(), true, s, st);
+    int rc = ENSEI_OK;
+    if (s.chunk < 0) {
+        for (HcLayer h : P->problems) {
+            h.tile0 = 0;  // its own tile space
+            if (!rc) rc = homconv_launch(P->ctx, &h, nullptr, 1, true, HcSchedule{0, 0}, st);
+        }
+    } else if (!P->problems.empty()) {
+        rc = homconv_launch(P->ctx, P->problems.data(), P->d_table, (int)P->problems.size(), true, s, st);
+    }
     for (const auto &hp : P->single)
         if (!rc) rc = homconv_launch(P->ctx, &hp.first, nullptr, 1, hp.second, HcSchedule{0, 0}, st);
     return rc;
@@ -109,7 +116,7 @@ bool cache_lookup(const char *path, const std::string &key, HcSchedule *s) {
         int blocks;
         long long chunk;
         if (sscanf(line, "%3899s %d %lld", k, &blocks, &chunk) == 3 && (key == k || strcmp(k, "*") == 0) &&
-            blocks > 0 && chunk >= 0) {
+            blocks > 0 && chunk >= -1) {
             *s = HcSchedule{blocks, (int64_t)chunk};
             found = true;  // the last entry for a key wins
         }
@@ -245,7 +252,8 @@ int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, co
     } else if (tune_cache && cache_lookup(tune_cache, key, &best)) {
         P->info.from_cache = 1;
     } else {
-        const int64_t chunks[] = {0, 1, 4, 16, 64, 256};
+        // chunk -1: no shared launch, each problem on its own
+        const int64_t chunks[] = {0, 1, 4, 16, 64, 256, -1};
         bool first = true;
         for (int64_t c : chunks) {
             const HcSchedule s{ctx->num_cus, c};
