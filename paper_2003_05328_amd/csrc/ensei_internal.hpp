@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "../../include/ensei.h"
 
 struct ensei_ctx {
@@ -26,6 +28,10 @@ struct ensei_ctx {
 namespace ensei {
 
 constexpr int kTwPerDir = 127;
+// Launch facts computed once per device and kernel (occupancy, a raised
+// dynamic-LDS limit) are cached in atomics indexed by device; devices past
+// this count are not cached.
+constexpr int kMaxDevices = 64;
 constexpr int kCdtSize = 32, kCdtBits = 48;  // error sampler: thresholds, and their grid 2^-48
 
 // Host-side checks shared by the entry points.

@@ -620,7 +620,8 @@ constexpr int kDeepCols = 32;                        // columns per block
 constexpr int kDeepPlane = kDeepCols * 4 * 16;       // one digit plane of a block's K step
 constexpr int kDeepMaxKs = 4;
 
-template <bool WIDE_STORE>
+// SEEDED: seeded input (ensei_homconv_seeded), as in homconv_mfma_kernel.
+template <bool WIDE_STORE, bool SEEDED>
 __global__ __launch_bounds__(kDeepThreads, 2) void homconv_deep_kernel(HcLayer P, uint64_t delta) {
     extern __shared__ __attribute__((aligned(16))) uint8_t dlds[];  // [ks][plane 8] planes, then masks [n_ot 64]
     const int n_ks = P.n_ks, n_ot = P.n_ot, Cin = P.Cin, Cout = P.Cout;
@@ -669,9 +670,13 @@ __global__ __launch_bounds__(kDeepThreads, 2) void homconv_deep_kernel(HcLayer P
         const int jt = (int)(blk % n_jt);
         const int64_t fb = blk / n_jt, b = fb % P.B, f = fb / P.B;
 
-        // the block's words of every K step (8 channels of one column per thread)
-        const uint8_t *src = uniform_ptr(reinterpret_cast<const uint8_t *>(P.ct_in + (b * F + f) * rowlen * Cin));
-        const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, (uint32_t)(rowlen * Cin * 8));
+        // the block's words of every K step (8 channels of one column per
+        // thread); seeded: only the b words, read by the block holding column n
+        const uint8_t *src = uniform_ptr(
+            SEEDED ? reinterpret_cast<const uint8_t *>(P.b_in + (b * F + f) * Cin)
+                   : reinterpret_cast<const uint8_t *>(P.ct_in + (b * F + f) * rowlen * Cin));
+        const __amdgpu_buffer_rsrc_t rs =
+            make_rsrc(src, SEEDED ? (jt == n_jt - 1 ? (uint32_t)(Cin * 8) : 0u) : (uint32_t)(rowlen * Cin * 8));
         const int col = jt * kDeepCols + ld_col;
         u32x4 w[kDeepMaxKs][4];
 #pragma unroll
@@ -679,8 +684,9 @@ __global__ __launch_bounds__(kDeepThreads, 2) void homconv_deep_kernel(HcLayer P
             if (ks >= n_ks) break;
             // columns past n read zero; 8-channel groups past Cin are not read
             const bool any = ld_sc * 16 + ld_h * 8 < Cin - ks * 64;
-            const uint32_t off =
-                any ? (uint32_t)(((int64_t)col * Cin + ks * 64 + ld_sc * 16 + ld_h * 8) * 8) : 0x80000000u;
+            const int c0 = ks * 64 + ld_sc * 16 + ld_h * 8;
+            const uint32_t off = SEEDED ? (any && col == P.n ? (uint32_t)(c0 * 8) : 0x80000000u)
+                                        : (any ? (uint32_t)(((int64_t)col * Cin + c0) * 8) : 0x80000000u);
 #pragma unroll
             for (int q = 0; q < 4; ++q) w[ks][q] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16 * q), 0, 0);
         }
@@ -694,11 +700,27 @@ __global__ __launch_bounds__(kDeepThreads, 2) void homconv_deep_kernel(HcLayer P
 #pragma unroll
         for (int ks = 0; ks < kDeepMaxKs; ++ks) {
             if (ks >= n_ks) break;
+            // seeded: words j = col < n of the thread's 8 channels from the
+            // public stream (zero where the words were loaded)
+            uint64_t gen[8] = {};
+            if (SEEDED) {
+                const int c0 = ks * 64 + ld_sc * 16 + ld_h * 8;
+                const bool on = c0 < Cin && col < P.n;
+                const uint64_t q0 = P.idx0 + (uint64_t)((b * F + f) * Cin + c0);
+                uint64_t z = P.seed_a + (q0 * (uint64_t)P.n + (uint64_t)col + 1) * kGamma;
+                const uint64_t step = (uint64_t)P.n * kGamma;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const uint64_t a = splitmix_mix(z);
+                    gen[i] = on ? a : 0ull;
+                    z += step;
+                }
+            }
             uint32_t lo[8], hi[8], pl[8][2];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const uint64_t v0 = ((uint64_t)w[ks][q].y << 32 | w[ks][q].x) + 0x8080808080808080ull;
-                const uint64_t v1 = ((uint64_t)w[ks][q].w << 32 | w[ks][q].z) + 0x8080808080808080ull;
+                const uint64_t v0 = ((uint64_t)w[ks][q].y << 32 | w[ks][q].x) + gen[2 * q] + 0x8080808080808080ull;
+                const uint64_t v1 = ((uint64_t)w[ks][q].w << 32 | w[ks][q].z) + gen[2 * q + 1] + 0x8080808080808080ull;
                 lo[2 * q] = (uint32_t)v0;
                 hi[2 * q] = (uint32_t)(v0 >> 32);
                 lo[2 * q + 1] = (uint32_t)v1;
@@ -1238,12 +1260,13 @@ static int launch_narrow(const ensei_ctx *ctx, const HcLayer &P, HcSchedule sche
     const bool wide = P.Cout % 2 == 0;
     auto kernel = wide ? homconv_narrow_kernel<NCH, kNarrowDepth, true, SEEDED>
                        : homconv_narrow_kernel<NCH, kNarrowDepth, false, SEEDED>;
-    static int resident[2] = {0, 0};  // workgroups per CU, by store width
-    int per_cu = resident[wide];
+    static std::atomic<int> resident[kMaxDevices][2];  // workgroups per CU, by device and store width
+    const bool cached = ctx->device < kMaxDevices;
+    int per_cu = cached ? resident[ctx->device][wide].load(std::memory_order_relaxed) : 0;
     if (per_cu == 0) {
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kNarrowThreads, 0) != hipSuccess || per_cu < 1)
             per_cu = 1;
-        resident[wide] = per_cu;
+        if (cached) resident[ctx->device][wide].store(per_cu, std::memory_order_relaxed);
     }
     const int64_t units = P.B * P.F * P.n_ot * ((P.n + 1 + 15) / 16);
     int64_t blocks = sched.blocks > 0 ? sched.blocks : (int64_t)ctx->num_cus * per_cu;
@@ -1265,17 +1288,19 @@ bool homconv_deep_fits(const HcLayer &P) {
            deep_lds_bytes(P) <= (size_t)kLdsBytes / 2;
 }
 
+template <bool SEEDED>
 static int launch_deep(const ensei_ctx *ctx, const HcLayer &P, hipStream_t stream) {
     if (!homconv_deep_fits(P)) return ENSEI_ERR_LIMIT;
     const size_t lds = deep_lds_bytes(P);
     const bool wide = P.Cout % 2 == 0;
-    auto kernel = wide ? homconv_deep_kernel<true> : homconv_deep_kernel<false>;
-    static bool attr[2] = {false, false};
-    if (!attr[wide]) {
+    auto kernel = wide ? homconv_deep_kernel<true, SEEDED> : homconv_deep_kernel<false, SEEDED>;
+    static std::atomic<bool> attr[kMaxDevices][2];  // dynamic-LDS limit raised, by device and store width
+    const bool cached = ctx->device < kMaxDevices;
+    if (!cached || !attr[ctx->device][wide].load(std::memory_order_acquire)) {
         if (hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes / 2) !=
             hipSuccess)
             return ENSEI_ERR_HIP;
-        attr[wide] = true;
+        if (cached) attr[ctx->device][wide].store(true, std::memory_order_release);
     }
     // two resident workgroups per CU
     const int64_t blocks_total = P.B * P.F * ((P.n + 1 + kDeepCols - 1) / kDeepCols);
@@ -1289,7 +1314,7 @@ int homconv_launch(const ensei_ctx *ctx, const HcLayer *problems, const HcLayer 
     if (nlayers < 1 || (nlayers > 1 && (!dev_table || !paired))) return ENSEI_ERR_ARG;
     if (sched.chunk < 0) return ENSEI_ERR_ARG;
     if (nlayers == 1 && paired && sched.blocks == 0) {
-        const int rc = launch_deep(ctx, problems[0], stream);
+        const int rc = launch_deep<false>(ctx, problems[0], stream);
         if (rc != ENSEI_ERR_LIMIT) return rc;
     }
     if (nlayers == 1 && !paired && problems[0].Cin <= kNarrowCin) {
@@ -1359,6 +1384,10 @@ int ensei_homconv_seeded(ensei_ctx *ctx, const uint64_t *b_in, uint64_t seed_a, 
     if (Cin <= kNarrowCin)
         return Cin <= 4 ? launch_narrow<4, true>(ctx, P, HcSchedule{0, 0}, (hipStream_t)stream)
                         : launch_narrow<8, true>(ctx, P, HcSchedule{0, 0}, (hipStream_t)stream);
+    if (Cin >= kPairedCin) {
+        const int rc = launch_deep<true>(ctx, P, (hipStream_t)stream);
+        if (rc != ENSEI_ERR_LIMIT) return rc;
+    }
     // otherwise the streaming kernel: one 8-wave workgroup per CU
     const bool paired = Cin >= kPairedCin, wide = Cout % 2 == 0;
     const int64_t blocks = P.n_tiles < ctx->num_cus ? P.n_tiles : ctx->num_cus;

@@ -187,11 +187,12 @@ static int launch_ntt(const uint32_t *in, uint32_t *out, int64_t batch, const en
     using S = NttShape<LOGH, LOGW>;
     const size_t lds = (size_t)S::LDS_WORDS * 4;
     auto kern = ntt2d_kernel<LOGH, LOGW, MODE>;
-    static bool attr_set = false;
-    if (!attr_set && lds > 48 * 1024) {
+    static std::atomic<bool> attr_set[kMaxDevices];  // dynamic-LDS limit raised, by device
+    const bool cached = ctx->device < kMaxDevices;
+    if (lds > 48 * 1024 && (!cached || !attr_set[ctx->device].load(std::memory_order_acquire))) {
         if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
             return ENSEI_ERR_HIP;
-        attr_set = true;
+        if (cached) attr_set[ctx->device].store(true, std::memory_order_release);
     }
     const int64_t blocks = (batch + S::T - 1) / S::T;
     if (blocks > 0x7fffffff) return ENSEI_ERR_LIMIT;

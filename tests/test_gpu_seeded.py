@@ -53,8 +53,9 @@ def test_encrypt_seeded(ctx, orc, B, C, F, n, idx0):
 
 
 HC_CASES = [
-    # B, Cin, Cout, F, n (narrow kernel up to 8 input channels, then the
-    # streaming kernel: folded scheme below 48 input channels, paired from 48)
+    # B, Cin, Cout, F, n (narrow kernel up to 8 input channels, the deep kernel
+    # where it fits, else the streaming kernel: folded scheme below 48 input
+    # channels, paired from 48)
     (1, 1, 1, 1, 1),
     (2, 3, 8, 5, 64),
     (2, 8, 64, 7, 31),
@@ -68,6 +69,11 @@ HC_CASES = [
     (1, 64, 130, 3, 63),
     (2, 100, 64, 40, 130),  # more tiles than resident workgroups
     (1, 3, 64, 64, 255),
+    # deep kernel (several row tiles, at most 256 input channels)
+    (1, 48, 300, 3, 70),
+    (2, 100, 128, 64, 64),
+    (1, 256, 130, 5, 129),
+    (1, 130, 512, 2, 40),
 ]
 
 
