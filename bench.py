@@ -391,6 +391,21 @@ def stack_batched(ctx, reps: int, seed: int):
     macs = sum(S.B * S.Cout * S.Cin * S.F for S in shapes)
     hc_bytes = sum(8 * (S.n + 1) * S.F * S.B * (S.Cin + S.Cout) for S in shapes)
     plan.close()
+    del seq
+    torch.cuda.empty_cache()
+    # the same stack on seeded ciphertexts (b words only on the input side)
+    sl = []
+    for S, l in zip(shapes, layers):
+        d = {k: l[k] for k in ("H", "W", "Cin", "Cout", "kh", "kw", "n", "seed_a", "w", "x", "s", "e", "r")}
+        d.update(Plan.buffers(ctx, S.H, S.W, S.Cin, S.Cout, S.n, S.B, seeded=True))
+        sl.append(d)
+    splan = Plan(ctx, sl, seeded=True)
+    seeded_ms = timed(splan.run)
+    seeded_same = all(torch.equal(a[k], b[k]) for a, b in zip(sl, layers) for k in ("ct_out", "m", "s_a", "s_b"))
+    seeded_same = seeded_same and all(torch.equal(a["ct_in"], b["ct_in"][:, :, S.n, :])
+                                      for S, a, b in zip(shapes, sl, layers))
+    seeded_sched = splan.schedule()
+    splan.close()
     return {
         "workload": "stack8: 7 layers (3,64,32),(64,64,32),(64,128,16),(128,128,16),(128,256,8),(256,256,8),"
                     "(256,512,4), 3x3, n=1024, batch 8",
@@ -404,6 +419,8 @@ def stack_batched(ctx, reps: int, seed: int):
         "homconv_ct_bytes": hc_bytes,
         "plan_create_s": create_s,
         "bit_exact_vs_sequential": bool(same),
+        "seeded": {"batched_ms": seeded_ms, "ct_mac_per_s": macs / (seeded_ms * 1e-3),
+                   "homconv_schedule": seeded_sched, "bit_exact_vs_unseeded": bool(seeded_same)},
     }
 
 
@@ -795,7 +812,8 @@ def main():
         torch.cuda.empty_cache()
         result["homconv_layers"] = homconv_layers(ctx)
         result["batched"] = stack_batched(ctx, args.stack_reps, args.seed)
-        result["verified"] = result["verified"] and result["batched"]["bit_exact_vs_sequential"]
+        result["verified"] = (result["verified"] and result["batched"]["bit_exact_vs_sequential"]
+                              and result["batched"]["seeded"]["bit_exact_vs_unseeded"])
         torch.cuda.empty_cache()
         result["chained"] = chained(ctx, args.stack_reps, args.seed)
         result["verified"] = result["verified"] and result["chained"]["bit_exact"]

@@ -345,6 +345,14 @@ typedef struct ensei_schedule {
 int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const char *tune_cache,
                       ensei_plan **out);
 
+/* The same plan on seeded ciphertexts (ensei_encrypt_seeded,
+ * ensei_homconv_seeded): each layer's ct_in holds only the b words, uint64
+ * [batch][F][Cin], and HomConv regenerates the a-words from the layer's
+ * seed_a. Every other buffer, and every result (ct_out, m, s_a, s_b), is
+ * as in ensei_plan_create. Tuning-cache keys carry "/seeded". */
+int ensei_plan_create_seeded(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const char *tune_cache,
+                             ensei_plan **out);
+
 /* Enqueues one run of the captured graph on `stream` (asynchronous). */
 int ensei_plan_run(ensei_plan *plan, void *stream);
 

@@ -134,7 +134,8 @@ int homconv_problem(const ensei_ctx *ctx, HcLayer *P, const uint64_t *ct_in, con
 bool homconv_deep_fits(const HcLayer &P);
 // Launches the matrix-core HomConv over problems[0..nlayers) (host copies;
 // dev_table holds the same array in device memory when nlayers > 1).
+// seeded: the problems' inputs are seeded (b_in, seed_a, idx0)
 int homconv_launch(const ensei_ctx *ctx, const HcLayer *problems, const HcLayer *dev_table, int nlayers, bool paired,
-                   HcSchedule sched, hipStream_t stream);
+                   HcSchedule sched, hipStream_t stream, bool seeded = false);
 
 }  // namespace ensei

@@ -1309,18 +1309,42 @@ static int launch_deep(const ensei_ctx *ctx, const HcLayer &P, hipStream_t strea
     return launch_status();
 }
 
+// The streaming kernel for a launch's layout: paired or folded limbs, even or
+// odd Cout, one problem or a table of them, plain or seeded input.
+template <bool MULTI, bool SEEDED>
+static void launch_streaming(const ensei_ctx *ctx, const HcLayer *problems, const HcLayer *dev_table, int nlayers,
+                             bool paired, bool wide, int64_t blocks, int64_t total, int64_t chunk, hipStream_t stream) {
+    if (MULTI) {  // multi-problem launches use paired fragments
+        auto kernel = wide ? homconv_mfma_kernel<true, true, true, SEEDED> : homconv_mfma_kernel<true, false, true, SEEDED>;
+        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kHcThreads), 0, stream, problems[0], dev_table, nlayers,
+                           total, chunk, ctx->delta);
+        return;
+    }
+    // one limb pair per MFMA once the 64-channel K steps are full enough;
+    // limbs folded into K for narrow inputs
+    auto kernel = paired ? (wide ? homconv_mfma_kernel<true, true, false, SEEDED>
+                                 : homconv_mfma_kernel<true, false, false, SEEDED>)
+                         : (wide ? homconv_mfma_kernel<false, true, false, SEEDED>
+                                 : homconv_mfma_kernel<false, false, false, SEEDED>);
+    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kHcThreads), 0, stream, problems[0], dev_table, 1, total,
+                       chunk, ctx->delta);
+}
+
 int homconv_launch(const ensei_ctx *ctx, const HcLayer *problems, const HcLayer *dev_table, int nlayers, bool paired,
-                   HcSchedule sched, hipStream_t stream) {
+                   HcSchedule sched, hipStream_t stream, bool seeded) {
     if (nlayers < 1 || (nlayers > 1 && (!dev_table || !paired))) return ENSEI_ERR_ARG;
     if (sched.chunk < 0) return ENSEI_ERR_ARG;
     if (nlayers == 1 && paired && sched.blocks == 0) {
-        const int rc = launch_deep<false>(ctx, problems[0], stream);
+        const int rc = seeded ? launch_deep<true>(ctx, problems[0], stream) : launch_deep<false>(ctx, problems[0], stream);
         if (rc != ENSEI_ERR_LIMIT) return rc;
     }
     if (nlayers == 1 && !paired && problems[0].Cin <= kNarrowCin) {
-        const int Cin = problems[0].Cin;
-        return Cin <= 4 ? launch_narrow<4, false>(ctx, problems[0], sched, stream)
-                        : launch_narrow<8, false>(ctx, problems[0], sched, stream);
+        const bool four = problems[0].Cin <= 4;
+        if (seeded)
+            return four ? launch_narrow<4, true>(ctx, problems[0], sched, stream)
+                        : launch_narrow<8, true>(ctx, problems[0], sched, stream);
+        return four ? launch_narrow<4, false>(ctx, problems[0], sched, stream)
+                    : launch_narrow<8, false>(ctx, problems[0], sched, stream);
     }
     int64_t total = 0;
     bool wide = true;
@@ -1332,21 +1356,15 @@ int homconv_launch(const ensei_ctx *ctx, const HcLayer *problems, const HcLayer 
     int64_t blocks = sched.blocks > 0 ? sched.blocks : ctx->num_cus;
     if (blocks > ctx->num_cus) blocks = ctx->num_cus;
     if (sched.chunk == 0 && total < blocks) blocks = total;
-    if (nlayers > 1) {
-        auto kernel =
-            wide ? homconv_mfma_kernel<true, true, true, false> : homconv_mfma_kernel<true, false, true, false>;
-        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kHcThreads), 0, stream, problems[0], dev_table, nlayers,
-                           total, sched.chunk, ctx->delta);
-    } else {
-        // one limb pair per MFMA once the 64-channel K steps are full enough;
-        // limbs folded into K for narrow inputs
-        auto kernel =
-            paired ? (wide ? homconv_mfma_kernel<true, true, false, false> : homconv_mfma_kernel<true, false, false, false>)
-                   : (wide ? homconv_mfma_kernel<false, true, false, false>
-                           : homconv_mfma_kernel<false, false, false, false>);
-        hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kHcThreads), 0, stream, problems[0], dev_table, 1,
-                           total, sched.chunk, ctx->delta);
-    }
+    const bool multi = nlayers > 1;
+    if (multi && seeded)
+        launch_streaming<true, true>(ctx, problems, dev_table, nlayers, paired, wide, blocks, total, sched.chunk, stream);
+    else if (multi)
+        launch_streaming<true, false>(ctx, problems, dev_table, nlayers, paired, wide, blocks, total, sched.chunk, stream);
+    else if (seeded)
+        launch_streaming<false, true>(ctx, problems, dev_table, 1, paired, wide, blocks, total, sched.chunk, stream);
+    else
+        launch_streaming<false, false>(ctx, problems, dev_table, 1, paired, wide, blocks, total, sched.chunk, stream);
     return launch_status();
 }
 
@@ -1381,22 +1399,7 @@ int ensei_homconv_seeded(ensei_ctx *ctx, const uint64_t *b_in, uint64_t seed_a, 
     if (st) return st;
     P.seed_a = seed_a;
     P.idx0 = ct_index0;
-    if (Cin <= kNarrowCin)
-        return Cin <= 4 ? launch_narrow<4, true>(ctx, P, HcSchedule{0, 0}, (hipStream_t)stream)
-                        : launch_narrow<8, true>(ctx, P, HcSchedule{0, 0}, (hipStream_t)stream);
-    if (Cin >= kPairedCin) {
-        const int rc = launch_deep<true>(ctx, P, (hipStream_t)stream);
-        if (rc != ENSEI_ERR_LIMIT) return rc;
-    }
-    // otherwise the streaming kernel: one 8-wave workgroup per CU
-    const bool paired = Cin >= kPairedCin, wide = Cout % 2 == 0;
-    const int64_t blocks = P.n_tiles < ctx->num_cus ? P.n_tiles : ctx->num_cus;
-    auto kernel =
-        paired ? (wide ? homconv_mfma_kernel<true, true, false, true> : homconv_mfma_kernel<true, false, false, true>)
-               : (wide ? homconv_mfma_kernel<false, true, false, true> : homconv_mfma_kernel<false, false, false, true>);
-    hipLaunchKernelGGL(kernel, dim3((unsigned)blocks), dim3(kHcThreads), 0, (hipStream_t)stream, P, nullptr, 1,
-                       P.n_tiles, (int64_t)0, ctx->delta);
-    return launch_status();
+    return homconv_launch(ctx, &P, nullptr, 1, Cin >= kPairedCin, HcSchedule{0, 0}, (hipStream_t)stream, true);
 }
 
 int ensei_homconv_valu(ensei_ctx *ctx, const uint64_t *ct_in, const uint32_t *w_hat, const uint32_t *r,

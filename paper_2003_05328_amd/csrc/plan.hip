@@ -25,6 +25,9 @@ struct ensei_plan {
     hipGraphExec_t exec = nullptr;
     ensei::HcSchedule sched{0, 0};
     ensei_schedule info{};
+    // seeded ciphertexts: each layer's ct_in holds only the b words,
+    // [batch][F][Cin], and HomConv regenerates the a-words from seed_a
+    bool seeded = false;
 };
 
 namespace ensei {
@@ -55,7 +58,10 @@ int run_front(ensei_plan *P, hipStream_t st) {
     for (const ensei_layer &l : P->layers) {
         const int64_t F = (int64_t)l.H * l.W;
         int rc = ensei_ntt2d(P->ctx, l.x, l.x_hat, l.batch * l.Cin, l.H, l.W, st);
-        if (!rc) rc = ensei_encrypt(P->ctx, l.x_hat, l.s, l.e, l.batch, l.Cin, F, l.n, l.seed_a, 0, l.ct_in, st);
+        if (!rc)
+            rc = P->seeded
+                     ? ensei_encrypt_seeded(P->ctx, l.x_hat, l.s, l.e, l.batch, l.Cin, F, l.n, l.seed_a, 0, l.ct_in, st)
+                     : ensei_encrypt(P->ctx, l.x_hat, l.s, l.e, l.batch, l.Cin, F, l.n, l.seed_a, 0, l.ct_in, st);
         if (rc) return rc;
     }
     return ENSEI_OK;
@@ -79,13 +85,13 @@ int run_homconv(ensei_plan *P, HcSchedule s, hipStream_t st) {
     if (s.chunk < 0) {
         for (HcLayer h : P->problems) {
             h.tile0 = 0;  // its own tile space
-            if (!rc) rc = homconv_launch(P->ctx, &h, nullptr, 1, true, HcSchedule{0, 0}, st);
+            if (!rc) rc = homconv_launch(P->ctx, &h, nullptr, 1, true, HcSchedule{0, 0}, st, P->seeded);
         }
     } else if (!P->problems.empty()) {
-        rc = homconv_launch(P->ctx, P->problems.data(), P->d_table, (int)P->problems.size(), true, s, st);
+        rc = homconv_launch(P->ctx, P->problems.data(), P->d_table, (int)P->problems.size(), true, s, st, P->seeded);
     }
     for (const auto &hp : P->single)
-        if (!rc) rc = homconv_launch(P->ctx, &hp.first, nullptr, 1, hp.second, HcSchedule{0, 0}, st);
+        if (!rc) rc = homconv_launch(P->ctx, &hp.first, nullptr, 1, hp.second, HcSchedule{0, 0}, st, P->seeded);
     return rc;
 }
 
@@ -95,7 +101,7 @@ std::string plan_key(const ensei_plan *P) {
     hipDeviceProp_t prop;
     char buf[160];
     const char *arch = hipGetDeviceProperties(&prop, P->ctx->device) == hipSuccess ? prop.gcnArchName : "unknown";
-    snprintf(buf, sizeof buf, "%s/cus=%d/p=%u", arch, P->ctx->num_cus, P->ctx->p);
+    snprintf(buf, sizeof buf, "%s/cus=%d/p=%u%s", arch, P->ctx->num_cus, P->ctx->p, P->seeded ? "/seeded" : "");
     std::string key = buf;
     for (const HcLayer &h : P->problems) {
         snprintf(buf, sizeof buf, "|b%lld.f%lld.i%d.o%d.n%d", (long long)h.B, (long long)h.F, h.Cin, h.Cout, h.n);
@@ -154,15 +160,9 @@ int time_schedule(ensei_plan *P, HcSchedule s, double *us) {
     return rc;
 }
 
-}  // namespace
-}  // namespace ensei
-
-using namespace ensei;
-
-extern "C" {
-
-int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const char *tune_cache,
-                      ensei_plan **out) {
+// Creates a plan (ensei_plan_create, ensei_plan_create_seeded).
+int plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const char *tune_cache, ensei_plan **out,
+                bool seeded) {
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!out || !layers || nlayers < 1) return ENSEI_ERR_ARG;
@@ -171,6 +171,7 @@ int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, co
     DeviceGuard guard(ctx->device);
     ensei_plan *P = new ensei_plan;
     P->ctx = ctx;
+    P->seeded = seeded;
     P->layers.assign(layers, layers + nlayers);
     if (hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) != hipSuccess) {
         P->stream = nullptr;
@@ -202,7 +203,9 @@ int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, co
         rc = ensei_weight_prep(ctx, l.w, l.Cout, l.Cin, l.kh, l.kw, l.H, l.W, wh, P->stream);
         if (!rc) rc = pack_weights_as(ctx, wh, l.Cout, l.Cin, F, !narrow, wp, P->stream);
         HcLayer h;
-        if (!rc) rc = homconv_problem(ctx, &h, l.ct_in, wp, l.r, l.batch, l.Cin, l.Cout, F, l.n, l.ct_out, wpb);
+        if (!rc) rc = homconv_problem(ctx, &h, l.ct_in, wp, l.r, l.batch, l.Cin, l.Cout, F, l.n, l.ct_out, wpb, seeded);
+        h.seed_a = seeded ? l.seed_a : 0;
+        h.idx0 = 0;
         if (rc) {
             release(P);
             return rc;
@@ -298,6 +301,22 @@ int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, co
     }
     *out = P;
     return ENSEI_OK;
+}
+}  // namespace
+}  // namespace ensei
+
+using namespace ensei;
+
+extern "C" {
+
+int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const char *tune_cache,
+                      ensei_plan **out) {
+    return plan_create(ctx, layers, nlayers, tune_cache, out, false);
+}
+
+int ensei_plan_create_seeded(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const char *tune_cache,
+                             ensei_plan **out) {
+    return plan_create(ctx, layers, nlayers, tune_cache, out, true);
 }
 
 int ensei_plan_run(ensei_plan *plan, void *stream) {

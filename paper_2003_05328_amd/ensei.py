@@ -59,6 +59,7 @@ SIGNATURES = {
     "ensei_homrec": (_i32, [_vp, _vp, _vp, _i64, _i32, _i64, _i32, _vp]),
     "ensei_reshare": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _vp, _vp]),
     "ensei_plan_create": (_i32, [_vp, _vp, _i32, C.c_char_p, C.POINTER(_vp)]),
+    "ensei_plan_create_seeded": (_i32, [_vp, _vp, _i32, C.c_char_p, C.POINTER(_vp)]),
     "ensei_plan_run": (_i32, [_vp, _vp]),
     "ensei_plan_schedule": (_i32, [_vp, _vp]),
     "ensei_plan_destroy": (_i32, [_vp]),
@@ -415,7 +416,9 @@ class Plan:
     _INPUTS = ("w", "x", "s", "e", "r")
     _OUTPUTS = ("x_hat", "ct_in", "ct_out", "m", "s_a", "s_b")
 
-    def __init__(self, ctx: "Context", layers: list, tune_cache: str | None = None):
+    def __init__(self, ctx: "Context", layers: list, tune_cache: str | None = None, seeded: bool = False):
+        """seeded: seeded ciphertexts (ensei_plan_create_seeded); each layer's
+        ct_in then holds only the b words, [batch][F][Cin]."""
         self.ctx = ctx
         self.layers = layers
         arr = (LayerDesc * len(layers))()
@@ -431,7 +434,7 @@ class Plan:
             H, W, Cin, Cout, n = (int(l[k]) for k in ("H", "W", "Cin", "Cout", "n"))
             F = H * W
             sizes = {"w": Cout * Cin * int(l["kh"]) * int(l["kw"]), "x": B * Cin * F, "s": n, "e": B * Cin * F,
-                     "r": B * Cout * F, "x_hat": B * Cin * F, "ct_in": B * F * (n + 1) * Cin,
+                     "r": B * Cout * F, "x_hat": B * Cin * F, "ct_in": B * F * (1 if seeded else n + 1) * Cin,
                      "ct_out": B * F * (n + 1) * Cout, "m": B * Cout * F, "s_a": B * Cout * F, "s_b": B * Cout * F}
             for k in self._INPUTS + self._OUTPUTS:
                 t = ctx._dev(l[k], k, dtypes[k])
@@ -441,16 +444,17 @@ class Plan:
         h = C.c_void_p()
         cache = tune_cache.encode() if tune_cache else None
         with torch.cuda.device(ctx.device):
-            _check(lib().ensei_plan_create(ctx._h, arr, len(layers), cache, C.byref(h)), "ensei_plan_create")
+            name = "ensei_plan_create_seeded" if seeded else "ensei_plan_create"
+            _check(getattr(lib(), name)(ctx._h, arr, len(layers), cache, C.byref(h)), name)
         self._h = h
 
     @staticmethod
-    def buffers(ctx: "Context", H, W, Cin, Cout, n, batch) -> dict:
-        """Device outputs of one layer of a plan."""
+    def buffers(ctx: "Context", H, W, Cin, Cout, n, batch, seeded: bool = False) -> dict:
+        """Device outputs of one layer of a plan (seeded: ct_in holds the b words only)."""
         F = H * W
         return {
             "x_hat": ctx._empty((batch, Cin, F), torch.uint32),
-            "ct_in": ctx._empty((batch, F, n + 1, Cin), torch.uint64),
+            "ct_in": ctx._empty((batch, F, Cin) if seeded else (batch, F, n + 1, Cin), torch.uint64),
             "ct_out": ctx._empty((batch, F, n + 1, Cout), torch.uint64),
             "m": ctx._empty((batch, Cout, F), torch.uint32),
             "s_a": ctx._empty((batch, Cout, H, W), torch.uint32),

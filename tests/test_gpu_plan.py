@@ -148,3 +148,41 @@ def test_plan_replays_see_new_inputs(ctx, orc, tmp_path):
             for k in Plan._OUTPUTS:
                 assert np.array_equal(host(l[k]).reshape(-1), host(ref[k]).reshape(-1)), (rep, k)
     plan.close()
+
+
+# seeded plan: a narrow layer, a deep one and two in the shared launch
+STACK_SEEDED = [
+    LayerShape(H=8, W=8, Cin=3, Cout=16, kh=3, kw=3, n=70, B=2),
+    LayerShape(H=4, W=8, Cin=130, Cout=130, kh=3, kw=3, n=64, B=1),
+    LayerShape(H=16, W=16, Cin=64, Cout=64, kh=3, kw=3, n=100, B=2, hidden=True),
+    LayerShape(H=8, W=8, Cin=48, Cout=70, kh=3, kw=3, n=40, B=1),
+]
+
+
+@pytest.mark.parametrize("chunk", [None, 16, -1])
+def test_seeded_plan_matches_single_calls(ctx, orc, tmp_path, chunk):
+    """A plan on seeded ciphertexts: its b words are those of the unseeded
+    single calls' ciphertexts, and every other result is the same bits."""
+    layers = []
+    for i, S in enumerate(STACK_SEEDED):
+        inp, l = _layer(ctx, S, 500 + i)
+        l.update(Plan.buffers(ctx, S.H, S.W, S.Cin, S.Cout, S.n, S.B, seeded=True))
+        layers.append((inp, l))
+    cache = tmp_path / "t.txt"
+    if chunk is not None:
+        cache.write_text(f"* {torch.cuda.get_device_properties(0).multi_processor_count} {chunk}\n")
+    plan = Plan(ctx, [l for _, l in layers], tune_cache=str(cache), seeded=True)
+    if chunk is not None:
+        assert plan.schedule()["chunk"] == chunk
+    for _ in range(2):  # the captured graph replays
+        plan.run()
+        torch.cuda.synchronize()
+        for S, (inp, l) in zip(STACK_SEEDED, layers):
+            ref = _single_calls(ctx, S, l)
+            assert np.array_equal(host(l["ct_in"]), host(ref["ct_in"])[:, :, S.n, :])
+            for k in ("x_hat", "ct_out", "m", "s_a", "s_b"):
+                assert np.array_equal(host(l[k]).reshape(-1), host(ref[k]).reshape(-1)), k
+            conv = orc.cyclic_conv(inp.x, inp.w, P)
+            shares = (host(l["s_a"]).astype(np.int64) + host(l["s_b"])) % P
+            assert np.array_equal(shares.reshape(conv.shape), conv)
+    plan.close()
