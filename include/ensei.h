@@ -16,9 +16,16 @@
  *   server:  s_B = INTT2D(-r)              ensei_server_share  transform of their shares)
  * and s_A + s_B = x (*) w mod p (Sec. 4.1, Appendix A).
  *
+ * Beyond that round: later rounds chain through ensei_reshare (a stand-in for
+ * the activation, in the clear) and ensei_homrec (the server adds its share
+ * to the client's fresh ciphertexts); seeded ciphertexts keep only their b
+ * words (ensei_encrypt_seeded, ensei_homconv_seeded, ensei_plan_create_seeded);
+ * ensei_sample_errors draws Enc's errors on the device; batched plans and a
+ * serving layer run many convolutions.
+ *
  * Common rules for every call below:
- *   - every array pointer is a DEVICE pointer on the context's device, owned
- *     by the caller, who keeps it alive until the work queued on `stream`
+ *   - every array pointer is a DEVICE pointer on the context's device (the
+ *     calls that take host memory say so), owned by the caller, who keeps it alive until the work queued on `stream`
  *     has finished; the library never frees, retains or allocates on a call;
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
  *     every call only enqueues work on it and returns without synchronising;
