@@ -432,6 +432,13 @@ size_t ensei_request_bytes(const ensei_shape *shape);
  * requests per batch. Starts the worker thread. */
 int ensei_server_create(ensei_ctx *ctx, size_t budget_bytes, int nstreams, int max_batch, ensei_server **out);
 
+/* The same server on seeded ciphertexts (ensei_encrypt_seeded,
+ * ensei_homconv_seeded): a request keeps only the b words of its input
+ * ciphertexts, so it takes 8*F*n*Cin bytes less of the budget than
+ * ensei_request_bytes states (up to alignment); results are unchanged. */
+int ensei_server_create_seeded(ensei_ctx *ctx, size_t budget_bytes, int nstreams, int max_batch,
+                               ensei_server **out);
+
 /* Registers a shape with the server's filters w [Cout][Cin][kh][kw] int32
  * (read once, synchronously). ENSEI_ERR_LIMIT if one request of the shape
  * does not fit the budget; the single calls' shape errors otherwise. */

@@ -93,6 +93,9 @@ struct ensei_server {
     Clock::time_point t0 = Clock::now();
     uint64_t n_done = 0, n_failed = 0, n_batches = 0;
     size_t peak_used = 0;
+    // seeded ciphertexts (ensei_server_create_seeded): a request keeps only
+    // the b words of its input ciphertexts
+    bool seeded = false;
 };
 
 namespace ensei {
@@ -100,18 +103,19 @@ namespace {
 
 double secs(const ensei_server *S, Clock::time_point t) { return std::chrono::duration<double>(t - S->t0).count(); }
 
-// Arena layout of one request: x^ [Cin][F] u32, ct_in [F][n+1][Cin] u64,
-// ct_out [F][n+1][Cout] u64, m [Cout][F] u32 (each 256-byte aligned).
+// Arena layout of one request: x^ [Cin][F] u32, ct_in [F][n+1][Cin] u64
+// (seeded: the b words, [F][Cin]), ct_out [F][n+1][Cout] u64, m [Cout][F] u32
+// (each 256-byte aligned).
 struct Parts {
     size_t x_hat, ct_in, ct_out, m, total;
 };
-Parts parts_of(const ensei_shape &d) {
+Parts parts_of(const ensei_shape &d, bool seeded = false) {
     auto al = [](size_t v) { return (v + kAlign - 1) / kAlign * kAlign; };
     const size_t F = (size_t)d.H * d.W;
     Parts p;
     p.x_hat = 0;
     p.ct_in = al(F * d.Cin * 4);
-    p.ct_out = p.ct_in + al(F * (d.n + 1) * d.Cin * 8);
+    p.ct_out = p.ct_in + al(F * (seeded ? 1 : d.n + 1) * d.Cin * 8);
     p.m = p.ct_out + al(F * (d.n + 1) * d.Cout * 8);
     p.total = p.m + al(F * d.Cout * 4);
     return p;
@@ -129,20 +133,25 @@ int launch_batch(ensei_server *S, Batch &b) {
         Request &q = S->reqs[t];
         const Shape &sh = S->shapes[q.shape];
         const ensei_shape &d = sh.d;
-        const Parts pt = parts_of(d);
+        const Parts pt = parts_of(d, S->seeded);
         uint8_t *base = S->pool + q.off;
         uint32_t *x_hat = reinterpret_cast<uint32_t *>(base + pt.x_hat);
         uint64_t *ct_in = reinterpret_cast<uint64_t *>(base + pt.ct_in);
         uint64_t *ct_out = reinterpret_cast<uint64_t *>(base + pt.ct_out);
         rc = ensei_ntt2d(S->ctx, q.io.x, x_hat, d.Cin, d.H, d.W, st);
-        if (!rc) rc = ensei_encrypt(S->ctx, x_hat, q.io.s, q.io.e, 1, d.Cin, sh.F, d.n, q.io.seed_a, 0, ct_in, st);
+        if (!rc)
+            rc = S->seeded ? ensei_encrypt_seeded(S->ctx, x_hat, q.io.s, q.io.e, 1, d.Cin, sh.F, d.n, q.io.seed_a, 0,
+                                                  ct_in, st)
+                           : ensei_encrypt(S->ctx, x_hat, q.io.s, q.io.e, 1, d.Cin, sh.F, d.n, q.io.seed_a, 0, ct_in, st);
         HcLayer h;
         if (!rc)
             rc = homconv_problem(S->ctx, &h, ct_in, sh.w_pack, q.io.r, 1, d.Cin, d.Cout, sh.F, d.n, ct_out,
-                                 sh.wpack_bytes);
+                                 sh.wpack_bytes, S->seeded);
+        h.seed_a = S->seeded ? q.io.seed_a : 0;
+        h.idx0 = 0;
         // narrow and deep shapes run on their own kernels, the others share one launch
         const bool alone = !rc && (sh.narrow || homconv_deep_fits(h));
-        if (alone) rc = homconv_launch(S->ctx, &h, nullptr, 1, !sh.narrow, HcSchedule{0, 0}, st);
+        if (alone) rc = homconv_launch(S->ctx, &h, nullptr, 1, !sh.narrow, HcSchedule{0, 0}, st, S->seeded);
         if (rc) break;
         if (alone) continue;
         h.n_items = frag_items(d.Cin, true);
@@ -154,16 +163,16 @@ int launch_batch(ensei_server *S, Batch &b) {
         HcLayer *dtab = S->d_tables + (size_t)b.slot * S->max_batch;
         if (hipMemcpyAsync(dtab, tab, np * sizeof(HcLayer), hipMemcpyHostToDevice, st) != hipSuccess)
             rc = ENSEI_ERR_HIP;
-        if (!rc) rc = homconv_launch(S->ctx, tab, dtab, np, true, HcSchedule{0, 0}, st);
+        if (!rc) rc = homconv_launch(S->ctx, tab, dtab, np, true, HcSchedule{0, 0}, st, S->seeded);
     } else if (!rc && np == 1) {
-        rc = homconv_launch(S->ctx, tab, nullptr, 1, true, HcSchedule{0, 0}, st);
+        rc = homconv_launch(S->ctx, tab, nullptr, 1, true, HcSchedule{0, 0}, st, S->seeded);
     }
     for (uint64_t t : b.tickets) {
         if (rc) break;
         Request &q = S->reqs[t];
         const Shape &sh = S->shapes[q.shape];
         const ensei_shape &d = sh.d;
-        const Parts pt = parts_of(d);
+        const Parts pt = parts_of(d, S->seeded);
         uint8_t *base = S->pool + q.off;
         const uint64_t *ct_out = reinterpret_cast<const uint64_t *>(base + pt.ct_out);
         uint32_t *m = reinterpret_cast<uint32_t *>(base + pt.m);
@@ -287,7 +296,8 @@ size_t ensei_request_bytes(const ensei_shape *shape) {
     return parts_of(*shape).total;
 }
 
-int ensei_server_create(ensei_ctx *ctx, size_t budget_bytes, int nstreams, int max_batch, ensei_server **out) {
+static int server_create(ensei_ctx *ctx, size_t budget_bytes, int nstreams, int max_batch, ensei_server **out,
+                         bool seeded) {
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!out || budget_bytes == 0 || nstreams < 1 || nstreams > 8 || max_batch < 1 || max_batch > 256)
@@ -298,6 +308,7 @@ int ensei_server_create(ensei_ctx *ctx, size_t budget_bytes, int nstreams, int m
     (void)hipSetDevice(ctx->device);
     ensei_server *S = new ensei_server;
     S->ctx = ctx;
+    S->seeded = seeded;
     S->budget = (budget_bytes + kAlign - 1) / kAlign * kAlign;
     S->nstreams = nstreams;
     S->max_batch = max_batch;
@@ -331,6 +342,15 @@ int ensei_server_create(ensei_ctx *ctx, size_t budget_bytes, int nstreams, int m
     return ENSEI_OK;
 }
 
+int ensei_server_create(ensei_ctx *ctx, size_t budget_bytes, int nstreams, int max_batch, ensei_server **out) {
+    return server_create(ctx, budget_bytes, nstreams, max_batch, out, false);
+}
+
+int ensei_server_create_seeded(ensei_ctx *ctx, size_t budget_bytes, int nstreams, int max_batch,
+                               ensei_server **out) {
+    return server_create(ctx, budget_bytes, nstreams, max_batch, out, true);
+}
+
 int ensei_server_add_shape(ensei_server *S, const ensei_shape *shape, const int32_t *w, int *shape_id) {
     if (!S || !shape || !w || !shape_id) return ENSEI_ERR_ARG;
     const ensei_shape &d = *shape;
@@ -339,7 +359,7 @@ int ensei_server_add_shape(ensei_server *S, const ensei_shape *shape, const int3
     Shape sh;
     sh.d = d;
     sh.F = (int64_t)d.H * d.W;
-    sh.footprint = parts_of(d).total;
+    sh.footprint = parts_of(d, S->seeded).total;
     if (sh.footprint > S->budget) return ENSEI_ERR_LIMIT;
     sh.narrow = d.Cin <= kNarrowCin;
     sh.wpack_bytes = wpack_bytes_as(d.Cout, d.Cin, sh.F, !sh.narrow);

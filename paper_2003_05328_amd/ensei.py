@@ -65,6 +65,7 @@ SIGNATURES = {
     "ensei_plan_destroy": (_i32, [_vp]),
     "ensei_request_bytes": (C.c_size_t, [_vp]),
     "ensei_server_create": (_i32, [_vp, C.c_size_t, _i32, _i32, C.POINTER(_vp)]),
+    "ensei_server_create_seeded": (_i32, [_vp, C.c_size_t, _i32, _i32, C.POINTER(_vp)]),
     "ensei_server_add_shape": (_i32, [_vp, _vp, _vp, C.POINTER(_i32)]),
     "ensei_server_submit": (_i32, [_vp, _i32, _vp, C.POINTER(_u64)]),
     "ensei_server_poll": (_i32, [_vp, _u64, _vp]),
@@ -491,12 +492,15 @@ class Server:
 
     STATES = ("queued", "running", "done", "failed")
 
-    def __init__(self, ctx: "Context", budget_bytes: int, nstreams: int = 4, max_batch: int = 16):
+    def __init__(self, ctx: "Context", budget_bytes: int, nstreams: int = 4, max_batch: int = 16,
+                 seeded: bool = False):
+        """seeded: requests keep only the b words of their input ciphertexts
+        (ensei_server_create_seeded)."""
         self.ctx = ctx
         h = C.c_void_p()
+        name = "ensei_server_create_seeded" if seeded else "ensei_server_create"
         with torch.cuda.device(ctx.device):
-            _check(lib().ensei_server_create(ctx._h, int(budget_bytes), nstreams, max_batch, C.byref(h)),
-                   "ensei_server_create")
+            _check(getattr(lib(), name)(ctx._h, int(budget_bytes), nstreams, max_batch, C.byref(h)), name)
         self._h = h
         self._shapes = {}
         self._keep = {}  # ticket -> the request's tensors, kept alive until forget()

@@ -92,6 +92,29 @@ def test_mixed_requests_match_alone_under_a_tight_budget(ctx):
     server.close()
 
 
+def test_seeded_server_matches_alone(ctx):
+    """A server on seeded ciphertexts: every request gives exactly what the
+    unseeded single calls give, and its footprint leaves out the a-words."""
+    biggest = max(Server.request_bytes(S.H, S.W, S.Cin, S.Cout, S.kh, S.kw, S.n) for S in SHAPES)
+    budget = int(2.5 * biggest)
+    server = Server(ctx, budget, nstreams=3, max_batch=4, seeded=True)
+    shapes = _setup(ctx, server)
+    subs = []
+    for i in range(20):
+        S, sid, _, sets = shapes[i % len(shapes)]
+        t, s_a, s_b = _submit(server, S, sid, sets[i % len(sets)][1])
+        subs.append((t, S, sets[i % len(sets)], s_a, s_b))
+    for t, S, (inp, io, ref), s_a, s_b in subs:
+        server.wait(t)
+        assert server.poll(t)["state"] == "done"
+        assert np.array_equal(host(s_a), ref[0]) and np.array_equal(host(s_b), ref[1])
+        server.forget(t)
+    st = server.stats()
+    assert st["completed"] == 20 and st["failed"] == 0
+    assert 0 < st["peak_used_bytes"] <= budget
+    server.close()
+
+
 def test_shares_add_up_to_the_convolution(ctx):
     orc = oracle.default()
     server = Server(ctx, 1 << 30, nstreams=2, max_batch=8)
