@@ -268,8 +268,9 @@ int ensei_encrypt_seeded(ensei_ctx *ctx, const uint32_t *m, const int8_t *s, con
  * (q = (b*F + f)*Cin + i, as ensei_encrypt) and whose word n is
  * b_in[b][f][i]; b_in: uint64 [batch][F][Cin], 8-byte aligned.
  * w_pack, r, ct_out, limits and errors as ensei_homconv; the input side
- * moves 8 bytes per ciphertext instead of 8 (n+1). Runs the narrow-input
- * kernel for Cin <= 8 and the streaming matrix-core kernel otherwise. */
+ * moves 8 bytes per ciphertext instead of 8 (n+1). The kernel is chosen by
+ * shape as for ensei_homconv (narrow inputs, deep layers, or the streaming
+ * kernel), each in its seeded form. */
 int ensei_homconv_seeded(ensei_ctx *ctx, const uint64_t *b_in, uint64_t seed_a, uint64_t ct_index0,
                          const int8_t *w_pack, const uint32_t *r, int64_t batch, int Cin, int Cout, int64_t F, int n,
                          uint64_t *ct_out, void *stream);
