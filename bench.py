@@ -106,7 +106,8 @@ def homconv_layers(ctx, warm: int = 10, reps: int = 10):
     """HomConv alone on every distinct workload layer shape (random words: the
     kernels' cost does not depend on values), timed after `warm` launches as
     the mean of `reps`: the algorithmic HBM rate, and the i8 multiply-
-    accumulate rate (21 per word-MAC) against the dense matrix-core peak."""
+    accumulate rate (21 per word-MAC) against the dense matrix-core peak; and
+    the same layer's seeded HomConv time (b words in, a-words regenerated)."""
     import torch
     from paper_2003_05328_amd import configs
 
@@ -130,13 +131,24 @@ def homconv_layers(ctx, warm: int = 10, reps: int = 10):
         ev[1].record()
         torch.cuda.synchronize()
         us = ev[0].elapsed_time(ev[1]) * 1e3 / reps
+        # the same layer on seeded input (b words only, a-words regenerated)
+        bw = torch.empty((S.B, S.F, S.Cin), dtype=torch.int64, device=dv).random_().view(torch.uint64)
+        for _ in range(warm):
+            ctx.homconv_seeded(bw, S.n, 12345, pack, r, S.Cout, out=out)
+        ev[0].record()
+        for _ in range(reps):
+            ctx.homconv_seeded(bw, S.n, 12345, pack, r, S.Cout, out=out)
+        ev[1].record()
+        torch.cuda.synchronize()
+        us_seeded = ev[0].elapsed_time(ev[1]) * 1e3 / reps
         nbytes = homconv_bytes(S, int(pack.numel()))
         word_macs = S.B * S.Cout * S.Cin * S.F * (S.n + 1)
         i8 = 21 * word_macs / (us * 1e-6)
         rows.append({"layer": name, "us": us, "algorithmic_bytes": nbytes,
                      "hbm_gbs": nbytes / (us * 1e-6) / 1e9, "frac_hbm": nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
-                     "word_mac_per_byte": word_macs / nbytes, "i8_mac_per_s": i8, "frac_mfma": i8 / MFMA_I8_PEAK_MACS})
-        del ct, w, r, pack, out
+                     "word_mac_per_byte": word_macs / nbytes, "i8_mac_per_s": i8, "frac_mfma": i8 / MFMA_I8_PEAK_MACS,
+                     "seeded_us": us_seeded})
+        del ct, w, r, pack, out, bw
         torch.cuda.empty_cache()
     return rows
 
