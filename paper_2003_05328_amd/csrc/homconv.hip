@@ -1288,9 +1288,16 @@ bool homconv_deep_fits(const HcLayer &P) {
            deep_lds_bytes(P) <= (size_t)kLdsBytes / 2;
 }
 
+// Seeded input: the deep kernel generates a block's words once for all of its
+// row tiles (the streaming kernel once per row tile), so it takes every layer
+// with two or more row tiles.
+static bool deep_fits_seeded(const HcLayer &P) {
+    return P.Cin >= kPairedCin && P.n_ks <= kDeepMaxKs && P.n_ot >= 2 && deep_lds_bytes(P) <= (size_t)kLdsBytes / 2;
+}
+
 template <bool SEEDED>
 static int launch_deep(const ensei_ctx *ctx, const HcLayer &P, hipStream_t stream) {
-    if (!homconv_deep_fits(P)) return ENSEI_ERR_LIMIT;
+    if (!(SEEDED ? deep_fits_seeded(P) : homconv_deep_fits(P))) return ENSEI_ERR_LIMIT;
     const size_t lds = deep_lds_bytes(P);
     const bool wide = P.Cout % 2 == 0;
     auto kernel = wide ? homconv_deep_kernel<true, SEEDED> : homconv_deep_kernel<false, SEEDED>;
