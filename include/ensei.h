@@ -222,6 +222,13 @@ int ensei_decrypt(ensei_ctx *ctx, const uint64_t *ct, const int8_t *s, int64_t b
 int ensei_homrec(ensei_ctx *ctx, uint64_t *ct, const uint32_t *s_hat, int64_t batch, int C, int64_t F, int n,
                  void *stream);
 
+/* HomRec on seeded ciphertexts (ensei_encrypt_seeded): the same addition on
+ * the compact b words, b_words: uint64 [batch][F][C] (8-byte aligned), in
+ * place; the a-words stay implicit in (seed_a, ct_index0). Limits and errors
+ * as ensei_homrec. */
+int ensei_homrec_seeded(ensei_ctx *ctx, uint64_t *b_words, const uint32_t *s_hat, int64_t batch, int C, int64_t F,
+                        void *stream);
+
 /* A stand-in for the oblivious activation between the rounds of Fig. 2,
  * computed in the clear so that chained rounds can run on one device (the
  * garbled-circuit or triplet evaluation itself is outside this library):

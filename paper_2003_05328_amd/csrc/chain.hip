@@ -85,6 +85,22 @@ int ensei_homrec(ensei_ctx *ctx, uint64_t *ct, const uint32_t *s_hat, int64_t ba
     return launch_status();
 }
 
+int ensei_homrec_seeded(ensei_ctx *ctx, uint64_t *b_words, const uint32_t *s_hat, int64_t batch, int C, int64_t F,
+                        void *stream) {
+    int st = check_ctx(ctx);
+    if (st) return st;
+    if (!b_words || !s_hat || batch <= 0 || C <= 0 || F <= 0) return ENSEI_ERR_ARG;
+    if (C > ENSEI_MAX_COUT || batch > ((int64_t)1 << 40) / C / F) return ENSEI_ERR_LIMIT;
+    if (((uintptr_t)b_words & 7) || ((uintptr_t)s_hat & 3)) return ENSEI_ERR_ALIGN;
+    const size_t num = (size_t)batch * C * F;
+    if (overlaps(b_words, num * 8, s_hat, num * 4)) return ENSEI_ERR_OVERLAP;
+    // the compact b words are the word-major layout with no a-words (word n = 0)
+    const int64_t tiles = batch * ((C + kHrC - 1) / kHrC) * ((F + kHrF - 1) / kHrF);
+    hipLaunchKernelGGL(homrec_kernel, dim3((unsigned)(tiles < 65536 ? tiles : 65536)), dim3(kHrThreads), 0,
+                       (hipStream_t)stream, b_words, s_hat, batch, C, F, 0, ctx->delta);
+    return launch_status();
+}
+
 int ensei_reshare(ensei_ctx *ctx, const uint32_t *s_a, const uint32_t *s_b, const uint32_t *s_b_next, int64_t count,
                   int act, uint32_t *s_a_next, void *stream) {
     int st = check_ctx(ctx);

@@ -57,6 +57,7 @@ SIGNATURES = {
     "ensei_homconv_valu": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
     "ensei_decrypt": (_i32, [_vp, _vp, _vp, _i64, _i32, _i64, _i32, _vp, _vp]),
     "ensei_homrec": (_i32, [_vp, _vp, _vp, _i64, _i32, _i64, _i32, _vp]),
+    "ensei_homrec_seeded": (_i32, [_vp, _vp, _vp, _i64, _i32, _i64, _vp]),
     "ensei_reshare": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _vp, _vp]),
     "ensei_plan_create": (_i32, [_vp, _vp, _i32, C.c_char_p, C.POINTER(_vp)]),
     "ensei_plan_create_seeded": (_i32, [_vp, _vp, _i32, C.c_char_p, C.POINTER(_vp)]),
@@ -341,6 +342,17 @@ class Context:
             raise ValueError(f"s_hat must be [B][C][F] = {(B, Cc, F)}")
         self._call("ensei_homrec", _ptr(ct), _ptr(s_hat), B, Cc, F, n1 - 1)
         return ct
+
+    def homrec_seeded(self, b_words, s_hat) -> torch.Tensor:
+        """In place: seeded ciphertexts' b words uint64 [B][F][C] gain
+        Delta * s_hat[b][c][f] (ensei_homrec_seeded); returns b_words."""
+        self._dev(b_words, "b_words", torch.uint64)
+        self._dev(s_hat, "s_hat", torch.uint32)
+        B, F, Cc = tuple(b_words.shape)
+        if tuple(s_hat.shape) != (B, Cc, F):
+            raise ValueError(f"s_hat must be [B][C][F] = {(B, Cc, F)}")
+        self._call("ensei_homrec_seeded", _ptr(b_words), _ptr(s_hat), B, Cc, F)
+        return b_words
 
     def reshare(self, s_a, s_b, s_b_next, act: int, out=None) -> torch.Tensor:
         """The activation stand-in: f((s_a + s_b) mod p) - s_b_next mod p,

@@ -112,6 +112,44 @@ def test_two_chained_rounds(ctx, orc, k, act):
     assert np.array_equal(got.reshape(want.shape), want)
 
 
+@pytest.mark.parametrize("B,F,C", [(1, 1, 1), (2, 5, 64), (1, 3, 7), (3, 64, 130), (2, 100, 70)])
+def test_homrec_seeded(ctx, orc, B, F, C):
+    """HomRec on the compact b words of seeded ciphertexts: the oracle's HomRec
+    on the layout with no a-words."""
+    bw = synth.uniform_u64(150 + C, (B, F, C))
+    s_hat = synth.uniform_u32(151 + C, (B, C, F), P)
+    bw[0, 0, 0] = 2**64 - 1
+    s_hat.flat[0] = P - 1
+    ref = orc.homrec(bw.reshape(B, F, 1, C), s_hat, P).reshape(B, F, C)
+    t = dev(bw)
+    assert ctx.homrec_seeded(t, dev(s_hat)) is t
+    assert np.array_equal(host(t), ref)
+
+
+@pytest.mark.parametrize("act", [0, 1])
+def test_seeded_second_round(ctx, orc, act):
+    """Round 1 on seeded ciphertexts (Enc keeps the b words, HomRec adds the
+    server's share to them, HomConv regenerates the a-words) gives exactly the
+    output ciphertexts and plaintexts of the unseeded round."""
+    S0, S1 = CHAINS[1]
+    inp1 = synth.generate(S1, P, 95 + act)
+    s_a1 = dev(synth.uniform_u32(96, (S1.B, S1.Cin, S1.H, S1.W), P))
+    s_b1 = dev(synth.uniform_u32(97, (S1.B, S1.Cin, S1.H, S1.W), P))
+    s1, e1, r1 = dev(inp1.s), dev(inp1.e.reshape(S1.B, S1.Cin, S1.F)), dev(inp1.r)
+    x_hat, sb_hat = ctx.ntt2d(s_a1), ctx.ntt2d(s_b1)
+    pack = ctx.pack_weights(ctx.weight_prep(dev(inp1.w), S1.H, S1.W))
+    ct = ctx.homrec(ctx.encrypt(x_hat, s1, e1, inp1.seed_a), sb_hat)
+    out = ctx.homconv(ct, pack, r1, S1.Cout)
+    bw = ctx.homrec_seeded(ctx.encrypt_seeded(x_hat, s1, e1, inp1.seed_a), sb_hat)
+    out_s = ctx.homconv_seeded(bw, S1.n, inp1.seed_a, pack, r1, S1.Cout)
+    assert np.array_equal(host(bw), host(ct)[:, :, S1.n, :])
+    assert np.array_equal(host(out_s), host(out))
+    m = host(ctx.decrypt(out_s, s1)).astype(np.int64)
+    u_hat = (host(x_hat).astype(np.int64) + host(sb_hat)) % P
+    w_hat = orc.weight_prep(inp1.w, S1.H, S1.W, P).astype(np.int64)
+    assert np.array_equal(m, (np.einsum("oif,bif->bof", w_hat, u_hat) + inp1.r) % P)
+
+
 def test_chain_argument_errors(ctx):
     ct = torch.zeros((1, 2, 5, 3), dtype=torch.uint64, device="cuda:0")
     s_hat = torch.zeros((1, 3, 2), dtype=torch.uint32, device="cuda:0")
@@ -125,6 +163,11 @@ def test_chain_argument_errors(ctx):
     assert L.ensei_homrec(h, _ptr(ct), None, 1, 3, 2, 4, st) == -1
     assert L.ensei_homrec(h, _ptr(ct), _ptr(ct), 1, 3, 2, 4, st) == -5  # share inside the ciphertexts
     assert L.ensei_homrec(h, _ptr(ct), _ptr(s_hat), 1 << 40, 3, 2, 4, st) == -6  # beyond 2^40 ciphertexts
+    bw = torch.zeros((1, 2, 3), dtype=torch.uint64, device="cuda:0")
+    assert L.ensei_homrec_seeded(h, None, _ptr(s_hat), 1, 3, 2, st) == -1
+    assert L.ensei_homrec_seeded(h, _ptr(bw), _ptr(bw), 1, 3, 2, st) == -5  # share inside the b words
+    with pytest.raises(ValueError):
+        ctx.homrec_seeded(bw, torch.zeros((1, 2, 3), dtype=torch.uint32, device="cuda:0"))
     v = torch.zeros(8, dtype=torch.uint32, device="cuda:0")
     with pytest.raises(EnseiError, match="ARG"):
         ctx.reshare(v, v, v, 2)
