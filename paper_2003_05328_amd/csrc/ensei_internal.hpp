@@ -131,7 +131,7 @@ int homconv_problem(const ensei_ctx *ctx, HcLayer *P, const uint64_t *ct_in, con
                     bool seeded = false);
 // Whether a single problem (paired fragments) runs on the deep-layer kernel;
 // batched launches keep such layers out of the multi-problem table.
-bool homconv_deep_fits(const HcLayer &P);
+bool homconv_deep_fits(const HcLayer &P, bool seeded = false);
 // Launches the matrix-core HomConv over problems[0..nlayers) (host copies;
 // dev_table holds the same array in device memory when nlayers > 1).
 // seeded: the problems' inputs are seeded (b_in, seed_a, idx0)

@@ -1281,13 +1281,6 @@ static int launch_narrow(const ensei_ctx *ctx, const HcLayer &P, HcSchedule sche
 constexpr int kLdsBytes = 160 * 1024;
 static size_t deep_lds_bytes(const HcLayer &P) { return (size_t)P.n_ks * 8 * kDeepPlane + (size_t)P.n_ot * 64 * 4; }
 
-bool homconv_deep_fits(const HcLayer &P) {
-    // all K steps of a block in half the LDS, several row tiles, and at least
-    // four (row tile, K step) phases per block to share the conversion
-    return P.Cin >= kPairedCin && P.n_ks <= kDeepMaxKs && P.n_ot >= 2 && P.n_ot * P.n_ks >= 4 &&
-           deep_lds_bytes(P) <= (size_t)kLdsBytes / 2;
-}
-
 // Seeded input: the deep kernel generates a block's words once for all of its
 // row tiles (the streaming kernel once per row tile), so it takes every layer
 // with two or more row tiles.
@@ -1295,9 +1288,17 @@ static bool deep_fits_seeded(const HcLayer &P) {
     return P.Cin >= kPairedCin && P.n_ks <= kDeepMaxKs && P.n_ot >= 2 && deep_lds_bytes(P) <= (size_t)kLdsBytes / 2;
 }
 
+bool homconv_deep_fits(const HcLayer &P, bool seeded) {
+    if (seeded) return deep_fits_seeded(P);
+    // all K steps of a block in half the LDS, several row tiles, and at least
+    // four (row tile, K step) phases per block to share the conversion
+    return P.Cin >= kPairedCin && P.n_ks <= kDeepMaxKs && P.n_ot >= 2 && P.n_ot * P.n_ks >= 4 &&
+           deep_lds_bytes(P) <= (size_t)kLdsBytes / 2;
+}
+
 template <bool SEEDED>
 static int launch_deep(const ensei_ctx *ctx, const HcLayer &P, hipStream_t stream) {
-    if (!(SEEDED ? deep_fits_seeded(P) : homconv_deep_fits(P))) return ENSEI_ERR_LIMIT;
+    if (!homconv_deep_fits(P, SEEDED)) return ENSEI_ERR_LIMIT;
     const size_t lds = deep_lds_bytes(P);
     const bool wide = P.Cout % 2 == 0;
     auto kernel = wide ? homconv_deep_kernel<true, SEEDED> : homconv_deep_kernel<false, SEEDED>;

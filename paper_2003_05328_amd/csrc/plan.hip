@@ -210,7 +210,7 @@ int plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const ch
             release(P);
             return rc;
         }
-        if (narrow || homconv_deep_fits(h)) {
+        if (narrow || homconv_deep_fits(h, seeded)) {
             P->single.emplace_back(h, !narrow);
             continue;
         }

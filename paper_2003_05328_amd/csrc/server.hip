@@ -150,7 +150,7 @@ int launch_batch(ensei_server *S, Batch &b) {
         h.seed_a = S->seeded ? q.io.seed_a : 0;
         h.idx0 = 0;
         // narrow and deep shapes run on their own kernels, the others share one launch
-        const bool alone = !rc && (sh.narrow || homconv_deep_fits(h));
+        const bool alone = !rc && (sh.narrow || homconv_deep_fits(h, S->seeded));
         if (alone) rc = homconv_launch(S->ctx, &h, nullptr, 1, !sh.narrow, HcSchedule{0, 0}, st, S->seeded);
         if (rc) break;
         if (alone) continue;
