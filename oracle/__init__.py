@@ -12,6 +12,7 @@ conventions and the paper passages they restate).
 from __future__ import annotations
 
 import ctypes as C
+import importlib
 import os
 from decimal import ROUND_FLOOR, Decimal, localcontext
 
@@ -60,9 +61,9 @@ class Oracle:
 
     def __init__(self, lib_path: str = _LIB_PATH):
         if lib_path == _LIB_PATH and not os.path.exists(lib_path):
-            from . import build as _b
-
-            _b.build()
+            # import the submodule by name: ``from . import build`` would first
+            # look the name up through this module's __getattr__
+            importlib.import_module(__name__ + ".build").build()
         lib = C.CDLL(lib_path)
         for name, (res, args) in _SIG.items():
             f = getattr(lib, name)

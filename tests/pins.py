@@ -445,6 +445,25 @@ def check_seeded(orc):
     assert np.array_equal(orc.decrypt(out, s, P).astype(np.int64), want)
 
 
+def check_cdt_exact(orc):
+    """The sampler's thresholds exactly: T[k] = floor(2^48 erf((k + 1/2) /
+    (sigma sqrt 2))) for every k < 32, with erf from mpmath at 60 digits (an
+    implementation independent of the oracle's decimal series). Every
+    2^48 erf value checked lies at least 1e-30 from an integer, so the floor
+    taken at this precision is certain."""
+    import mpmath
+
+    T = oracle.cdt_table()
+    assert len(T) == oracle.CDT_SIZE
+    with mpmath.workdps(60):
+        sigma = mpmath.mpf(oracle.SIGMA_NUM) / oracle.SIGMA_DEN
+        for k, t in enumerate(T):
+            v = mpmath.ldexp(mpmath.erf((k + mpmath.mpf(1) / 2) / (sigma * mpmath.sqrt(2))), oracle.CDT_BITS)
+            fl = int(mpmath.floor(v))
+            assert mpmath.mpf(10) ** -30 < v - fl < 1 - mpmath.mpf(10) ** -30, k
+            assert t == fl, (k, t, fl)
+
+
 def check_noise_sampler(orc):
     """The rounded-Gaussian error sampler (sigma 3.2): its thresholds against
     the library erf, its draws against a stateful big-int generator and a
@@ -504,5 +523,6 @@ ALL_CHECKS = [
     check_reshare,
     check_chained_rounds,
     check_seeded,
+    check_cdt_exact,
     check_noise_sampler,
 ]

@@ -4,17 +4,22 @@ Each mutant is a copy of ``oracle/ensei_oracle.c`` with one plausible bug
 (a dropped term, a wrong sign, a wrong index, a transposed operand, a missing
 reduction) compiled into a temporary library. The test asserts that at least
 one pin of ``tests/pins.py`` fails on it, so the pins constrain every part of
-the oracle rather than only its own restatement.
+the oracle rather than only its own restatement. The Python part of the oracle
+(the error sampler's thresholds, ``oracle.cdt_table``) gets the same treatment:
+a mutated copy of the function replaces it while the pins run.
 """
 import os
 import subprocess
+import textwrap
 
 import pytest
 
 import oracle
 from tests import pins
 
-SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "ensei_oracle.c")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "ensei_oracle.c")
+PY_SRC = os.path.join(ROOT, "oracle", "__init__.py")
 
 MUTANTS = {
     "root_not_inverted": ("return inverse ? powmod(w, p - 2, p) : w;", "return w;"),
@@ -80,6 +85,43 @@ def _build(tmp_path, name, old, new):
 def test_mutant_is_caught(tmp_path, name):
     old, new = MUTANTS[name]
     orc = _build(tmp_path, name, old, new)
+    caught_by = None
+    for check in pins.ALL_CHECKS:
+        try:
+            check(orc)
+        except (AssertionError, ValueError, IndexError, OverflowError):
+            caught_by = check.__name__
+            break
+    assert caught_by, f"planted mistake {name!r} passed every pin"
+
+
+# Planted mistakes in the Python threshold table of the rounded-Gaussian
+# sampler: rounding instead of the floor, the half-integer edge dropped, the
+# sqrt(2) of the Gaussian's erf dropped, too little working precision.
+PY_MUTANTS = {
+    "cdt_rounds_not_floors": ("rounding=ROUND_FLOOR", 'rounding="ROUND_HALF_EVEN"'),
+    "cdt_edge_not_half_integer": ("x = (Decimal(k) + Decimal(1) / 2) /", "x = Decimal(k) /"),
+    "cdt_sigma_without_sqrt2": ("/ (sigma * Decimal(2).sqrt())", "/ sigma"),
+    "cdt_low_precision": ("prec = 80", "prec = 12"),
+}
+
+
+def _mutated_cdt_table(old, new):
+    src = open(PY_SRC).read()
+    start = src.index("def cdt_table()")
+    end = src.index("\ndef ", start + 1)
+    fn = src[start:end]
+    assert fn.count(old) == 1, f"mutation site {old!r} not found"
+    ns = dict(vars(oracle))
+    exec(textwrap.dedent(fn.replace(old, new)), ns)
+    return ns["cdt_table"]
+
+
+@pytest.mark.parametrize("name", sorted(PY_MUTANTS))
+def test_python_mutant_is_caught(monkeypatch, name):
+    old, new = PY_MUTANTS[name]
+    monkeypatch.setattr(oracle, "cdt_table", _mutated_cdt_table(old, new))
+    orc = oracle.default()
     caught_by = None
     for check in pins.ALL_CHECKS:
         try:
