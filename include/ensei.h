@@ -56,7 +56,10 @@ enum ensei_status {
     ENSEI_ERR_LIMIT = -6,   /* size beyond the supported range (see each call) */
     ENSEI_ERR_DEVICE = -7,  /* current HIP device is not the context's device */
     ENSEI_ERR_HIP = -8,     /* HIP runtime error (allocation at create, launch failure) */
-    ENSEI_ERR_TIMEOUT = -9  /* a wait ended before the request finished (serving) */
+    ENSEI_ERR_TIMEOUT = -9, /* a wait ended before the request finished (serving) */
+    ENSEI_ERR_BUDGET = -10, /* a request does not fit the server's budget or queue limit (serving) */
+    ENSEI_ERR_CANCELLED = -11, /* the request was cancelled (serving) */
+    ENSEI_ERR_STATE = -12   /* the request has already finished (serving) */
 };
 
 /* Largest supported sizes. */
@@ -84,7 +87,9 @@ int ensei_ctx_destroy(ensei_ctx *ctx);
 /* Static human-readable text for a status code. */
 const char *ensei_status_str(int status);
 
-/* The context's p, Delta = floor(2^64/p) and largest usable transform size. */
+/* The context's p, Delta = floor(2^64/p), largest usable transform size and
+ * HIP device (-1 for a NULL context). */
+int ensei_ctx_device(const ensei_ctx *ctx);
 uint32_t ensei_ctx_modulus(const ensei_ctx *ctx);
 uint64_t ensei_ctx_delta(const ensei_ctx *ctx);
 int ensei_ctx_max_dim(const ensei_ctx *ctx);
@@ -191,12 +196,6 @@ int ensei_encrypt(ensei_ctx *ctx, const uint32_t *m, const int8_t *s, const int3
  * are the same bits. */
 int ensei_homconv(ensei_ctx *ctx, const uint64_t *ct_in, const int8_t *w_pack, const uint32_t *r, int64_t batch,
                   int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, void *stream);
-
-/* The same HomConv computed with 64-bit vector-ALU multiply-adds straight
- * from w_hat: uint32 [Cout][Cin][F] (values < p). Bit-identical results;
- * kept as the vector-ALU comparison point for the matrix-core kernel. */
-int ensei_homconv_valu(ensei_ctx *ctx, const uint64_t *ct_in, const uint32_t *w_hat, const uint32_t *r,
-                       int64_t batch, int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, void *stream);
 
 /* ------------------------------------------------------------------ Dec --
  * Decryption with round-half-up (Sec. 3.1, "round off the fractions"):
@@ -347,6 +346,8 @@ typedef struct ensei_schedule {
     int from_cache;
     int64_t chunk;
     double homconv_us;
+    int shared_layers;   /* layers in the shared persistent launch */
+    int own_layers;      /* layers on a HomConv kernel of their own (narrow inputs, deep layers) */
 } ensei_schedule;
 
 /* Creates a plan for nlayers (1..ENSEI_MAX_PLAN_LAYERS) layers. Allocates the
@@ -354,7 +355,8 @@ typedef struct ensei_schedule {
  * device (freed by ensei_plan_destroy), runs the filters' preparation, tunes
  * the schedule, runs the whole stack once eagerly (so every argument check of
  * the single calls applies and is reported here) and captures the graph.
- * Synchronous. Errors: those of the single calls, ENSEI_ERR_LIMIT for too
+ * Synchronous; it first waits for every piece of work already queued on the
+ * device, so the layers' inputs may come from pending work on any stream. Errors: those of the single calls, ENSEI_ERR_LIMIT for too
  * many layers, ENSEI_ERR_HIP for allocation or capture failures. */
 #define ENSEI_MAX_PLAN_LAYERS 64
 int ensei_plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const char *tune_cache,
@@ -370,6 +372,14 @@ int ensei_plan_create_seeded(ensei_ctx *ctx, const ensei_layer *layers, int nlay
 
 /* Enqueues one run of the captured graph on `stream` (asynchronous). */
 int ensei_plan_run(ensei_plan *plan, void *stream);
+
+/* Enqueues one stage of a run, each captured as a graph of its own: 0 the
+ * client's NTT2D and Enc of every layer, 1 the server's HomConv of every
+ * layer (the shared persistent launch and the layers' own kernels), 2 Dec,
+ * INTT2D and the server's share of every layer. Stages 0, 1, 2 in that order
+ * on one stream are one ensei_plan_run (the two parties' steps can so be
+ * enqueued, and timed, separately). ENSEI_ERR_ARG for another stage. */
+int ensei_plan_run_stage(ensei_plan *plan, int stage, void *stream);
 
 /* The schedule the plan runs (see ensei_schedule). */
 int ensei_plan_schedule(const ensei_plan *plan, ensei_schedule *out);
@@ -397,8 +407,9 @@ int ensei_plan_destroy(ensei_plan *plan);
  * ensei_server_add_shape. A request's inputs and outputs are the caller's
  * device buffers: x [Cin][H][W] residues < p, s [n] ternary, e [Cin][F]
  * int32, r [Cout][F] masks < p, and the written shares s_a, s_b
- * [Cout][H][W]; inputs must be complete when the request is submitted and
- * every buffer must stay valid until the request is done. Word j of
+ * [Cout][H][W]; the inputs must be complete in the order of the request's
+ * `stream` and every buffer must stay valid
+ * until the request has finished (done, failed or cancelled). Word j of
  * ciphertext (c, f) is keyed by seed_a and q = f*Cin + c, as ensei_encrypt
  * with one image and ct_index0 = 0.
  *
@@ -419,9 +430,14 @@ typedef struct ensei_request {
     uint64_t seed_a;
     uint32_t *s_a;
     uint32_t *s_b;
+    /* The hipStream_t (as void*; NULL = the null stream) whose queued work
+     * produces x, s, e and r: the request's kernels start only after the
+     * work queued on it before the submit (an event recorded there). */
+    void *stream;
 } ensei_request;
 
-/* state: 0 queued, 1 running, 2 done, 3 failed (status holds the error). */
+/* state: 0 queued, 1 running, 2 done, 3 failed (status holds the error),
+ * 4 cancelled (status ENSEI_ERR_CANCELLED). */
 typedef struct ensei_request_info {
     int state;
     int status;
@@ -431,6 +447,7 @@ typedef struct ensei_request_info {
 typedef struct ensei_server_info {
     uint64_t budget_bytes, used_bytes, peak_used_bytes;
     uint64_t queued, inflight_batches, completed, failed, batches;
+    uint64_t cancelled, refused; /* cancel calls that took effect; submits refused with ENSEI_ERR_BUDGET */
 } ensei_server_info;
 
 /* Device bytes of one request of this shape inside the budget (0 if invalid). */
@@ -448,18 +465,41 @@ int ensei_server_create_seeded(ensei_ctx *ctx, size_t budget_bytes, int nstreams
                                ensei_server **out);
 
 /* Registers a shape with the server's filters w [Cout][Cin][kh][kw] int32
- * (read once, synchronously). ENSEI_ERR_LIMIT if one request of the shape
- * does not fit the budget; the single calls' shape errors otherwise. */
+ * (read once, synchronously, after every piece of work already queued on the
+ * device has finished, so w may come from pending work on any stream).
+ * ENSEI_ERR_BUDGET if one request of the shape does not fit the budget; the
+ * single calls' shape errors otherwise. */
 int ensei_server_add_shape(ensei_server *server, const ensei_shape *shape, const int32_t *w, int *shape_id);
 
-/* Queues one request; returns at once with its ticket. */
+/* Queues one request; returns at once with its ticket. Its arrival time is
+ * taken before the call waits for the server's lock. ENSEI_ERR_BUDGET (and
+ * nothing queued) if its footprint exceeds the budget, or if the footprints
+ * of the requests waiting for admission would exceed the queue limit. */
 int ensei_server_submit(ensei_server *server, int shape_id, const ensei_request *req, uint64_t *ticket);
+
+/* Cancels a request (paper Fig. 2: the client may abandon a round). A queued
+ * request leaves the queue at once: it never takes budget or device time,
+ * and requests behind it may be admitted in its place. A running request's
+ * device work cannot be recalled: it is marked, its budget returns when its
+ * batch has finished, and it is then reported cancelled (its output shares
+ * may or may not have been written). Other requests are not affected. Returns
+ * ENSEI_OK, ENSEI_ERR_ARG for an unknown ticket, ENSEI_ERR_STATE if the
+ * request has already finished. */
+int ensei_server_cancel(ensei_server *server, uint64_t ticket);
+
+/* Caps the bytes of requests waiting for admission (0 = no cap, the
+ * default); a submit past the cap returns ENSEI_ERR_BUDGET. */
+int ensei_server_set_queue_limit(ensei_server *server, size_t bytes);
+
+/* The server's clock: seconds since it was created (the time base of
+ * ensei_request_info). */
+int ensei_server_clock(ensei_server *server, double *now);
 
 /* The request's state and times (ENSEI_ERR_ARG for an unknown ticket). */
 int ensei_server_poll(ensei_server *server, uint64_t ticket, ensei_request_info *info);
 
-/* Blocks until the request is done (timeout_ms < 0: no limit); returns its
- * status, or ENSEI_ERR_TIMEOUT. */
+/* Blocks until the request has finished (timeout_ms < 0: no limit); returns
+ * its status (ENSEI_ERR_CANCELLED for a cancelled one), or ENSEI_ERR_TIMEOUT. */
 int ensei_server_wait(ensei_server *server, uint64_t ticket, int timeout_ms);
 
 /* Drops a finished request's record (ENSEI_ERR_ARG if unknown or not done). */

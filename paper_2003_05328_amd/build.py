@@ -13,6 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libensei.so")
+# comparison kernels (csrc/bench/), linked against libensei.so; never loaded by the product path
+BENCH_LIB = os.path.join(HERE, "libensei_bench.so")
 ROOT = os.path.dirname(HERE)
 
 ARCH = "gfx950"
@@ -34,6 +36,11 @@ FLAGS = [
 
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
+
+
+def bench_sources():
+    d = os.path.join(CSRC, "bench")
+    return sorted(os.path.join(d, f) for f in os.listdir(d) if f.endswith(".hip"))
 
 
 def _compile(src: str, verbose: bool) -> str:
@@ -59,6 +66,15 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    bsrcs = bench_sources()
+    with cf.ThreadPoolExecutor(max_workers=min(jobs, len(bsrcs))) as ex:
+        bobjs = list(ex.map(lambda s: _compile(s, verbose), bsrcs))
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *bobjs, f"-L{HERE}", "-lensei",
+           "-Wl,-rpath,$ORIGIN", "-o", BENCH_LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(BENCH_LIB + ".tmp", BENCH_LIB)
     return LIB
 
 

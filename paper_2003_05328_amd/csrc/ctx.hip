@@ -87,6 +87,9 @@ const char *ensei_status_str(int s) {
         case ENSEI_ERR_DEVICE: return "current HIP device is not the context's device";
         case ENSEI_ERR_HIP: return "HIP runtime error";
         case ENSEI_ERR_TIMEOUT: return "timed out before the request finished";
+        case ENSEI_ERR_BUDGET: return "request does not fit the server's budget or queue limit";
+        case ENSEI_ERR_CANCELLED: return "request was cancelled";
+        case ENSEI_ERR_STATE: return "request has already finished";
         default: return "unknown status";
     }
 }
@@ -176,6 +179,7 @@ int ensei_error_table(const ensei_ctx *ctx, uint64_t *out, int n) {
     return kCdtSize;
 }
 
+int ensei_ctx_device(const ensei_ctx *ctx) { return ctx ? ctx->device : -1; }
 uint32_t ensei_ctx_modulus(const ensei_ctx *ctx) { return ctx ? ctx->p : 0; }
 uint64_t ensei_ctx_delta(const ensei_ctx *ctx) { return ctx ? ctx->delta : 0; }
 int ensei_ctx_max_dim(const ensei_ctx *ctx) { return ctx ? (1 << ctx->max_log) : 0; }

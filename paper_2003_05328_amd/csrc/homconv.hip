@@ -1132,50 +1132,6 @@ __global__ __launch_bounds__(kPackThreads) void pack_weights_kernel(const uint32
     }
 }
 
-// Vector-ALU HomConv: one thread per word index j of one (b, f), TO
-// consecutive rows o in registers; the thread walks the Cin contiguous input
-// words of its j, and W^[o][i][f] is uniform across the workgroup (scalar
-// loads). Each word-MAC is a 32 x 32 -> 64-bit multiply-add plus a low 32-bit
-// multiply for the high half.
-template <int TO>
-__global__ __launch_bounds__(256) void homconv_valu_kernel(const uint64_t *__restrict__ ct_in,
-                                                           const uint32_t *__restrict__ w_hat,
-                                                           const uint32_t *__restrict__ r, int Cin, int Cout,
-                                                           int64_t F, int n, uint64_t delta,
-                                                           uint64_t *__restrict__ ct_out, int n_jb, int n_ot) {
-    int64_t t = blockIdx.x;
-    const int jb = (int)(t % n_jb);
-    t /= n_jb;
-    const int ot = (int)(t % n_ot);
-    t /= n_ot;
-    const int64_t f = t % F, b = t / F;
-    const int j = jb * 256 + threadIdx.x;
-    if (j > n) return;
-    const int o0 = ot * TO;
-    const int64_t rowlen = (int64_t)n + 1;
-    uint64_t acc[TO];
-#pragma unroll
-    for (int k = 0; k < TO; ++k) acc[k] = 0;
-    const uint64_t *src = ct_in + ((b * F + f) * rowlen + j) * Cin;
-    for (int i = 0; i < Cin; ++i) {
-        const uint64_t c = src[i];
-#pragma unroll
-        for (int k = 0; k < TO; ++k) {
-            const int o = o0 + k < Cout ? o0 + k : Cout - 1;
-            acc[k] += (uint64_t)w_hat[((int64_t)o * Cin + i) * F + f] * c;
-        }
-    }
-    uint64_t *dst = ct_out + ((b * F + f) * rowlen + j) * Cout;
-#pragma unroll
-    for (int k = 0; k < TO; ++k) {
-        const int o = o0 + k;
-        if (o >= Cout) break;
-        uint64_t v = acc[k];
-        if (j == n) v += delta * (uint64_t)r[(b * Cout + o) * F + f];
-        dst[o] = v;
-    }
-}
-
 int homconv_sizes(int64_t batch, int Cin, int Cout, int64_t F, int n) {
     if (batch <= 0 || Cin <= 0 || Cout <= 0 || F <= 0 || n <= 0) return ENSEI_ERR_ARG;
     if (Cin > ENSEI_MAX_CIN || Cout > ENSEI_MAX_COUT || n > ENSEI_MAX_LWE_N || F > (1 << 20)) return ENSEI_ERR_LIMIT;
@@ -1408,20 +1364,6 @@ int ensei_homconv_seeded(ensei_ctx *ctx, const uint64_t *b_in, uint64_t seed_a, 
     P.seed_a = seed_a;
     P.idx0 = ct_index0;
     return homconv_launch(ctx, &P, nullptr, 1, Cin >= kPairedCin, HcSchedule{0, 0}, (hipStream_t)stream, true);
-}
-
-int ensei_homconv_valu(ensei_ctx *ctx, const uint64_t *ct_in, const uint32_t *w_hat, const uint32_t *r,
-                       int64_t batch, int Cin, int Cout, int64_t F, int n, uint64_t *ct_out, void *stream) {
-    int st = check_homconv(ctx, ct_in, w_hat, r, batch, Cin, Cout, F, n, ct_out, (size_t)Cout * Cin * F * 4);
-    if (st) return st;
-    if ((uintptr_t)w_hat & 3) return ENSEI_ERR_ALIGN;
-    constexpr int TO = 16;
-    const int n_ot = (Cout + TO - 1) / TO, n_jb = (n + 1 + 255) / 256;
-    const int64_t blocks = batch * F * n_ot * n_jb;
-    if (blocks > 0x7fffffff) return ENSEI_ERR_LIMIT;
-    hipLaunchKernelGGL(homconv_valu_kernel<TO>, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, ct_in,
-                       w_hat, r, Cin, Cout, F, n, ctx->delta, ct_out, n_jb, n_ot);
-    return launch_status();
 }
 
 }  // extern "C"

@@ -23,6 +23,9 @@ struct ensei_plan {
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // the same work as three graphs, one per stage (ensei_plan_run_stage)
+    hipGraph_t stage_graph[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t stage_exec[3] = {nullptr, nullptr, nullptr};
     ensei::HcSchedule sched{0, 0};
     ensei_schedule info{};
     // seeded ciphertexts: each layer's ct_in holds only the b words,
@@ -46,6 +49,10 @@ void release(ensei_plan *P) {
     if (P->stream) (void)hipStreamSynchronize(P->stream);  // setup work may still read the buffers
     if (P->exec) (void)hipGraphExecDestroy(P->exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
+    for (int k = 0; k < 3; ++k) {
+        if (P->stage_exec[k]) (void)hipGraphExecDestroy(P->stage_exec[k]);
+        if (P->stage_graph[k]) (void)hipGraphDestroy(P->stage_graph[k]);
+    }
     for (auto *q : P->w_hat) (void)hipFree(q);
     for (auto *q : P->w_pack) (void)hipFree(q);
     if (P->d_table) (void)hipFree(P->d_table);
@@ -160,6 +167,25 @@ int time_schedule(ensei_plan *P, HcSchedule s, double *us) {
     return rc;
 }
 
+// Captures stage k of the plan (0 client front, 1 HomConv, 2 back; -1 all
+// three in order) as a graph and instantiates it.
+int capture(ensei_plan *P, int k, hipGraph_t *graph, hipGraphExec_t *exec) {
+    if (hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return ENSEI_ERR_HIP;
+    int rc = ENSEI_OK;
+    if (k < 0 || k == 0) rc = run_front(P, P->stream);
+    if (!rc && (k < 0 || k == 1)) rc = run_homconv(P, P->sched, P->stream);
+    if (!rc && (k < 0 || k == 2)) rc = run_back(P, P->stream);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(P->stream, &g);
+    *graph = g;
+    if (!rc && (ec != hipSuccess || !g)) rc = ENSEI_ERR_HIP;
+    if (!rc && hipGraphInstantiate(exec, g, nullptr, nullptr, 0) != hipSuccess) {
+        *exec = nullptr;
+        rc = ENSEI_ERR_HIP;
+    }
+    return rc;
+}
+
 // Creates a plan (ensei_plan_create, ensei_plan_create_seeded).
 int plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const char *tune_cache, ensei_plan **out,
                 bool seeded) {
@@ -169,6 +195,9 @@ int plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const ch
     if (nlayers > ENSEI_MAX_PLAN_LAYERS) return ENSEI_ERR_LIMIT;
     *out = nullptr;
     DeviceGuard guard(ctx->device);
+    // the layers' buffers are read on the plan's own stream: let pending work
+    // of every stream (the caller's included) finish first
+    if (hipDeviceSynchronize() != hipSuccess) return ENSEI_ERR_HIP;
     ensei_plan *P = new ensei_plan;
     P->ctx = ctx;
     P->seeded = seeded;
@@ -278,23 +307,12 @@ int plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const ch
     P->info.blocks = best.blocks;
     P->info.chunk = best.chunk;
     P->info.homconv_us = best_us;
+    P->info.shared_layers = (int)P->problems.size();
+    P->info.own_layers = (int)P->single.size();
 
-    // capture the whole stack as one graph
-    if (hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        release(P);
-        return ENSEI_ERR_HIP;
-    }
-    rc = run_front(P, P->stream);
-    if (!rc) rc = run_homconv(P, P->sched, P->stream);
-    if (!rc) rc = run_back(P, P->stream);
-    hipGraph_t g = nullptr;
-    const hipError_t ec = hipStreamEndCapture(P->stream, &g);
-    P->graph = g;
-    if (!rc && (ec != hipSuccess || !g)) rc = ENSEI_ERR_HIP;
-    if (!rc && hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) != hipSuccess) {
-        P->exec = nullptr;
-        rc = ENSEI_ERR_HIP;
-    }
+    // capture the whole stack as one graph, and each stage as a graph of its own
+    rc = capture(P, -1, &P->graph, &P->exec);
+    for (int k = 0; k < 3 && !rc; ++k) rc = capture(P, k, &P->stage_graph[k], &P->stage_exec[k]);
     if (rc) {
         release(P);
         return rc;
@@ -322,6 +340,11 @@ int ensei_plan_create_seeded(ensei_ctx *ctx, const ensei_layer *layers, int nlay
 int ensei_plan_run(ensei_plan *plan, void *stream) {
     if (!plan || !plan->exec) return ENSEI_ERR_ARG;
     return hipGraphLaunch(plan->exec, (hipStream_t)stream) == hipSuccess ? ENSEI_OK : ENSEI_ERR_HIP;
+}
+
+int ensei_plan_run_stage(ensei_plan *plan, int stage, void *stream) {
+    if (!plan || stage < 0 || stage > 2 || !plan->stage_exec[stage]) return ENSEI_ERR_ARG;
+    return hipGraphLaunch(plan->stage_exec[stage], (hipStream_t)stream) == hipSuccess ? ENSEI_OK : ENSEI_ERR_HIP;
 }
 
 int ensei_plan_schedule(const ensei_plan *plan, ensei_schedule *out) {

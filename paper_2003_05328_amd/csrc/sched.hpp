@@ -1,15 +1,21 @@
 // Host-side admission logic of the serving layer, free of any device code so
 // that it can be exercised on the CPU: a first-fit arena over the ciphertext
-// budget and the rule that forms batches from the arrival queue.
+// budget, the rule that forms batches from the arrival queue, and the
+// bookkeeping of every request from submission to completion (including
+// cancellation and refusal of requests that exceed the budget).
 #pragma once
 
 #include <stddef.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <deque>
 #include <iterator>
 #include <map>
+#include <unordered_map>
 #include <vector>
+
+#include "ensei.h"
 
 namespace ensei {
 namespace sched {
@@ -97,6 +103,124 @@ std::vector<Admitted> next_batch(std::deque<uint64_t> &queue, Arena &arena, int 
     }
     return batch;
 }
+
+enum ReqState { kQueued = 0, kRunning = 1, kDone = 2, kFailed = 3, kCancelled = 4 };
+
+// What the book keeps per request (times in the caller's clock, seconds).
+struct Ticket {
+    int shape = -1;
+    size_t bytes = 0;      // footprint in the budget
+    ReqState state = kQueued;
+    int status = ENSEI_OK;
+    bool cancel = false;   // cancelled while running: reported as cancelled when its batch ends
+    size_t off = 0;        // block in the budget while running
+    double t_submit = 0, t_start = 0, t_done = 0;
+};
+
+// Request bookkeeping of a server: the queue in arrival order, the arena over
+// the budget and the records of every request. Not thread-safe: the server
+// calls it under its mutex.
+//   submit: refuses (ENSEI_ERR_BUDGET) a request whose footprint exceeds the
+//           whole budget, or that would take the bytes waiting in the queue
+//           past the queue limit (0 = no limit);
+//   cancel: a queued request leaves the queue at once and never takes budget
+//           or device time; a running one is marked and, once its batch has
+//           finished, released like any other and reported cancelled; a
+//           finished request cannot be cancelled (ENSEI_ERR_STATE);
+//   admit:  the next batch (next_batch's rule), its requests marked running;
+//   finish: a batch has ended with status rc: its blocks return to the arena.
+class Book {
+   public:
+    void reset(size_t budget, size_t queue_limit = 0) {
+        arena_.reset(budget);
+        queue_.clear();
+        recs_.clear();
+        queue_limit_ = queue_limit;
+        queued_bytes_ = 0;
+        peak_used_ = 0;
+    }
+    void set_queue_limit(size_t bytes) { queue_limit_ = bytes; }
+    int submit(uint64_t ticket, int shape, size_t bytes, double now) {
+        if (bytes == 0 || recs_.count(ticket)) return ENSEI_ERR_ARG;
+        if (align_up(bytes) > arena_.size()) return ENSEI_ERR_BUDGET;
+        if (queue_limit_ && queued_bytes_ + align_up(bytes) > queue_limit_) return ENSEI_ERR_BUDGET;
+        Ticket t;
+        t.shape = shape;
+        t.bytes = bytes;
+        t.t_submit = now;
+        recs_.emplace(ticket, t);
+        queue_.push_back(ticket);
+        queued_bytes_ += align_up(bytes);
+        return ENSEI_OK;
+    }
+    int cancel(uint64_t ticket, double now) {
+        auto it = recs_.find(ticket);
+        if (it == recs_.end()) return ENSEI_ERR_ARG;
+        Ticket &t = it->second;
+        if (t.state == kQueued) {
+            queue_.erase(std::find(queue_.begin(), queue_.end(), ticket));
+            queued_bytes_ -= align_up(t.bytes);
+            t.state = kCancelled;
+            t.status = ENSEI_ERR_CANCELLED;
+            t.t_done = now;
+            return ENSEI_OK;
+        }
+        if (t.state == kRunning) {
+            t.cancel = true;
+            return ENSEI_OK;
+        }
+        return ENSEI_ERR_STATE;
+    }
+    std::vector<Admitted> admit(int max_batch, double now) {
+        auto b = next_batch(queue_, arena_, max_batch, [&](uint64_t k) { return recs_[k].bytes; });
+        for (const Admitted &a : b) {
+            Ticket &t = recs_[a.ticket];
+            t.state = kRunning;
+            t.off = a.off;
+            t.t_start = now;
+            queued_bytes_ -= align_up(t.bytes);
+        }
+        if (arena_.used() > peak_used_) peak_used_ = arena_.used();
+        return b;
+    }
+    void finish(const std::vector<uint64_t> &tickets, int rc, double now) {
+        for (uint64_t k : tickets) {
+            Ticket &t = recs_[k];
+            arena_.release(t.off, t.bytes);
+            t.t_done = now;
+            if (t.cancel) {
+                t.state = kCancelled;
+                t.status = ENSEI_ERR_CANCELLED;
+            } else {
+                t.state = rc ? kFailed : kDone;
+                t.status = rc;
+            }
+        }
+    }
+    // Drops a finished record (ENSEI_ERR_ARG if unknown or not finished).
+    int forget(uint64_t ticket) {
+        auto it = recs_.find(ticket);
+        if (it == recs_.end() || it->second.state < kDone) return ENSEI_ERR_ARG;
+        recs_.erase(it);
+        return ENSEI_OK;
+    }
+    const Ticket *find(uint64_t ticket) const {
+        auto it = recs_.find(ticket);
+        return it == recs_.end() ? nullptr : &it->second;
+    }
+    size_t queued() const { return queue_.size(); }
+    size_t queued_bytes() const { return queued_bytes_; }
+    size_t used() const { return arena_.used(); }
+    size_t peak_used() const { return peak_used_; }
+    size_t budget() const { return arena_.size(); }
+    const Arena &arena() const { return arena_; }
+
+   private:
+    Arena arena_;
+    std::deque<uint64_t> queue_;
+    std::unordered_map<uint64_t, Ticket> recs_;
+    size_t queue_limit_ = 0, queued_bytes_ = 0, peak_used_ = 0;
+};
 
 }  // namespace sched
 }  // namespace ensei

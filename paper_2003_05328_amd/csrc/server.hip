@@ -31,6 +31,7 @@ namespace {
 using Clock = std::chrono::steady_clock;
 
 using sched::Arena;
+using sched::Book;
 using sched::kAlign;
 
 struct Shape {
@@ -43,20 +44,26 @@ struct Shape {
     bool narrow = false;   // HomConv on the narrow-input kernel (folded fragments), outside the shared launch
 };
 
-enum ReqState { kQueued = 0, kRunning = 1, kDone = 2, kFailed = 3 };
-
-struct Request {
-    uint64_t ticket;
-    int shape;
+// A submitted request's buffers until it is admitted (or cancelled), and the
+// event that marks its inputs complete on the caller's stream.
+struct Pending {
     ensei_request io;
-    ReqState state = kQueued;
-    int status = ENSEI_OK;
-    size_t off = 0;
-    Clock::time_point t_submit, t_start, t_done;
+    hipEvent_t ready = nullptr;
+};
+
+// One admitted request, copied out of the shared state so that the batch can
+// be enqueued without holding the server's lock.
+struct Job {
+    uint64_t ticket;
+    Shape sh;
+    ensei_request io;
+    hipEvent_t ready;
+    size_t off;
 };
 
 struct Batch {
     std::vector<uint64_t> tickets;
+    std::vector<Job> jobs;
     hipStream_t stream;
     hipEvent_t done;
     int slot;  // launch-table slot
@@ -72,27 +79,26 @@ struct ensei_server {
     size_t budget = 0;
     int nstreams = 0, max_batch = 0;
     uint8_t *pool = nullptr;
-    Arena arena;
-    std::vector<Shape> shapes;
+    std::deque<Shape> shapes;  // grows under mu; elements never move
     std::vector<hipStream_t> streams;
     int next_stream = 0;
     // launch tables of the multi-problem HomConv: per slot max_batch entries,
     // device copy and pinned host staging; a slot is busy while its batch runs
     HcLayer *d_tables = nullptr, *h_tables = nullptr;
     std::vector<int> free_slots;
-    std::vector<hipEvent_t> event_pool;
+    std::vector<hipEvent_t> event_pool;  // batch completion
+    std::vector<hipEvent_t> ready_pool;  // callers' input streams
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::deque<uint64_t> queue;
-    std::unordered_map<uint64_t, Request> reqs;
+    Book book;
+    std::unordered_map<uint64_t, Pending> pending;
     std::deque<Batch> inflight;
     uint64_t next_ticket = 1;
     bool stop = false;
     std::thread worker;
     Clock::time_point t0 = Clock::now();
-    uint64_t n_done = 0, n_failed = 0, n_batches = 0;
-    size_t peak_used = 0;
+    uint64_t n_done = 0, n_failed = 0, n_batches = 0, n_cancelled = 0, n_refused = 0;
     // seeded ciphertexts (ensei_server_create_seeded): a request keeps only
     // the b words of its input ciphertexts
     bool seeded = false;
@@ -102,6 +108,7 @@ namespace ensei {
 namespace {
 
 double secs(const ensei_server *S, Clock::time_point t) { return std::chrono::duration<double>(t - S->t0).count(); }
+double now_s(const ensei_server *S) { return secs(S, Clock::now()); }
 
 // Arena layout of one request: x^ [Cin][F] u32, ct_in [F][n+1][Cin] u64
 // (seeded: the b words, [F][Cin]), ct_out [F][n+1][Cout] u64, m [Cout][F] u32
@@ -121,33 +128,37 @@ Parts parts_of(const ensei_shape &d, bool seeded = false) {
     return p;
 }
 
-// Enqueues one batch; the caller holds the lock. Returns a status; on error
-// nothing of the batch is left running.
+// Enqueues one batch. Called WITHOUT the server's lock: it reads only the
+// batch's own jobs, its launch-table slot and the arena memory of its
+// requests. Returns a status; on error nothing of the batch is left running
+// once its stream has been synchronised.
 int launch_batch(ensei_server *S, Batch &b) {
     const hipStream_t st = b.stream;
     HcLayer *tab = S->h_tables + (size_t)b.slot * S->max_batch;
     int np = 0;
     int64_t tile0 = 0;
     int rc = ENSEI_OK;
-    for (uint64_t t : b.tickets) {
-        Request &q = S->reqs[t];
-        const Shape &sh = S->shapes[q.shape];
+    // inputs produced by pending work on the callers' streams
+    for (const Job &j : b.jobs)
+        if (j.ready && hipStreamWaitEvent(st, j.ready, 0) != hipSuccess) return ENSEI_ERR_HIP;
+    for (const Job &j : b.jobs) {
+        const Shape &sh = j.sh;
         const ensei_shape &d = sh.d;
         const Parts pt = parts_of(d, S->seeded);
-        uint8_t *base = S->pool + q.off;
+        uint8_t *base = S->pool + j.off;
         uint32_t *x_hat = reinterpret_cast<uint32_t *>(base + pt.x_hat);
         uint64_t *ct_in = reinterpret_cast<uint64_t *>(base + pt.ct_in);
         uint64_t *ct_out = reinterpret_cast<uint64_t *>(base + pt.ct_out);
-        rc = ensei_ntt2d(S->ctx, q.io.x, x_hat, d.Cin, d.H, d.W, st);
+        rc = ensei_ntt2d(S->ctx, j.io.x, x_hat, d.Cin, d.H, d.W, st);
         if (!rc)
-            rc = S->seeded ? ensei_encrypt_seeded(S->ctx, x_hat, q.io.s, q.io.e, 1, d.Cin, sh.F, d.n, q.io.seed_a, 0,
+            rc = S->seeded ? ensei_encrypt_seeded(S->ctx, x_hat, j.io.s, j.io.e, 1, d.Cin, sh.F, d.n, j.io.seed_a, 0,
                                                   ct_in, st)
-                           : ensei_encrypt(S->ctx, x_hat, q.io.s, q.io.e, 1, d.Cin, sh.F, d.n, q.io.seed_a, 0, ct_in, st);
+                           : ensei_encrypt(S->ctx, x_hat, j.io.s, j.io.e, 1, d.Cin, sh.F, d.n, j.io.seed_a, 0, ct_in, st);
         HcLayer h;
         if (!rc)
-            rc = homconv_problem(S->ctx, &h, ct_in, sh.w_pack, q.io.r, 1, d.Cin, d.Cout, sh.F, d.n, ct_out,
+            rc = homconv_problem(S->ctx, &h, ct_in, sh.w_pack, j.io.r, 1, d.Cin, d.Cout, sh.F, d.n, ct_out,
                                  sh.wpack_bytes, S->seeded);
-        h.seed_a = S->seeded ? q.io.seed_a : 0;
+        h.seed_a = S->seeded ? j.io.seed_a : 0;
         h.idx0 = 0;
         // narrow and deep shapes run on their own kernels, the others share one launch
         const bool alone = !rc && (sh.narrow || homconv_deep_fits(h, S->seeded));
@@ -167,36 +178,35 @@ int launch_batch(ensei_server *S, Batch &b) {
     } else if (!rc && np == 1) {
         rc = homconv_launch(S->ctx, tab, nullptr, 1, true, HcSchedule{0, 0}, st, S->seeded);
     }
-    for (uint64_t t : b.tickets) {
+    for (const Job &j : b.jobs) {
         if (rc) break;
-        Request &q = S->reqs[t];
-        const Shape &sh = S->shapes[q.shape];
+        const Shape &sh = j.sh;
         const ensei_shape &d = sh.d;
         const Parts pt = parts_of(d, S->seeded);
-        uint8_t *base = S->pool + q.off;
+        uint8_t *base = S->pool + j.off;
         const uint64_t *ct_out = reinterpret_cast<const uint64_t *>(base + pt.ct_out);
         uint32_t *m = reinterpret_cast<uint32_t *>(base + pt.m);
-        rc = ensei_decrypt(S->ctx, ct_out, q.io.s, 1, d.Cout, sh.F, d.n, m, st);
-        if (!rc) rc = ensei_intt2d(S->ctx, m, q.io.s_a, d.Cout, d.H, d.W, st);
-        if (!rc) rc = ensei_server_share(S->ctx, q.io.r, q.io.s_b, d.Cout, d.H, d.W, st);
+        rc = ensei_decrypt(S->ctx, ct_out, j.io.s, 1, d.Cout, sh.F, d.n, m, st);
+        if (!rc) rc = ensei_intt2d(S->ctx, m, j.io.s_a, d.Cout, d.H, d.W, st);
+        if (!rc) rc = ensei_server_share(S->ctx, j.io.r, j.io.s_b, d.Cout, d.H, d.W, st);
     }
     if (!rc && hipEventRecord(b.done, st) != hipSuccess) rc = ENSEI_ERR_HIP;
     return rc;
 }
 
+// A batch has ended (caller holds the lock): the book releases its budget and
+// records the outcome; the batch's events return to their pools.
 void finish(ensei_server *S, Batch &b, int rc) {
-    const auto now = Clock::now();
+    S->book.finish(b.tickets, rc, now_s(S));
     for (uint64_t t : b.tickets) {
-        Request &q = S->reqs[t];
-        q.t_done = now;
-        q.status = rc;
-        q.state = rc ? kFailed : kDone;
-        S->arena.release(q.off, S->shapes[q.shape].footprint);
-        if (rc)
-            ++S->n_failed;
-        else
+        const sched::Ticket *k = S->book.find(t);
+        if (k->state == sched::kDone)
             ++S->n_done;
+        else if (k->state == sched::kFailed)
+            ++S->n_failed;
     }
+    for (const Job &j : b.jobs)
+        if (j.ready) S->ready_pool.push_back(j.ready);
     S->free_slots.push_back(b.slot);
     S->event_pool.push_back(b.done);
 }
@@ -218,21 +228,17 @@ void worker_loop(ensei_server *S) {
         }
         // admit queued requests in arrival order while they fit, one batch
         // per free launch slot
-        while (!S->queue.empty() && !S->free_slots.empty()) {
-            Batch b;
-            const auto admitted = sched::next_batch(S->queue, S->arena, S->max_batch, [&](uint64_t t) {
-                return S->shapes[S->reqs[t].shape].footprint;
-            });
+        while (S->book.queued() && !S->free_slots.empty()) {
+            const auto admitted = S->book.admit(S->max_batch, now_s(S));
             if (admitted.empty()) break;
-            const auto now = Clock::now();
+            Batch b;
             for (const sched::Admitted &a : admitted) {
-                Request &q = S->reqs[a.ticket];
-                q.off = a.off;
-                q.state = kRunning;
-                q.t_start = now;
+                auto pit = S->pending.find(a.ticket);
+                const int shape = S->book.find(a.ticket)->shape;
                 b.tickets.push_back(a.ticket);
+                b.jobs.push_back(Job{a.ticket, S->shapes[shape], pit->second.io, pit->second.ready, a.off});
+                S->pending.erase(pit);
             }
-            if (S->arena.used() > S->peak_used) S->peak_used = S->arena.used();
             b.slot = S->free_slots.back();
             S->free_slots.pop_back();
             b.done = S->event_pool.back();
@@ -240,18 +246,21 @@ void worker_loop(ensei_server *S) {
             b.stream = S->streams[S->next_stream];
             S->next_stream = (S->next_stream + 1) % S->nstreams;
             ++S->n_batches;
+            // enqueue without the lock, so that submits, polls and cancels
+            // are not held up by the launches
+            lk.unlock();
             const int rc = launch_batch(S, b);
+            if (rc) (void)hipStreamSynchronize(b.stream);  // enqueued work must end before the memory is reused
+            lk.lock();
             if (rc) {
-                // work already enqueued must finish before the memory is reused
-                (void)hipStreamSynchronize(b.stream);
                 finish(S, b, rc);
                 S->cv_done.notify_all();
             } else {
-                S->inflight.push_back(b);
+                S->inflight.push_back(std::move(b));
             }
         }
-        if (S->stop && S->queue.empty() && S->inflight.empty()) break;
-        if (S->inflight.empty() && (S->queue.empty() || S->free_slots.empty()) && !S->stop) {
+        if (S->stop && !S->book.queued() && S->inflight.empty()) break;
+        if (S->inflight.empty() && (!S->book.queued() || S->free_slots.empty()) && !S->stop) {
             S->cv_work.wait(lk);
         } else {
             // device work pending: poll its events at a fine interval
@@ -276,6 +285,9 @@ void destroy(ensei_server *S) {
         (void)hipStreamDestroy(s);
     }
     for (hipEvent_t e : S->event_pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : S->ready_pool) (void)hipEventDestroy(e);
+    for (auto &kv : S->pending)
+        if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
     for (Shape &sh : S->shapes) {
         if (sh.w_hat) (void)hipFree(sh.w_hat);
         if (sh.w_pack) (void)hipFree(sh.w_pack);
@@ -336,7 +348,7 @@ static int server_create(ensei_ctx *ctx, size_t budget_bytes, int nstreams, int 
         destroy(S);
         return ENSEI_ERR_HIP;
     }
-    S->arena.reset(S->budget);
+    S->book.reset(S->budget);
     S->worker = std::thread(worker_loop, S);
     *out = S;
     return ENSEI_OK;
@@ -360,16 +372,19 @@ int ensei_server_add_shape(ensei_server *S, const ensei_shape *shape, const int3
     sh.d = d;
     sh.F = (int64_t)d.H * d.W;
     sh.footprint = parts_of(d, S->seeded).total;
-    if (sh.footprint > S->budget) return ENSEI_ERR_LIMIT;
+    if (sh.footprint > S->book.budget()) return ENSEI_ERR_BUDGET;
     sh.narrow = d.Cin <= kNarrowCin;
     sh.wpack_bytes = wpack_bytes_as(d.Cout, d.Cin, sh.F, !sh.narrow);
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(S->ctx->device);
     int rc = ENSEI_OK;
-    if (hipMalloc(&sh.w_hat, (size_t)d.Cout * d.Cin * sh.F * 4) != hipSuccess) sh.w_hat = nullptr;
-    if (sh.w_hat && hipMalloc(&sh.w_pack, sh.wpack_bytes) != hipSuccess) sh.w_pack = nullptr;
-    if (!sh.w_hat || !sh.w_pack) rc = ENSEI_ERR_HIP;
+    // w is read on a private stream: pending work of every stream that may
+    // still write it finishes first
+    if (hipDeviceSynchronize() != hipSuccess) rc = ENSEI_ERR_HIP;
+    if (!rc && hipMalloc(&sh.w_hat, (size_t)d.Cout * d.Cin * sh.F * 4) != hipSuccess) sh.w_hat = nullptr;
+    if (!rc && sh.w_hat && hipMalloc(&sh.w_pack, sh.wpack_bytes) != hipSuccess) sh.w_pack = nullptr;
+    if (!rc && (!sh.w_hat || !sh.w_pack)) rc = ENSEI_ERR_HIP;
     hipStream_t st = nullptr;
     if (!rc && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
         st = nullptr;
@@ -396,32 +411,88 @@ int ensei_server_add_shape(ensei_server *S, const ensei_shape *shape, const int3
 int ensei_server_submit(ensei_server *S, int shape_id, const ensei_request *req, uint64_t *ticket) {
     if (!S || !req || !ticket) return ENSEI_ERR_ARG;
     if (!req->x || !req->s || !req->e || !req->r || !req->s_a || !req->s_b) return ENSEI_ERR_ARG;
+    const double t_arrival = now_s(S);  // before waiting for the lock
     std::lock_guard<std::mutex> g(S->mu);
     if (shape_id < 0 || shape_id >= (int)S->shapes.size()) return ENSEI_ERR_ARG;
     if (S->stop) return ENSEI_ERR_ARG;
-    Request q;
-    q.ticket = S->next_ticket++;
-    q.shape = shape_id;
-    q.io = *req;
-    q.t_submit = Clock::now();
-    S->reqs.emplace(q.ticket, q);
-    S->queue.push_back(q.ticket);
-    *ticket = q.ticket;
+    const uint64_t t = S->next_ticket;
+    const int rc = S->book.submit(t, shape_id, S->shapes[shape_id].footprint, t_arrival);
+    if (rc == ENSEI_ERR_BUDGET) ++S->n_refused;
+    if (rc) return rc;
+    Pending p;
+    p.io = *req;
+    {
+        // the request's kernels wait for the caller's pending input work
+        if (S->ready_pool.empty()) {
+            hipEvent_t e;
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                S->book.cancel(t, t_arrival);
+                S->book.forget(t);
+                return ENSEI_ERR_HIP;
+            }
+            S->ready_pool.push_back(e);
+        }
+        p.ready = S->ready_pool.back();
+        if (hipEventRecord(p.ready, static_cast<hipStream_t>(req->stream)) != hipSuccess) {
+            S->book.cancel(t, t_arrival);
+            S->book.forget(t);
+            return ENSEI_ERR_HIP;
+        }
+        S->ready_pool.pop_back();
+    }
+    S->pending.emplace(t, p);
+    ++S->next_ticket;
+    *ticket = t;
     S->cv_work.notify_one();
+    return ENSEI_OK;
+}
+
+int ensei_server_cancel(ensei_server *S, uint64_t ticket) {
+    if (!S) return ENSEI_ERR_ARG;
+    std::lock_guard<std::mutex> g(S->mu);
+    const sched::Ticket *k = S->book.find(ticket);
+    if (!k) return ENSEI_ERR_ARG;
+    const bool queued = k->state == sched::kQueued;
+    const int rc = S->book.cancel(ticket, now_s(S));
+    if (rc) return rc;
+    ++S->n_cancelled;
+    if (queued) {
+        // it never runs: its input event goes back, and requests that waited
+        // behind it may be admitted now
+        auto pit = S->pending.find(ticket);
+        if (pit != S->pending.end()) {
+            if (pit->second.ready) S->ready_pool.push_back(pit->second.ready);
+            S->pending.erase(pit);
+        }
+        S->cv_done.notify_all();
+        S->cv_work.notify_one();
+    }
+    return ENSEI_OK;
+}
+
+int ensei_server_set_queue_limit(ensei_server *S, size_t bytes) {
+    if (!S) return ENSEI_ERR_ARG;
+    std::lock_guard<std::mutex> g(S->mu);
+    S->book.set_queue_limit(bytes);
+    return ENSEI_OK;
+}
+
+int ensei_server_clock(ensei_server *S, double *now) {
+    if (!S || !now) return ENSEI_ERR_ARG;
+    *now = now_s(S);
     return ENSEI_OK;
 }
 
 int ensei_server_poll(ensei_server *S, uint64_t ticket, ensei_request_info *info) {
     if (!S || !info) return ENSEI_ERR_ARG;
     std::lock_guard<std::mutex> g(S->mu);
-    auto it = S->reqs.find(ticket);
-    if (it == S->reqs.end()) return ENSEI_ERR_ARG;
-    const Request &q = it->second;
-    info->state = q.state;
-    info->status = q.status;
-    info->t_submit = secs(S, q.t_submit);
-    info->t_start = q.state >= kRunning ? secs(S, q.t_start) : 0.0;
-    info->t_done = q.state >= kDone ? secs(S, q.t_done) : 0.0;
+    const sched::Ticket *k = S->book.find(ticket);
+    if (!k) return ENSEI_ERR_ARG;
+    info->state = k->state;
+    info->status = k->status;
+    info->t_submit = k->t_submit;
+    info->t_start = k->state == sched::kRunning || k->t_start > 0 ? k->t_start : 0.0;
+    info->t_done = k->state >= sched::kDone ? k->t_done : 0.0;
     return ENSEI_OK;
 }
 
@@ -429,37 +500,37 @@ int ensei_server_wait(ensei_server *S, uint64_t ticket, int timeout_ms) {
     if (!S) return ENSEI_ERR_ARG;
     std::unique_lock<std::mutex> lk(S->mu);
     auto done = [&] {
-        auto it = S->reqs.find(ticket);
-        return it == S->reqs.end() || it->second.state >= kDone;
+        const sched::Ticket *k = S->book.find(ticket);
+        return !k || k->state >= sched::kDone;
     };
-    if (S->reqs.find(ticket) == S->reqs.end()) return ENSEI_ERR_ARG;
+    if (!S->book.find(ticket)) return ENSEI_ERR_ARG;
     if (timeout_ms < 0)
         S->cv_done.wait(lk, done);
     else if (!S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), done))
         return ENSEI_ERR_TIMEOUT;
-    return S->reqs[ticket].status;
+    const sched::Ticket *k = S->book.find(ticket);
+    return k ? k->status : ENSEI_ERR_ARG;
 }
 
 int ensei_server_forget(ensei_server *S, uint64_t ticket) {
     if (!S) return ENSEI_ERR_ARG;
     std::lock_guard<std::mutex> g(S->mu);
-    auto it = S->reqs.find(ticket);
-    if (it == S->reqs.end() || it->second.state < kDone) return ENSEI_ERR_ARG;
-    S->reqs.erase(it);
-    return ENSEI_OK;
+    return S->book.forget(ticket);
 }
 
 int ensei_server_stats(ensei_server *S, ensei_server_info *out) {
     if (!S || !out) return ENSEI_ERR_ARG;
     std::lock_guard<std::mutex> g(S->mu);
     out->budget_bytes = S->budget;
-    out->used_bytes = S->arena.used();
-    out->peak_used_bytes = S->peak_used;
-    out->queued = S->queue.size();
+    out->used_bytes = S->book.used();
+    out->peak_used_bytes = S->book.peak_used();
+    out->queued = S->book.queued();
     out->inflight_batches = S->inflight.size();
     out->completed = S->n_done;
     out->failed = S->n_failed;
     out->batches = S->n_batches;
+    out->cancelled = S->n_cancelled;
+    out->refused = S->n_refused;
     return ENSEI_OK;
 }
 

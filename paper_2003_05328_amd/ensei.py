@@ -18,6 +18,8 @@ import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libensei.so")
+# the vector-ALU comparison kernel (include/ensei_bench.h), outside the product library
+BENCH_LIB_PATH = os.path.join(_HERE, "libensei_bench.so")
 
 ENSEI_OK = 0
 STATUS = {
@@ -30,6 +32,9 @@ STATUS = {
     -7: "ENSEI_ERR_DEVICE",
     -8: "ENSEI_ERR_HIP",
     -9: "ENSEI_ERR_TIMEOUT",
+    -10: "ENSEI_ERR_BUDGET",
+    -11: "ENSEI_ERR_CANCELLED",
+    -12: "ENSEI_ERR_STATE",
 }
 
 _vp, _i32, _i64, _u32, _u64 = C.c_void_p, C.c_int, C.c_int64, C.c_uint32, C.c_uint64
@@ -39,6 +44,7 @@ SIGNATURES = {
     "ensei_ctx_create": (_i32, [C.POINTER(_vp), _u32, _i32]),
     "ensei_ctx_destroy": (_i32, [_vp]),
     "ensei_status_str": (C.c_char_p, [_i32]),
+    "ensei_ctx_device": (_i32, [_vp]),
     "ensei_ctx_modulus": (_u32, [_vp]),
     "ensei_ctx_delta": (_u64, [_vp]),
     "ensei_ctx_max_dim": (_i32, [_vp]),
@@ -54,7 +60,6 @@ SIGNATURES = {
     "ensei_error_table": (_i32, [_vp, _vp, _i32]),
     "ensei_encrypt_seeded": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i64, _i32, _u64, _u64, _vp, _vp]),
     "ensei_homconv_seeded": (_i32, [_vp, _vp, _u64, _u64, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
-    "ensei_homconv_valu": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
     "ensei_decrypt": (_i32, [_vp, _vp, _vp, _i64, _i32, _i64, _i32, _vp, _vp]),
     "ensei_homrec": (_i32, [_vp, _vp, _vp, _i64, _i32, _i64, _i32, _vp]),
     "ensei_homrec_seeded": (_i32, [_vp, _vp, _vp, _i64, _i32, _i64, _vp]),
@@ -62,6 +67,7 @@ SIGNATURES = {
     "ensei_plan_create": (_i32, [_vp, _vp, _i32, C.c_char_p, C.POINTER(_vp)]),
     "ensei_plan_create_seeded": (_i32, [_vp, _vp, _i32, C.c_char_p, C.POINTER(_vp)]),
     "ensei_plan_run": (_i32, [_vp, _vp]),
+    "ensei_plan_run_stage": (_i32, [_vp, _i32, _vp]),
     "ensei_plan_schedule": (_i32, [_vp, _vp]),
     "ensei_plan_destroy": (_i32, [_vp]),
     "ensei_request_bytes": (C.c_size_t, [_vp]),
@@ -69,11 +75,19 @@ SIGNATURES = {
     "ensei_server_create_seeded": (_i32, [_vp, C.c_size_t, _i32, _i32, C.POINTER(_vp)]),
     "ensei_server_add_shape": (_i32, [_vp, _vp, _vp, C.POINTER(_i32)]),
     "ensei_server_submit": (_i32, [_vp, _i32, _vp, C.POINTER(_u64)]),
+    "ensei_server_cancel": (_i32, [_vp, _u64]),
+    "ensei_server_set_queue_limit": (_i32, [_vp, C.c_size_t]),
+    "ensei_server_clock": (_i32, [_vp, C.POINTER(C.c_double)]),
     "ensei_server_poll": (_i32, [_vp, _u64, _vp]),
     "ensei_server_wait": (_i32, [_vp, _u64, _i32]),
     "ensei_server_forget": (_i32, [_vp, _u64]),
     "ensei_server_stats": (_i32, [_vp, _vp]),
     "ensei_server_destroy": (_i32, [_vp]),
+}
+
+
+BENCH_SIGNATURES = {
+    "ensei_bench_homconv_valu": (_i32, [_vp, _vp, _vp, _vp, _i64, _i32, _i32, _i64, _i32, _vp, _vp]),
 }
 
 
@@ -86,7 +100,8 @@ class ShapeDesc(C.Structure):
 class RequestDesc(C.Structure):
     """``ensei_request``: one request's device buffers."""
 
-    _fields_ = [("x", _vp), ("s", _vp), ("e", _vp), ("r", _vp), ("seed_a", _u64), ("s_a", _vp), ("s_b", _vp)]
+    _fields_ = [("x", _vp), ("s", _vp), ("e", _vp), ("r", _vp), ("seed_a", _u64), ("s_a", _vp), ("s_b", _vp),
+                ("stream", _vp)]
 
 
 class RequestInfo(C.Structure):
@@ -100,7 +115,7 @@ class ServerInfo(C.Structure):
     """``ensei_server_info``."""
 
     _fields_ = [(f, _u64) for f in ("budget_bytes", "used_bytes", "peak_used_bytes", "queued", "inflight_batches",
-                                    "completed", "failed", "batches")]
+                                    "completed", "failed", "batches", "cancelled", "refused")]
 
 
 class LayerDesc(C.Structure):
@@ -115,7 +130,8 @@ class LayerDesc(C.Structure):
 class ScheduleDesc(C.Structure):
     """``ensei_schedule``: the HomConv tile schedule a plan runs."""
 
-    _fields_ = [("blocks", _i32), ("from_cache", _i32), ("chunk", _i64), ("homconv_us", C.c_double)]
+    _fields_ = [("blocks", _i32), ("from_cache", _i32), ("chunk", _i64), ("homconv_us", C.c_double),
+                ("shared_layers", _i32), ("own_layers", _i32)]
 
 
 class EnseiError(RuntimeError):
@@ -145,6 +161,25 @@ def lib():
             fn.argtypes = args
         _lib = l
     return _lib
+
+
+_bench_lib = None
+
+
+def bench_lib():
+    """libensei_bench.so (comparison kernels for benchmarks and tests)."""
+    global _bench_lib
+    if _bench_lib is None:
+        lib()
+        if not os.path.exists(BENCH_LIB_PATH):
+            raise RuntimeError(f"{BENCH_LIB_PATH} is missing: build it with `python -m paper_2003_05328_amd.build`")
+        l = C.CDLL(BENCH_LIB_PATH)
+        for name, (res, args) in BENCH_SIGNATURES.items():
+            fn = getattr(l, name)
+            fn.restype = res
+            fn.argtypes = args
+        _bench_lib = l
+    return _bench_lib
 
 
 def _check(status: int, where: str):
@@ -403,7 +438,8 @@ class Context:
         return out
 
     def homconv_valu(self, ct_in, w_hat, r, out=None) -> torch.Tensor:
-        """Same contraction from W^ uint32 [Cout][Cin][F] on the vector ALUs (ensei_homconv_valu)."""
+        """Same contraction from W^ uint32 [Cout][Cin][F] on the vector ALUs
+        (ensei_bench_homconv_valu, in the comparison library libensei_bench.so)."""
         self._dev(ct_in, "ct_in", torch.uint64)
         self._dev(w_hat, "w_hat", torch.uint32)
         self._dev(r, "r", torch.uint32)
@@ -412,7 +448,9 @@ class Context:
         if tuple(w_hat.shape) != (Cout, Cin, F):
             raise ValueError("w_hat must be [Cout][Cin][F]")
         out = self._out(out, (B, F, n + 1, Cout), torch.uint64)
-        self._call("ensei_homconv_valu", _ptr(ct_in), _ptr(w_hat), _ptr(r), B, Cin, Cout, F, n, _ptr(out))
+        with torch.cuda.device(self.device):
+            _check(bench_lib().ensei_bench_homconv_valu(self._h, _ptr(ct_in), _ptr(w_hat), _ptr(r), B, Cin, Cout, F, n,
+                                                        _ptr(out), self._stream()), "ensei_bench_homconv_valu")
         return out
 
 
@@ -479,10 +517,17 @@ class Plan:
         with torch.cuda.device(self.ctx.device):
             _check(lib().ensei_plan_run(self._h, self.ctx._stream()), "ensei_plan_run")
 
+    def run_stage(self, stage: int):
+        """Enqueue one stage (0 client NTT2D + Enc, 1 server HomConv, 2 Dec,
+        INTT2D and the server's share) on the current stream."""
+        with torch.cuda.device(self.ctx.device):
+            _check(lib().ensei_plan_run_stage(self._h, int(stage), self.ctx._stream()), "ensei_plan_run_stage")
+
     def schedule(self) -> dict:
         sd = ScheduleDesc()
         _check(lib().ensei_plan_schedule(self._h, C.byref(sd)), "ensei_plan_schedule")
-        return {"blocks": sd.blocks, "chunk": sd.chunk, "homconv_us": sd.homconv_us, "from_cache": bool(sd.from_cache)}
+        return {"blocks": sd.blocks, "chunk": sd.chunk, "homconv_us": sd.homconv_us, "from_cache": bool(sd.from_cache),
+                "shared_layers": sd.shared_layers, "own_layers": sd.own_layers}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -502,7 +547,7 @@ class Server:
     requests of mixed shapes under a device-memory budget for their
     ciphertext state."""
 
-    STATES = ("queued", "running", "done", "failed")
+    STATES = ("queued", "running", "done", "failed", "cancelled")
 
     def __init__(self, ctx: "Context", budget_bytes: int, nstreams: int = 4, max_batch: int = 16,
                  seeded: bool = False):
@@ -535,7 +580,9 @@ class Server:
 
     def submit(self, shape_id: int, x, s, e, r, seed_a: int, s_a, s_b) -> int:
         """Queues one request (device tensors: x [Cin][H][W], s [n], e [Cin][F],
-        r [Cout][F]; outputs s_a, s_b [Cout][H][W]). Inputs must be complete."""
+        r [Cout][F]; outputs s_a, s_b [Cout][H][W]). The request's kernels
+        start after the work queued on the current stream so far, which may
+        still be writing the inputs."""
         H, W, Cin, Cout, kh, kw, n = self._shapes[shape_id]
         F = H * W
         need = {"x": (x, torch.uint32, Cin * F), "s": (s, torch.int8, n), "e": (e, torch.int32, Cin * F),
@@ -546,10 +593,26 @@ class Server:
             if t.numel() != cnt:
                 raise ValueError(f"{k} holds {t.numel()} elements, the shape needs {cnt}")
         rq = RequestDesc(_ptr(x).value, _ptr(s).value, _ptr(e).value, _ptr(r).value, int(seed_a) & (2**64 - 1),
-                         _ptr(s_a).value, _ptr(s_b).value)
+                         _ptr(s_a).value, _ptr(s_b).value, self.ctx._stream().value)
         t = C.c_uint64()
         _check(lib().ensei_server_submit(self._h, shape_id, C.byref(rq), C.byref(t)), "ensei_server_submit")
         self._keep[t.value] = (x, s, e, r, s_a, s_b)
+        return t.value
+
+    def cancel(self, ticket: int) -> None:
+        """Cancels a queued request (it never runs) or marks a running one
+        (reported cancelled when its batch ends); EnseiError(STATE) if the
+        request has finished."""
+        _check(lib().ensei_server_cancel(self._h, ticket), "ensei_server_cancel")
+
+    def set_queue_limit(self, nbytes: int) -> None:
+        """Caps the bytes of requests waiting for admission (0: no cap)."""
+        _check(lib().ensei_server_set_queue_limit(self._h, int(nbytes)), "ensei_server_set_queue_limit")
+
+    def clock(self) -> float:
+        """Seconds since the server was created (the time base of poll())."""
+        t = C.c_double()
+        _check(lib().ensei_server_clock(self._h, C.byref(t)), "ensei_server_clock")
         return t.value
 
     def poll(self, ticket: int) -> dict:

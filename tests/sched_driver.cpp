@@ -1,5 +1,7 @@
 // CPU checks of the serving layer's admission logic (csrc/sched.hpp): the
-// first-fit arena and the in-order batch rule. Exits non-zero on a failure.
+// first-fit arena, the in-order batch rule, and the request book (refusal of
+// over-budget requests, cancellation) driven by a fake executor in place of
+// the device. Exits non-zero on a failure.
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -122,12 +124,182 @@ static void random_stress() {
     CHECK(a.used() == 0 && a.free_blocks() == 1);
 }
 
+// Refusals at submit: a footprint larger than the whole budget, and bytes
+// waiting past the queue limit; nothing is queued for a refused request.
+static void book_budget() {
+    Book b;
+    b.reset(8 * 1024);
+    CHECK(b.submit(1, 0, 8 * 1024 + 1, 0.0) == ENSEI_ERR_BUDGET);
+    CHECK(b.find(1) == nullptr && b.queued() == 0);
+    CHECK(b.submit(1, 0, 8 * 1024, 0.0) == ENSEI_OK);  // exactly the budget fits
+    CHECK(b.submit(1, 0, 100, 0.0) == ENSEI_ERR_ARG);   // duplicate ticket
+    b.set_queue_limit(10 * 1024);
+    CHECK(b.submit(2, 0, 2048, 0.0) == ENSEI_OK);        // 8 KB + 2 KB waiting
+    CHECK(b.submit(3, 0, 1, 0.0) == ENSEI_ERR_BUDGET);   // 256 more bytes would pass the cap
+    CHECK(b.queued() == 2 && b.queued_bytes() == 10 * 1024);
+    auto a = b.admit(8, 1.0);
+    CHECK(a.size() == 1 && a[0].ticket == 1 && b.queued_bytes() == 2048);
+    CHECK(b.submit(3, 0, 1, 1.0) == ENSEI_OK);           // room in the queue again
+}
+
+// Cancellation: a queued request leaves at once and lets the requests behind
+// it in; a running one keeps its block until its batch ends and is then
+// reported cancelled; a finished one cannot be cancelled.
+static void book_cancel() {
+    Book b;
+    b.reset(10 * 1024);
+    CHECK(b.submit(1, 0, 6 * 1024, 0.0) == ENSEI_OK);
+    CHECK(b.submit(2, 0, 6 * 1024, 0.0) == ENSEI_OK);  // head of the queue once 1 runs; does not fit beside it
+    CHECK(b.submit(3, 0, 1024, 0.0) == ENSEI_OK);
+    auto a1 = b.admit(8, 1.0);
+    CHECK(a1.size() == 1 && a1[0].ticket == 1);
+    CHECK(b.admit(8, 1.0).empty());  // 3 may not overtake 2
+    CHECK(b.cancel(2, 2.0) == ENSEI_OK);
+    CHECK(b.find(2)->state == kCancelled && b.find(2)->status == ENSEI_ERR_CANCELLED);
+    auto a2 = b.admit(8, 2.0);  // 3 goes in beside 1
+    CHECK(a2.size() == 1 && a2[0].ticket == 3);
+    CHECK(b.cancel(1, 3.0) == ENSEI_OK && b.find(1)->state == kRunning);
+    CHECK(b.used() == 7 * 1024);  // 1 still holds its block
+    b.finish({1}, ENSEI_OK, 4.0);
+    CHECK(b.find(1)->state == kCancelled && b.find(1)->status == ENSEI_ERR_CANCELLED);
+    CHECK(b.used() == 1024);
+    b.finish({3}, ENSEI_OK, 4.0);
+    CHECK(b.find(3)->state == kDone && b.find(3)->status == ENSEI_OK && b.used() == 0);
+    CHECK(b.cancel(3, 5.0) == ENSEI_ERR_STATE);
+    CHECK(b.cancel(2, 5.0) == ENSEI_ERR_STATE);
+    CHECK(b.cancel(99, 5.0) == ENSEI_ERR_ARG);
+    CHECK(b.forget(3) == ENSEI_OK && b.find(3) == nullptr && b.forget(3) == ENSEI_ERR_ARG);
+    CHECK(b.queued() == 0 && b.queued_bytes() == 0);
+}
+
+// A fake executor: every request owns a 64-word output buffer that its batch
+// fills with a function of its own inputs only, at completion. Random
+// submits, cancels (queued and running), admissions and completions: every
+// request that completes holds exactly what it would hold alone, a request
+// cancelled while queued is never admitted and its buffer never written,
+// the budget is never exceeded, and every block is returned.
+static uint64_t fake_result(uint64_t input, int k) {
+    uint64_t z = input + 0x9E3779B97F4A7C15ull * (uint64_t)(k + 1);
+    z = (z ^ (z >> 31)) * 0xBF58476D1CE4E5B9ull;
+    return z ^ (z >> 29);
+}
+
+static void book_fake_executor() {
+    std::mt19937_64 g(11);
+    Book b;
+    const size_t budget = 32 << 20;
+    b.reset(budget, 200 << 20);
+    struct Out {
+        uint64_t input;
+        std::vector<uint64_t> words;
+        bool written = false;
+    };
+    std::map<uint64_t, Out> outs;
+    struct Running {
+        std::vector<uint64_t> tickets;
+    };
+    std::vector<Running> inflight;
+    std::map<uint64_t, bool> cancelled_queued;
+    uint64_t next = 1;
+    int refused = 0, cancels = 0;
+    for (int step = 0; step < 20000; ++step) {
+        const double now = step;
+        if (g() % 2 == 0 && next < 6000) {
+            const size_t bytes = 1 + g() % (40 << 20);  // some exceed the 32 MB budget
+            const int rc = b.submit(next, 0, bytes, now);
+            if (rc == ENSEI_OK) {
+                outs[next] = Out{g(), std::vector<uint64_t>(64, 0), false};
+            } else {
+                CHECK(rc == ENSEI_ERR_BUDGET);
+                CHECK(bytes > budget || b.queued_bytes() + align_up(bytes) > (200u << 20));
+                ++refused;
+            }
+            ++next;
+        }
+        if (g() % 7 == 0 && next > 1) {
+            const uint64_t t = 1 + g() % (next - 1);
+            const Ticket *k = b.find(t);
+            if (k) {
+                const bool queued = k->state == kQueued;
+                const int rc = b.cancel(t, now);
+                if (k->state >= kDone && !queued && rc == ENSEI_ERR_STATE) {
+                } else {
+                    CHECK(rc == ENSEI_OK);
+                    ++cancels;
+                    if (queued) cancelled_queued[t] = true;
+                }
+            }
+        }
+        if (!inflight.empty() && g() % 3 == 0) {
+            const size_t i = g() % inflight.size();
+            for (uint64_t t : inflight[i].tickets) {  // the "device" writes each request's own output
+                Out &o = outs[t];
+                for (int k = 0; k < 64; ++k) o.words[k] = fake_result(o.input, k);
+                o.written = true;
+            }
+            b.finish(inflight[i].tickets, ENSEI_OK, now);
+            inflight.erase(inflight.begin() + i);
+        }
+        auto a = b.admit(1 + (int)(g() % 8), now);
+        if (!a.empty()) {
+            Running r;
+            for (const Admitted &x : a) {
+                CHECK(!cancelled_queued.count(x.ticket));
+                CHECK(x.off + align_up(x.bytes) <= budget);
+                r.tickets.push_back(x.ticket);
+            }
+            inflight.push_back(r);
+        }
+        CHECK(b.used() <= budget);
+    }
+    for (auto &r : inflight) {
+        for (uint64_t t : r.tickets) {
+            Out &o = outs[t];
+            for (int k = 0; k < 64; ++k) o.words[k] = fake_result(o.input, k);
+            o.written = true;
+        }
+        b.finish(r.tickets, ENSEI_OK, 1e9);
+    }
+    while (b.queued()) {  // drain what is left, one batch at a time
+        auto a = b.admit(16, 2e9);
+        CHECK(!a.empty());
+        std::vector<uint64_t> ts;
+        for (const Admitted &x : a) {
+            Out &o = outs[x.ticket];
+            for (int k = 0; k < 64; ++k) o.words[k] = fake_result(o.input, k);
+            o.written = true;
+            ts.push_back(x.ticket);
+        }
+        b.finish(ts, ENSEI_OK, 2e9);
+    }
+    int done = 0;
+    for (auto &kv : outs) {
+        const Ticket *k = b.find(kv.first);
+        CHECK(k != nullptr && k->state >= kDone);
+        if (cancelled_queued.count(kv.first)) {
+            CHECK(k->state == kCancelled && !kv.second.written);
+            continue;
+        }
+        if (k->state == kDone) {
+            ++done;
+            for (int i = 0; i < 64; ++i) CHECK(kv.second.words[i] == fake_result(kv.second.input, i));
+        } else {
+            CHECK(k->state == kCancelled);  // cancelled while running: ran, reported cancelled
+        }
+    }
+    CHECK(b.used() == 0 && b.arena().free_blocks() == 1 && b.queued_bytes() == 0);
+    CHECK(refused > 0 && cancels > 0 && done > 1000);
+}
+
 int main() {
     arena_basics();
     arena_fragmentation();
     batches_in_arrival_order();
     batch_size_limit();
     random_stress();
+    book_budget();
+    book_cancel();
+    book_fake_executor();
     printf("%s\n", failures ? "sched checks FAILED" : "sched checks ok");
     return failures ? 1 : 0;
 }

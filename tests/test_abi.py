@@ -1,4 +1,5 @@
-"""The C-ABI library loads and exports every symbol include/ensei.h declares (no GPU)."""
+"""The C-ABI library loads and exports every symbol include/ensei.h declares,
+and the comparison library every symbol of include/ensei_bench.h (no GPU)."""
 import ctypes
 import os
 import re
@@ -10,10 +11,11 @@ from paper_2003_05328_amd import ensei
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ensei.h")
+BENCH_HEADER = os.path.join(ROOT, "include", "ensei_bench.h")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(ensei_[a-z0-9_]+)\s*\(", text)))
 
@@ -38,6 +40,22 @@ def test_every_declared_symbol_is_exported(lib):
         assert hasattr(lib, name), name
         assert name in ensei.SIGNATURES, f"binding lacks {name}"
     assert set(ensei.SIGNATURES) == set(declared_functions())
+
+
+def test_bench_library_exports_its_header(lib):
+    names = declared_functions(BENCH_HEADER)
+    assert names == sorted(ensei.BENCH_SIGNATURES)
+    bl = ensei.bench_lib()
+    for name in names:
+        assert hasattr(bl, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", ensei.BENCH_LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert set(names) <= exported
+    # the comparison kernel is not part of the product library
+    prod = subprocess.run(["nm", "-D", "--defined-only", ensei.LIB_PATH], capture_output=True, text=True,
+                          check=True).stdout
+    assert "homconv_valu" not in prod
 
 
 def test_exports_are_unmangled_c_symbols(lib):
@@ -94,16 +112,20 @@ def test_server_host_checks(lib):
     assert lib.ensei_request_bytes(ctypes.byref(sh)) == al(F * 64 * 4) + 2 * al(F * 1025 * 64 * 8) + al(F * 64 * 4)
     sh.n = 0
     assert lib.ensei_request_bytes(ctypes.byref(sh)) == 0
-    assert ctypes.sizeof(ensei.RequestDesc) == 7 * 8
+    assert ctypes.sizeof(ensei.RequestDesc) == 8 * 8
     assert ctypes.sizeof(ensei.RequestInfo) == 8 + 3 * 8
-    assert ctypes.sizeof(ensei.ServerInfo) == 8 * 8
+    assert ctypes.sizeof(ensei.ServerInfo) == 10 * 8
+    assert lib.ensei_server_cancel(None, 1) == -1
+    assert lib.ensei_server_set_queue_limit(None, 0) == -1
+    assert lib.ensei_server_clock(None, None) == -1
+    assert lib.ensei_ctx_device(None) == -1
 
 
 def test_plan_structs_match_the_header():
     # ensei_layer: 7 ints, int64 batch, uint64 seed_a, 11 pointers
     assert ctypes.sizeof(ensei.LayerDesc) == 7 * 4 + 4 + 8 + 8 + 11 * 8
     assert ensei.LayerDesc.batch.offset == 32 and ensei.LayerDesc.w.offset == 48
-    assert ctypes.sizeof(ensei.ScheduleDesc) == 24
+    assert ctypes.sizeof(ensei.ScheduleDesc) == 32
 
 
 def test_modulus_rejected_before_device_use(lib):

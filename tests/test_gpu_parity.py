@@ -410,7 +410,10 @@ FULL = [
     "conv64x64(56)_c64to64_k3_n1024",
     "conv128x128_c3to64_k7_n1024",
     "stack8_L1_32x32_c3to64",
+    "stack8_L2_32x32_c64to64",
+    "stack8_L3_16x16_c64to128",
     "stack8_L4_16x16_c128to128",
+    "stack8_L5_8x8_c128to256",
     "stack8_L6_8x8_c256to256",
     "stack8_L7_4x4_c256to512",
     "stack8bin_L5_8x8_c128to256",
@@ -445,3 +448,21 @@ def test_full_size_layer(ctx, orc, name):
     # the two shares reconstruct the cyclic convolution
     y = (host(got["s_a"]).astype(np.int64) + host(got["s_b"])) % P
     assert np.array_equal(y, orc.cyclic_conv(inp.x, inp.w, P))
+
+
+@pytest.mark.parametrize("name", ["conv32x32_c64to64_k3_n1024", "conv64x64(56)_c64to64_k3_n1024"])
+def test_full_size_ciphertexts_elementwise(ctx, orc, name):
+    """At full size, every word of ct_in and of ct_out equals the oracle's
+    (its Enc and HomConv over the whole layer), with the exact decryptions."""
+    S = configs.WORKLOADS[name]
+    inp = synth.generate(S, P, seed=2)
+    got = _gpu_round0(ctx, inp)
+    x_hat = orc.ntt2d(inp.x, P).reshape(S.B, S.Cin, S.F)
+    w_hat = orc.weight_prep(inp.w, S.H, S.W, P)
+    ct_in = orc.encrypt(x_hat, inp.s, inp.e, inp.seed_a, P)
+    assert np.array_equal(host(got["ct_in"]), ct_in)
+    del got["ct_in"]
+    ct_out = orc.homconv(ct_in, w_hat, inp.r, P)
+    del ct_in
+    assert np.array_equal(host(got["ct_out"]), ct_out)
+    assert np.array_equal(host(got["m"]), orc.decrypt(ct_out, inp.s, P))

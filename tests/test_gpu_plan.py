@@ -150,12 +150,16 @@ def test_plan_replays_see_new_inputs(ctx, orc, tmp_path):
     plan.close()
 
 
-# seeded plan: a narrow layer, a deep one and two in the shared launch
+# seeded plan: a narrow layer, two deep ones (seeded input with several row
+# tiles takes the deep kernel) and three layers of one row tile in the shared
+# launch
 STACK_SEEDED = [
     LayerShape(H=8, W=8, Cin=3, Cout=16, kh=3, kw=3, n=70, B=2),
     LayerShape(H=4, W=8, Cin=130, Cout=130, kh=3, kw=3, n=64, B=1),
     LayerShape(H=16, W=16, Cin=64, Cout=64, kh=3, kw=3, n=100, B=2, hidden=True),
     LayerShape(H=8, W=8, Cin=48, Cout=70, kh=3, kw=3, n=40, B=1),
+    LayerShape(H=8, W=4, Cin=16, Cout=32, kh=3, kw=3, n=33, B=2),
+    LayerShape(H=4, W=4, Cin=64, Cout=48, kh=3, kw=3, n=129, B=1),
 ]
 
 
@@ -174,6 +178,8 @@ def test_seeded_plan_matches_single_calls(ctx, orc, tmp_path, chunk):
     plan = Plan(ctx, [l for _, l in layers], tune_cache=str(cache), seeded=True)
     if chunk is not None:
         assert plan.schedule()["chunk"] == chunk
+    # the seeded multi-problem kernel runs with three problems
+    assert plan.schedule()["shared_layers"] == 3 and plan.schedule()["own_layers"] == 3
     for _ in range(2):  # the captured graph replays
         plan.run()
         torch.cuda.synchronize()
@@ -185,4 +191,52 @@ def test_seeded_plan_matches_single_calls(ctx, orc, tmp_path, chunk):
             conv = orc.cyclic_conv(inp.x, inp.w, P)
             shares = (host(l["s_a"]).astype(np.int64) + host(l["s_b"])) % P
             assert np.array_equal(shares.reshape(conv.shape), conv)
+    plan.close()
+
+
+def test_plan_inputs_from_pending_work(ctx, orc, tmp_path):
+    """Filters and inputs still being written by work queued on the current
+    stream when the plan is created: creation waits for it, so the plan's
+    first run and its filters match the single calls on the final values."""
+    layers = [_layer(ctx, S, 700 + i) for i, S in enumerate(STACK)]
+    final = {}
+    torch.cuda.synchronize()
+    for i, (inp, l) in enumerate(layers):
+        for k in ("w", "x", "e", "r"):
+            final[(i, k)] = l[k].clone()
+    torch.cuda.synchronize()
+    for i, (inp, l) in enumerate(layers):
+        for k in ("w", "x", "e", "r"):
+            l[k].zero_()
+    torch.cuda._sleep(int(40e-3 * 2.4e9))  # a spin that always ends
+    for i, (inp, l) in enumerate(layers):
+        for k in ("w", "x", "e", "r"):
+            l[k].copy_(final[(i, k)])  # queued behind the spin
+    plan = Plan(ctx, [l for _, l in layers], tune_cache=str(tmp_path / "t.txt"))
+    plan.run()
+    torch.cuda.synchronize()
+    for S, (inp, l) in zip(STACK, layers):
+        _check_layer(orc, S, inp, l, _single_calls(ctx, S, l))
+    plan.close()
+
+
+def test_plan_stages_equal_a_run(ctx, orc, tmp_path):
+    """Stages 0, 1, 2 enqueued one by one give exactly what one run gives."""
+    layers = [_layer(ctx, S, 800 + i) for i, S in enumerate(STACK)]
+    plan = Plan(ctx, [l for _, l in layers], tune_cache=str(tmp_path / "t.txt"))
+    plan.run()
+    torch.cuda.synchronize()
+    ref = [{k: l[k].clone() for k in Plan._OUTPUTS} for _, l in layers]
+    for _, l in layers:
+        for k in Plan._OUTPUTS:
+            l[k].zero_()
+    for stage in range(3):
+        plan.run_stage(stage)
+    torch.cuda.synchronize()
+    for (_, l), rf in zip(layers, ref):
+        for k in Plan._OUTPUTS:
+            assert torch.equal(l[k], rf[k]), k
+    from paper_2003_05328_amd.ensei import EnseiError
+    with pytest.raises(EnseiError, match="ARG"):
+        plan.run_stage(3)
     plan.close()

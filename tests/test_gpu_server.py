@@ -22,6 +22,9 @@ SHAPES = [
     LayerShape(H=4, W=8, Cin=130, Cout=17, kh=2, kw=3, n=33),
     LayerShape(H=32, W=32, Cin=5, Cout=32, kh=5, kw=5, n=129),
     LayerShape(H=4, W=4, Cin=130, Cout=130, kh=3, kw=3, n=33),
+    # a second shape of the shared persistent launch (one row tile, Cin > 8),
+    # so that seeded and unseeded batches hold two of them
+    LayerShape(H=8, W=8, Cin=64, Cout=48, kh=3, kw=3, n=40),
 ]
 
 
@@ -43,9 +46,11 @@ def _alone(ctx, S, inp, w):
     return host(ctx.intt2d(m[0], S.H, S.W)), host(ctx.server_share(r[0], S.H, S.W))
 
 
-def _setup(ctx, server, n_inputs=3):
+def _setup(ctx, server, n_inputs=3, only=None):
     shapes = []
     for k, S in enumerate(SHAPES):
+        if only is not None and k not in only:
+            continue
         base = synth.generate(S, P, 500 + k)
         w = dev(base.w)
         sid = server.add_shape(S.H, S.W, S.Cin, S.Cout, S.kh, S.kw, S.n, w)
@@ -160,10 +165,123 @@ def test_server_errors(ctx):
     S = SHAPES[1]
     small = Server(ctx, 1 << 16, nstreams=1, max_batch=1)
     w = dev(synth.generate(S, P, 1).w)
-    with pytest.raises(EnseiError, match="LIMIT"):
+    with pytest.raises(EnseiError, match="BUDGET"):
         small.add_shape(S.H, S.W, S.Cin, S.Cout, S.kh, S.kw, S.n, w)
     with pytest.raises(EnseiError, match="SHAPE"):
         Server(ctx, 1 << 30).add_shape(12, 8, S.Cin, S.Cout, S.kh, S.kw, S.n, w)
     with pytest.raises(EnseiError, match="ARG"):
         small.poll(12345)
     small.close()
+
+
+def _hold_stream(ms=40):
+    """Queues a spin of about `ms` on the current stream, so that work queued
+    after it (and a request ordered after it) starts later."""
+    torch.cuda._sleep(int(ms * 1e-3 * 2.4e9))  # cycles of a spin kernel that always ends
+
+
+def test_cancel(ctx):
+    """A queued request cancelled while the head of the queue waits for space:
+    it never runs, its outputs stay untouched, the request behind it is
+    admitted in its place; a running request marked cancelled finishes on the
+    device and releases its budget; a finished request cannot be cancelled;
+    the other requests give exactly what they give alone."""
+    big, small_s = SHAPES[1], SHAPES[0]
+    nb = Server.request_bytes(big.H, big.W, big.Cin, big.Cout, big.kh, big.kw, big.n)
+    ns = Server.request_bytes(small_s.H, small_s.W, small_s.Cin, small_s.Cout, small_s.kh, small_s.kw, small_s.n)
+    server = Server(ctx, nb + nb // 2 + ns + 4096, nstreams=2, max_batch=1)
+    shapes = _setup(ctx, server, n_inputs=1, only=(0, 1))
+    (Sb, sid_b, _, sets_b), (Ss, sid_s, _, sets_s) = shapes[1], shapes[0]
+    torch.cuda.synchronize()
+    _hold_stream(60)  # A's kernels wait for this spin on the submitting stream
+    tA, aA, bA = _submit(server, Sb, sid_b, sets_b[0][1])
+    tB, aB, bB = _submit(server, Sb, sid_b, sets_b[0][1])  # does not fit beside A: waits at the head
+    tC, aC, bC = _submit(server, Ss, sid_s, sets_s[0][1])  # fits, but may not overtake B
+    aB.fill_(7)
+    bB.fill_(7)
+    assert server.poll(tB)["state"] == "queued" and server.poll(tC)["state"] == "queued"
+    server.cancel(tB)
+    assert server.poll(tB)["state"] == "cancelled"
+    with pytest.raises(EnseiError, match="CANCELLED"):
+        server.wait(tB)
+    server.wait(tC)  # admitted beside A once B left the queue
+    assert server.poll(tA)["state"] in ("running", "done")
+    assert np.array_equal(host(aC), sets_s[0][2][0]) and np.array_equal(host(bC), sets_s[0][2][1])
+    server.wait(tA)
+    assert np.array_equal(host(aA), sets_b[0][2][0]) and np.array_equal(host(bA), sets_b[0][2][1])
+    assert (host(aB) == 7).all() and (host(bB) == 7).all()  # B never ran
+    # cancelling a request while it runs: it finishes, releases its budget, reports cancelled
+    _hold_stream(40)
+    tD, aD, bD = _submit(server, Sb, sid_b, sets_b[0][1])
+    for _ in range(2000):
+        if server.poll(tD)["state"] != "queued":
+            break
+    assert server.poll(tD)["state"] == "running"
+    server.cancel(tD)
+    with pytest.raises(EnseiError, match="CANCELLED"):
+        server.wait(tD)
+    assert server.poll(tD)["state"] == "cancelled"
+    with pytest.raises(EnseiError, match="STATE"):
+        server.cancel(tA)
+    with pytest.raises(EnseiError, match="ARG"):
+        server.cancel(123456)
+    st = server.stats()
+    assert st["used_bytes"] == 0 and st["cancelled"] == 2 and st["completed"] == 2  # A and C
+    # the server goes on serving normally
+    tE, aE, bE = _submit(server, Sb, sid_b, sets_b[0][1])
+    server.wait(tE)
+    assert np.array_equal(host(aE), sets_b[0][2][0]) and np.array_equal(host(bE), sets_b[0][2][1])
+    server.close()
+
+
+def test_budget_refusal(ctx):
+    """Submits past the queue limit are refused with ENSEI_ERR_BUDGET and
+    queue nothing; the accepted ones complete exactly."""
+    S = SHAPES[1]
+    nb = Server.request_bytes(S.H, S.W, S.Cin, S.Cout, S.kh, S.kw, S.n)
+    server = Server(ctx, nb + 1024, nstreams=1, max_batch=1)
+    shapes = _setup(ctx, server, n_inputs=1, only=(1,))
+    _, sid, _, sets = shapes[0]
+    server.set_queue_limit(2 * nb + 1024)  # two requests may wait for admission
+    torch.cuda.synchronize()
+    _hold_stream(60)
+    subs = [_submit(server, S, sid, sets[0][1])]  # admitted at once (held by the spin)
+    for _ in range(200):
+        if server.poll(subs[0][0])["state"] != "queued":
+            break
+    subs += [_submit(server, S, sid, sets[0][1]) for _ in range(2)]
+    with pytest.raises(EnseiError, match="BUDGET"):
+        _submit(server, S, sid, sets[0][1])
+    assert server.stats()["refused"] == 1 and server.stats()["queued"] == 2
+    for t, s_a, s_b in subs:
+        server.wait(t)
+        assert np.array_equal(host(s_a), sets[0][2][0]) and np.array_equal(host(s_b), sets[0][2][1])
+    server.set_queue_limit(0)
+    server.close()
+
+
+def test_inputs_from_pending_work(ctx):
+    """Inputs still being written by work queued on the submitting stream (and
+    filters still being written when a shape is added): the server's kernels
+    run after that work, so results equal the single calls'."""
+    S = SHAPES[1]
+    server = Server(ctx, 1 << 30, nstreams=2, max_batch=4)
+    inp = synth.generate(S, P, 4242)
+    w_src = dev(inp.w)
+    torch.cuda.synchronize()
+    w = torch.zeros_like(w_src)
+    _hold_stream(40)
+    w.copy_(w_src)  # still pending when add_shape reads w
+    sid = server.add_shape(S.H, S.W, S.Cin, S.Cout, S.kh, S.kw, S.n, w)
+    ref = _alone(ctx, S, inp, w_src)
+    srcs = {"x": dev(inp.x[0]), "s": dev(inp.s), "e": dev(inp.e[0]), "r": dev(inp.r[0])}
+    torch.cuda.synchronize()
+    io = {k: torch.zeros_like(v) for k, v in srcs.items()}
+    io["seed_a"] = inp.seed_a
+    _hold_stream(40)
+    for k in srcs:
+        io[k].copy_(srcs[k])  # queued behind the spin
+    t, s_a, s_b = _submit(server, S, sid, io)
+    server.wait(t)
+    assert np.array_equal(host(s_a), ref[0]) and np.array_equal(host(s_b), ref[1])
+    server.close()

@@ -35,6 +35,6 @@ def test_oracle_under_sanitizers(tmp_path):
 def test_scheduler_under_sanitizers(tmp_path):
     exe = tmp_path / "sched_driver_san"
     subprocess.run(["g++", "-std=c++17", *SAN, "-pthread", "-Wall", "-Wextra", "-Werror",
-                    "-I", os.path.join(ROOT, "paper_2003_05328_amd", "csrc"),
+                    "-I", os.path.join(ROOT, "paper_2003_05328_amd", "csrc"), "-I", os.path.join(ROOT, "include"),
                     os.path.join(ROOT, "tests", "sched_driver.cpp"), "-o", str(exe)], check=True)
     _run(exe, "sched checks ok")
