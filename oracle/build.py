@@ -1,4 +1,5 @@
-"""Builds the CPU oracle (test infrastructure) into oracle/libensei_oracle.so."""
+"""Builds the CPU oracles (test infrastructure): oracle/libensei_oracle.so and
+oracle/libensei_bfv_oracle.so."""
 from __future__ import annotations
 
 import os
@@ -16,6 +17,10 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    # the packed (BFV / RLWE) instantiation's oracle
+    from oracle import bfv
+
+    bfv.build(verbose=verbose)
     return LIB
 
 

@@ -31,9 +31,11 @@ STACK_LAYERS = [
 
 
 def stack_shapes(binary: bool = False, B: int = 8) -> list[LayerShape]:
+    """The stack's layers: pixels in [0, 255] into the first, residues
+    uniform in [0, p) (hidden activations) into the others."""
     return [
-        LayerShape(H=hw, W=hw, Cin=ci, Cout=co, kh=3, kw=3, n=1024, B=B, binary=binary)
-        for (ci, co, hw) in STACK_LAYERS
+        LayerShape(H=hw, W=hw, Cin=ci, Cout=co, kh=3, kw=3, n=1024, B=B, binary=binary, hidden=k > 0)
+        for k, (ci, co, hw) in enumerate(STACK_LAYERS)
     ]
 
 
