@@ -40,6 +40,8 @@ _SIG = {
     "bo_filters": (None, [u64, u64, u64, i32, i32, i64, i32, vp, vp]),
     "bo_homconv": (None, [u64, u64, i64, i32, i32, i32, i32, vp, vp, vp, vp]),
     "bo_fold": (None, [u64, i64, i32, i64, i32, vp, vp]),
+    "bo_rerand_draws": (None, [u64, u64, i32, i64, C.c_uint32, vp]),
+    "bo_rerandomize": (None, [u64, u64, i32, i64, vp, vp, u64, u64, C.c_uint32]),
     "bo_set_threads": (C.c_int, [C.c_int]),
 }
 
@@ -73,7 +75,7 @@ class Params:
 
     @property
     def delta(self) -> int:
-        return self.q // self.t
+        return (self.q + self.t // 2) // self.t
 
     def __repr__(self):
         return f"Params({self.name}, t={self.t}, q={self.q0}*{self.q1}, n={self.n})"
@@ -203,6 +205,21 @@ class BfvOracle:
         y = np.empty((B, Cout, F), dtype=np.uint32)
         self.lib.bo_fold(pr.t, B, Cout, F, pr.n, _p(v), _p(y))
         return y
+
+    def rerand_draws(self, pr: Params, count: int, seed_r: int, flood: int, ct_index0: int = 0) -> np.ndarray:
+        """The server's draws for re-randomising `count` ciphertexts: int32 [count][3][n] (rho, e1, e2)."""
+        out = np.empty((count, 3, pr.n), dtype=np.int32)
+        self.lib.bo_rerand_draws(seed_r % 2**64, ct_index0 % 2**64, pr.n, count, flood, _p(out))
+        return out
+
+    def rerandomize(self, pr: Params, ct, pk, seed_r: int, flood: int, ct_index0: int = 0) -> np.ndarray:
+        """ct[..., L, 2, n] plus a fresh public-key encryption of zero each (a new array)."""
+        ct = np.array(ct, dtype=np.uint32, copy=True, order="C")
+        pk = _c(pk, np.uint32)
+        assert pk.shape == (L, 2, pr.n)
+        count = ct.size // (L * 2 * pr.n)
+        self.lib.bo_rerandomize(pr.q0, pr.q1, pr.n, count, _p(ct), _p(pk), seed_r % 2**64, ct_index0 % 2**64, flood)
+        return ct
 
     def secure_conv(self, pr: Params, x_hat, w_hat, r, s, e, seed_a: int):
         """The packed start round of Fig. 2 on spectra: x_hat[B][Cin][F],

@@ -15,7 +15,10 @@
  *     X^n + 1 splits mod t and a plaintext holds n slots (Sec. 3.1 packing);
  *     the image transform and the shares use the same t;
  *   - ciphertext modulus q = q_0 q_1, two primes q_l = 1 mod 2n (residue
- *     number system), Delta = floor(q / t) (Eq. (bfv_enc), q / p_E);
+ *     number system), Delta = q / t rounded to the nearest integer (Eq.
+ *     (bfv_enc) writes q / p_E, which is not an integer; with the limbs
+ *     chosen for a small centred q mod t, Delta t = q - rho with |rho| small,
+ *     and rho is what multiplies the wrap term of a plaintext product);
  *   - psi_m = g^((m - 1) / 2n) for g the smallest primitive root of the prime
  *     m: a primitive 2n-th root of unity, psi^n = -1;
  *   - the negacyclic transform of a length-n vector mod m evaluates its
@@ -131,9 +134,9 @@ void bo_negacyclic(uint64_t m, int n, int64_t batch, const uint32_t *in, uint32_
     free(pw);
 }
 
-/* q = q0 q1 and Delta = floor(q / t). */
+/* q = q0 q1 and Delta = the integer nearest to q / t (t is odd: no ties). */
 static u128 modulus_q(const uint64_t *qs) { return (u128)qs[0] * qs[1]; }
-static u128 delta_q(uint64_t t, const uint64_t *qs) { return modulus_q(qs) / t; }
+static u128 delta_q(uint64_t t, const uint64_t *qs) { return (modulus_q(qs) + t / 2) / t; }
 
 /* Delta mod q_l for l < 2 (host helper for callers). */
 uint64_t bo_delta_mod(uint64_t t, uint64_t q0, uint64_t q1, int l) {
@@ -335,6 +338,61 @@ void bo_fold(uint64_t t, int64_t B, int Cout, int64_t F, int n, const uint32_t *
                 for (int64_t j = 0; j < P; ++j) acc += v[((b * Cout + o) * K + k) * n + j * Fp + f % Fp];
                 y[(b * Cout + o) * F + f] = (uint32_t)(acc % t);
             }
+}
+
+/* ------------------------------------------------- circuit privacy --- */
+
+/* The server's randomness for re-randomising output ciphertext c0 + i
+ * (i < count): for w = 0 (rho), 1 (e1), 2 (e2) and coefficient j,
+ * z = SplitMix64 output ((c0 + i) 3 + w) n + j + 1 of seed_r, and the draw is
+ * floor(hi32(z) (2 B + 1) / 2^32) - B with B = 1, E1_BOUND, flood for
+ * w = 0, 1, 2 (a ternary rho, a small e1, the flooding e2). draws:
+ * int32 [count][3][n]. */
+#define E1_BOUND 16
+void bo_rerand_draws(uint64_t seed_r, uint64_t ct_index0, int n, int64_t count, uint32_t flood, int32_t *draws) {
+    for (int64_t i = 0; i < count; ++i)
+        for (int w = 0; w < 3; ++w) {
+            const uint64_t B = w == 0 ? 1 : w == 1 ? E1_BOUND : flood;
+            for (int j = 0; j < n; ++j) {
+                const uint64_t z = bo_splitmix64(seed_r, ((ct_index0 + (uint64_t)i) * 3 + (uint64_t)w) * (uint64_t)n +
+                                                             (uint64_t)j + 1);
+                draws[(i * 3 + w) * n + j] = (int32_t)((int64_t)(((z >> 32) * (2 * B + 1)) >> 32) - (int64_t)B);
+            }
+        }
+}
+
+/* Circuit privacy by re-randomisation (the paper defers it to Gazelle, Sec.
+ * 4.1): every ciphertext of ct[count][L][2][n] gains a fresh public-key
+ * encryption of zero, (a^_pk rho^ + e1^, b^_pk rho^ + e2^), with the
+ * client's public key pk[L][2][n] (an encryption of zero under s:
+ * b^_pk = a^_pk s^ + NTT(e_pk)) and the draws of bo_rerand_draws, each
+ * transformed per limb. The message is unchanged; the a^ word becomes a fresh
+ * RLWE sample, and e2 floods the noise. In place. */
+void bo_rerandomize(uint64_t q0, uint64_t q1, int n, int64_t count, uint32_t *ct, const uint32_t *pk, uint64_t seed_r,
+                    uint64_t ct_index0, uint32_t flood) {
+    const uint64_t qs[NLIMB] = {q0, q1};
+    int32_t *dr = malloc((size_t)count * 3 * n * sizeof *dr);
+    uint32_t *c = malloc((size_t)count * 3 * n * sizeof *c);
+    uint32_t *h = malloc((size_t)count * 3 * n * sizeof *h);
+    bo_rerand_draws(seed_r, ct_index0, n, count, flood, dr);
+    for (int l = 0; l < NLIMB; ++l) {
+        const uint64_t m = qs[l];
+        for (int64_t i = 0; i < count * 3 * n; ++i)
+            c[i] = (uint32_t)(dr[i] < 0 ? m - (uint64_t)(-(int64_t)dr[i]) % m : (uint64_t)dr[i] % m) % m;
+        bo_negacyclic(m, n, count * 3, c, h, 0);
+        const uint32_t *pa = pk + (l * 2) * (int64_t)n, *pb = pa + n;
+        for (int64_t i = 0; i < count; ++i) {
+            uint32_t *wa = ct + ((i * NLIMB + l) * 2) * (int64_t)n, *wb = wa + n;
+            const uint32_t *rho = h + (i * 3) * (int64_t)n, *e1 = rho + n, *e2 = e1 + n;
+            for (int k = 0; k < n; ++k) {
+                wa[k] = (uint32_t)((wa[k] + mulm(pa[k], rho[k], m) + e1[k]) % m);
+                wb[k] = (uint32_t)((wb[k] + mulm(pb[k], rho[k], m) + e2[k]) % m);
+            }
+        }
+    }
+    free(dr);
+    free(c);
+    free(h);
 }
 
 int bo_set_threads(int k);

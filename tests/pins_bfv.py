@@ -6,7 +6,7 @@ disagreement with: Table 2's printed moduli and bit lengths, brute-force
 searches and closed forms in Python integers, schoolbook negacyclic products
 (numpy integer convolutions), a big-integer SplitMix64, Python big-integer
 CRT and Delta, and the exact noise identity of a plaintext-ciphertext product
-derived from Delta t = q - (q mod t). ``tests/test_bfv_oracle.py`` runs them;
+derived from Delta t = q - rho. ``tests/test_bfv_oracle.py`` runs them;
 ``tests/test_bfv_mutants.py`` plants mistakes in copies of the C oracle.
 """
 from __future__ import annotations
@@ -27,6 +27,13 @@ TOY = bfv.Params("toy", 257, 1073692673, 561770497, 64)
 
 def _rng(seed):
     return np.random.default_rng(seed)
+
+
+def _delta(pr) -> int:
+    """Delta: the integer nearest to q / t (exact rationals)."""
+    from fractions import Fraction
+
+    return int(Fraction(pr.q, pr.t) + Fraction(1, 2))
 
 
 def _sets():
@@ -183,7 +190,7 @@ def check_enc_phase_exact(orc):
                 a, b = ct[i, l, 0].astype(object), ct[i, l, 1].astype(object)
                 res.append(orc.negacyclic(np.array([(bb - aa * ss) % m for aa, bb, ss in zip(a, b, s_hat)],
                                                    dtype=np.int64), m, inverse=True))
-            want = [(pr.delta * int(uu) + int(ee)) % pr.q for uu, ee in zip(u[i], e[i])]
+            want = [(_delta(pr) * int(uu) + int(ee)) % pr.q for uu, ee in zip(u[i], e[i])]
             assert _crt(res[0], res[1], pr.q0, pr.q1) == want
             assert [int(x) for x in phi[i]] == want
 
@@ -209,7 +216,7 @@ def check_decryption_rounding(orc):
     pr = TOY
     s = np.zeros(pr.n, dtype=np.int8)
     g = _rng(5)
-    phis = [0, pr.delta // 2, pr.delta // 2 + 1, pr.q - 1, pr.q - pr.delta // 2 - 1, 3 * pr.delta + pr.delta // 2]
+    phis = [0, _delta(pr) // 2, _delta(pr) // 2 + 1, pr.q - 1, pr.q - _delta(pr) // 2 - 1, 3 * _delta(pr) + _delta(pr) // 2]
     phis += [int(x) for x in g.integers(0, pr.q, size=pr.n - len(phis))]
     ct = np.zeros((L, 2, pr.n), dtype=np.uint32)
     for l, m in enumerate((pr.q0, pr.q1)):
@@ -299,8 +306,9 @@ def check_homconv_noise_identity(orc):
     """The exact phase of an output ciphertext. With w_g the centred lift of
     INTT_t of filter vector g, u_g = INTT_t(v_g) and u_r = INTT_t(r) in
     [0, t), and M = sum_g w_g u_g + u_r in Z[X]/(X^n+1):
-        phi_out = Delta [M]_t + (sum_g w_g e_g - (q mod t) floor(M / t))  (mod q)
-    since Delta t = q - (q mod t). Checked coefficient by coefficient."""
+        phi_out = Delta [M]_t + (sum_g w_g e_g - rho floor(M / t))  (mod q)
+    since Delta t = q - rho (rho = q - Delta t, small and of either sign).
+    Checked coefficient by coefficient."""
     pr = TOY
     x_hat, w_hat, r, s, e, res = _conv_case(orc, pr, 1, 10, 2, 16, 40)
     P, K, G = bfv.shape_counts(10, 16, pr.n)
@@ -314,7 +322,7 @@ def check_homconv_noise_identity(orc):
             wv[o, c // P, (c % P) * 16:(c % P) * 16 + 16] = w_hat[o, c]
     wc = orc.negacyclic(wv, pr.t, inverse=True).astype(np.int64)
     wc = np.where(wc > pr.t // 2, wc - pr.t, wc)  # centred
-    rq = pr.q % pr.t
+    rq = pr.q - _delta(pr) * pr.t
     for o in range(2):
         M = np.array(ur[0, o], dtype=object)
         noise = np.zeros(pr.n, dtype=object)
@@ -323,7 +331,7 @@ def check_homconv_noise_identity(orc):
             noise = noise + np.array(negacyclic_product_z(wc[o, gi], e[0, gi]), dtype=object)
         for k in range(pr.n):
             Mk = int(M[k])
-            want = (pr.delta * (Mk % pr.t) + int(noise[k]) - rq * (Mk // pr.t)) % pr.q
+            want = (_delta(pr) * (Mk % pr.t) + int(noise[k]) - rq * (Mk // pr.t)) % pr.q
             assert int(phi[0, o, k]) == want, (o, k)
 
 
@@ -348,7 +356,70 @@ def check_homconv_words(orc):
     ur = orc.negacyclic(r, pr.t, inverse=True)
     for l, m in enumerate((pr.q0, pr.q1)):
         coeff = orc.negacyclic(me[0, 0, l], m, inverse=True)
-        assert [int(x) for x in coeff] == [pr.delta * int(v) % m for v in ur[0, 0]]
+        assert [int(x) for x in coeff] == [_delta(pr) * int(v) % m for v in ur[0, 0]]
+
+
+# ---------------------------------------------------- circuit privacy ---
+
+
+def check_rerandomize_draws(orc):
+    """The server's draws: output ((c0 + i) 3 + w) n + j + 1 of a big-integer
+    SplitMix64, mapped by floor(hi32 (2B + 1) / 2^32) - B; every value of the
+    ternary rho appears and the flooding e2 spans its range."""
+    pr, flood = TOY, 1000
+    d = orc.rerand_draws(pr, 3, seed_r=7, flood=flood, ct_index0=4)
+    stream = bf.splitmix64_stream(7, (4 + 3) * 3 * pr.n + 1)
+    for i in range(3):
+        for w, B in enumerate((1, 16, flood)):
+            for j in range(pr.n):
+                z = stream[((4 + i) * 3 + w) * pr.n + j]
+                assert int(d[i, w, j]) == (((z >> 32) * (2 * B + 1)) >> 32) - B
+    assert set(np.unique(d[:, 0])) == {-1, 0, 1}
+    assert np.abs(d[:, 1]).max() <= 16 and np.abs(d[:, 2]).max() <= flood
+    assert d[:, 2].max() > 0.8 * flood and d[:, 2].min() < -0.8 * flood
+
+
+def check_rerandomize_identity(orc):
+    """Re-randomising adds exactly a public-key encryption of zero: with
+    pk = Enc(0; e_pk) and draws (rho, e1, e2), the phase grows by
+    e_pk rho + e2 - e1 s (mod q) and the a^ word's coefficients by
+    a_pk rho + e1 (mod q_l), products in Z[X]/(X^n+1); the message stays."""
+    pr, flood = TOY, 5000
+    g = _rng(70)
+    s = g.integers(-1, 2, size=pr.n).astype(np.int8)
+    v = g.integers(0, pr.t, size=(2, pr.n))
+    e = np.rint(g.normal(0, 4.0, size=v.shape)).astype(np.int32)
+    e_pk = np.rint(g.normal(0, 4.0, size=(1, pr.n))).astype(np.int32)
+    pk = orc.encrypt(pr, np.zeros((1, pr.n), np.int64), s, e_pk, seed_a=71)[0]
+    ct = orc.encrypt(pr, v, s, e, seed_a=72)
+    out = orc.rerandomize(pr, ct, pk, seed_r=73, flood=flood, ct_index0=2)
+    d = orc.rerand_draws(pr, 2, seed_r=73, flood=flood, ct_index0=2)
+    phi0, phi1 = orc.phase(pr, ct, s), orc.phase(pr, out, s)
+    for i in range(2):
+        rho, e1, e2 = (d[i, w].astype(np.int64) for w in range(3))
+        grow = np.array(negacyclic_product_z(e_pk[0], rho), dtype=object) + e2.astype(object) - np.array(
+            negacyclic_product_z(e1, s.astype(np.int64)), dtype=object)
+        assert [(int(b) - int(a)) % pr.q for a, b in zip(phi0[i], phi1[i])] == [int(x) % pr.q for x in grow]
+        for l, m in enumerate((pr.q0, pr.q1)):
+            a_pk = orc.negacyclic(pk[l, 0], m, inverse=True)
+            da = orc.negacyclic(((out[i, l, 0].astype(np.int64) - ct[i, l, 0].astype(np.int64)) % m), m, inverse=True)
+            want = (negacyclic_product(a_pk, rho % m, m) + e1) % m
+            assert np.array_equal(da.astype(np.int64), want)
+    assert np.array_equal(orc.decrypt(pr, out, s), v)
+
+
+def check_rerandomize_table2(orc):
+    """Under Table 2's sets, re-randomising a HomConv output with the widest
+    flood that leaves room for the product's noise keeps the decryption."""
+    for pr in (_sets()[0], _sets()[2]):
+        x_hat, w_hat, r, s, e, res = _conv_case(orc, pr, 1, 3, 1, pr.n // 2, 80)
+        g = _rng(81)
+        pk = orc.encrypt(pr, np.zeros((1, pr.n), np.int64), s,
+                         np.rint(g.normal(0, 4.0, size=(1, pr.n))).astype(np.int32), seed_a=82)[0]
+        flood = min(_delta(pr) // 16, 2**30)
+        out = orc.rerandomize(pr, res["ct_out"], pk, seed_r=83, flood=flood)
+        assert np.array_equal(orc.decrypt(pr, out, s), res["v_out"])
+        assert not np.array_equal(out[..., 0, :], res["ct_out"][..., 0, :])
 
 
 # cheapest first (the mutant test stops at the first failing pin)
@@ -361,7 +432,10 @@ ALL_CHECKS = [
     check_public_constants,
     check_homconv_noise_identity,
     check_homconv_words,
+    check_rerandomize_draws,
+    check_rerandomize_identity,
     check_secure_conv_plaintext,
+    check_rerandomize_table2,
     check_roundtrip,
     check_convolution_theorem,
     check_enc_phase_exact,

@@ -21,9 +21,8 @@ MUTANTS = {
     "psi_of_order_n": ("return powm(primitive_root(m), (m - 1) / two_n, m);",
                        "return powm(primitive_root(m), (m - 1) / (uint64_t)n, m);"),
     "primitive_root_unchecked": ("        if (ok) return g;", "        return g;"),
-    "delta_rounded_up": ("return modulus_q(qs) / t; }", "return modulus_q(qs) / t + 1; }"),
-    "delta_of_one_limb": ("static u128 delta_q(uint64_t t, const uint64_t *qs) { return modulus_q(qs) / t; }",
-                          "static u128 delta_q(uint64_t t, const uint64_t *qs) { return qs[0] / t; }"),
+    "delta_floored": ("return (modulus_q(qs) + t / 2) / t; }", "return modulus_q(qs) / t; }"),
+    "delta_of_one_limb": ("return (modulus_q(qs) + t / 2) / t; }", "return ((u128)qs[0] + t / 2) / t; }"),
     "filters_lifted_canonically": ("            else if (x > t / 2)\n                x = m - (t - x);",
                                    "            else if (0)\n                x = m - (t - x);"),
     "enc_dropped_error": ("c[i] = (uint32_t)((mulm(dl, u[i], m) + ei) % m);", "c[i] = (uint32_t)(mulm(dl, u[i], m) % m);"),
@@ -49,6 +48,15 @@ MUTANTS = {
     "homconv_mask_on_a": ("if (w == 1) acc = (acc + mask_enc", "if (w == 0) acc = (acc + mask_enc"),
     "homconv_last_vector_dropped": ("for (int g = 0; g < G; ++g) {", "for (int g = 0; g + 1 < G; ++g) {"),
     "fold_one_block": ("for (int64_t j = 0; j < P; ++j) acc +=", "for (int64_t j = 0; j < 1; ++j) acc +="),
+    "rerand_counter_off_by_one": ("(uint64_t)n +\n                                                             (uint64_t)j + 1);",
+                                  "(uint64_t)n +\n                                                             (uint64_t)j);"),
+    "rerand_bound_not_doubled": ("(((z >> 32) * (2 * B + 1)) >> 32)", "(((z >> 32) * (B + 1)) >> 32)"),
+    "rerand_a_without_e1": ("wa[k] = (uint32_t)((wa[k] + mulm(pa[k], rho[k], m) + e1[k]) % m);",
+                            "wa[k] = (uint32_t)((wa[k] + mulm(pa[k], rho[k], m)) % m);"),
+    "rerand_b_with_a_key": ("wb[k] = (uint32_t)((wb[k] + mulm(pb[k], rho[k], m) + e2[k]) % m);",
+                            "wb[k] = (uint32_t)((wb[k] + mulm(pa[k], rho[k], m) + e2[k]) % m);"),
+    "rerand_flood_on_a": ("const uint32_t *rho = h + (i * 3) * (int64_t)n, *e1 = rho + n, *e2 = e1 + n;",
+                          "const uint32_t *rho = h + (i * 3) * (int64_t)n, *e2 = rho + n, *e1 = e2 + n;"),
     "mask_unscaled": ("            if (scaled)\n                x = mulm(dl, x, m);", "            if (scaled)\n                x = x;"),
 }
 
