@@ -15,6 +15,7 @@
 
 #include <chrono>
 #include <condition_variable>
+#include <algorithm>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -59,14 +60,15 @@ struct Job {
     ensei_request io;
     hipEvent_t ready;
     size_t off;
+    hipEvent_t done = nullptr;  // recorded after the request's last kernel
+    bool finished = false;
 };
 
 struct Batch {
-    std::vector<uint64_t> tickets;
     std::vector<Job> jobs;
     hipStream_t stream;
-    hipEvent_t done;
-    int slot;  // launch-table slot
+    int slot;  // launch-table slot, busy until every job of the batch has finished
+    int remaining = 0;
 };
 
 }  // namespace
@@ -86,7 +88,7 @@ struct ensei_server {
     // device copy and pinned host staging; a slot is busy while its batch runs
     HcLayer *d_tables = nullptr, *h_tables = nullptr;
     std::vector<int> free_slots;
-    std::vector<hipEvent_t> event_pool;  // batch completion
+    std::vector<hipEvent_t> event_pool;  // request completion
     std::vector<hipEvent_t> ready_pool;  // callers' input streams
 
     std::mutex mu;
@@ -130,10 +132,14 @@ Parts parts_of(const ensei_shape &d, bool seeded = false) {
 
 // Enqueues one batch. Called WITHOUT the server's lock: it reads only the
 // batch's own jobs, its launch-table slot and the arena memory of its
-// requests. Returns a status; on error nothing of the batch is left running
-// once its stream has been synchronised.
+// requests. The jobs run smallest first, and each request's completion event
+// follows its own last kernel, so that a small request does not wait for the
+// decryption of a large one. Returns a status; on error nothing of the batch
+// is left running once its stream has been synchronised.
 int launch_batch(ensei_server *S, Batch &b) {
     const hipStream_t st = b.stream;
+    std::stable_sort(b.jobs.begin(), b.jobs.end(),
+                     [](const Job &x, const Job &y) { return x.sh.footprint < y.sh.footprint; });
     HcLayer *tab = S->h_tables + (size_t)b.slot * S->max_batch;
     int np = 0;
     int64_t tile0 = 0;
@@ -178,7 +184,7 @@ int launch_batch(ensei_server *S, Batch &b) {
     } else if (!rc && np == 1) {
         rc = homconv_launch(S->ctx, tab, nullptr, 1, true, HcSchedule{0, 0}, st, S->seeded);
     }
-    for (const Job &j : b.jobs) {
+    for (Job &j : b.jobs) {
         if (rc) break;
         const Shape &sh = j.sh;
         const ensei_shape &d = sh.d;
@@ -189,42 +195,54 @@ int launch_batch(ensei_server *S, Batch &b) {
         rc = ensei_decrypt(S->ctx, ct_out, j.io.s, 1, d.Cout, sh.F, d.n, m, st);
         if (!rc) rc = ensei_intt2d(S->ctx, m, j.io.s_a, d.Cout, d.H, d.W, st);
         if (!rc) rc = ensei_server_share(S->ctx, j.io.r, j.io.s_b, d.Cout, d.H, d.W, st);
+        if (!rc && hipEventRecord(j.done, st) != hipSuccess) rc = ENSEI_ERR_HIP;
     }
-    if (!rc && hipEventRecord(b.done, st) != hipSuccess) rc = ENSEI_ERR_HIP;
     return rc;
 }
 
-// A batch has ended (caller holds the lock): the book releases its budget and
-// records the outcome; the batch's events return to their pools.
-void finish(ensei_server *S, Batch &b, int rc) {
-    S->book.finish(b.tickets, rc, now_s(S));
-    for (uint64_t t : b.tickets) {
-        const sched::Ticket *k = S->book.find(t);
-        if (k->state == sched::kDone)
-            ++S->n_done;
-        else if (k->state == sched::kFailed)
-            ++S->n_failed;
-    }
-    for (const Job &j : b.jobs)
-        if (j.ready) S->ready_pool.push_back(j.ready);
+// One request of a batch has ended (caller holds the lock): the book releases
+// its budget and records the outcome; its events return to their pools.
+void finish_job(ensei_server *S, Batch &b, Job &j, int rc) {
+    if (j.finished) return;
+    j.finished = true;
+    --b.remaining;
+    S->book.finish({j.ticket}, rc, now_s(S));
+    const sched::Ticket *k = S->book.find(j.ticket);
+    if (k->state == sched::kDone)
+        ++S->n_done;
+    else if (k->state == sched::kFailed)
+        ++S->n_failed;
+    if (j.ready) S->ready_pool.push_back(j.ready);
+    S->event_pool.push_back(j.done);
+}
+
+// Every request of the batch has ended: its launch-table slot is free again.
+void finish_batch(ensei_server *S, Batch &b, int rc) {
+    for (Job &j : b.jobs) finish_job(S, b, j, rc);
     S->free_slots.push_back(b.slot);
-    S->event_pool.push_back(b.done);
 }
 
 void worker_loop(ensei_server *S) {
     (void)hipSetDevice(S->ctx->device);
     std::unique_lock<std::mutex> lk(S->mu);
     while (true) {
-        // retire finished batches (in stream order per stream; check all)
+        // retire finished requests, and batches whose requests have all ended
         for (auto it = S->inflight.begin(); it != S->inflight.end();) {
-            const hipError_t q = hipEventQuery(it->done);
-            if (q == hipErrorNotReady) {
-                ++it;
-                continue;
+            bool any = false;
+            for (Job &j : it->jobs) {
+                if (j.finished) continue;
+                const hipError_t q = hipEventQuery(j.done);
+                if (q == hipErrorNotReady) break;  // later jobs of the stream come after it
+                finish_job(S, *it, j, q == hipSuccess ? ENSEI_OK : ENSEI_ERR_HIP);
+                any = true;
             }
-            finish(S, *it, q == hipSuccess ? ENSEI_OK : ENSEI_ERR_HIP);
-            it = S->inflight.erase(it);
-            S->cv_done.notify_all();
+            if (any) S->cv_done.notify_all();
+            if (it->remaining == 0) {
+                S->free_slots.push_back(it->slot);
+                it = S->inflight.erase(it);
+            } else {
+                ++it;
+            }
         }
         // admit queued requests in arrival order while they fit, one batch
         // per free launch slot
@@ -235,14 +253,15 @@ void worker_loop(ensei_server *S) {
             for (const sched::Admitted &a : admitted) {
                 auto pit = S->pending.find(a.ticket);
                 const int shape = S->book.find(a.ticket)->shape;
-                b.tickets.push_back(a.ticket);
-                b.jobs.push_back(Job{a.ticket, S->shapes[shape], pit->second.io, pit->second.ready, a.off});
+                Job j{a.ticket, S->shapes[shape], pit->second.io, pit->second.ready, a.off};
+                j.done = S->event_pool.back();
+                S->event_pool.pop_back();
+                b.jobs.push_back(j);
                 S->pending.erase(pit);
             }
+            b.remaining = (int)b.jobs.size();
             b.slot = S->free_slots.back();
             S->free_slots.pop_back();
-            b.done = S->event_pool.back();
-            S->event_pool.pop_back();
             b.stream = S->streams[S->next_stream];
             S->next_stream = (S->next_stream + 1) % S->nstreams;
             ++S->n_batches;
@@ -253,7 +272,7 @@ void worker_loop(ensei_server *S) {
             if (rc) (void)hipStreamSynchronize(b.stream);  // enqueued work must end before the memory is reused
             lk.lock();
             if (rc) {
-                finish(S, b, rc);
+                finish_batch(S, b, rc);
                 S->cv_done.notify_all();
             } else {
                 S->inflight.push_back(std::move(b));
@@ -335,13 +354,11 @@ static int server_create(ensei_ctx *ctx, size_t budget_bytes, int nstreams, int 
         ok = hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
         if (ok) S->streams.push_back(s);
     }
-    for (int i = 0; ok && i < slots; ++i) {
+    for (int i = 0; ok && i < slots; ++i) S->free_slots.push_back(slots - 1 - i);
+    for (int i = 0; ok && i < slots * max_batch; ++i) {  // one completion event per request in flight
         hipEvent_t e;
         ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
-        if (ok) {
-            S->event_pool.push_back(e);
-            S->free_slots.push_back(slots - 1 - i);
-        }
+        if (ok) S->event_pool.push_back(e);
     }
     (void)hipSetDevice(prev);
     if (!ok) {
