@@ -335,8 +335,12 @@ typedef struct ensei_layer {
 /* The HomConv schedule a plan runs: persistent workgroups, chunk (0 =
  * contiguous tile ranges, -1 = a launch per layer instead of the shared
  * one), the measured time of its HomConv launches in
- * microseconds (0 when taken from the cache), and whether it came from the
- * cache (1) or from tuning (0). Layers of at most 8 input channels, and
+ * microseconds (0 when taken from the cache), whether it came from the
+ * cache (1) or from tuning (0), and the capture form: the layers of each
+ * stage are independent, so they can run as concurrent branches of the
+ * graph (forked onto side streams of default priority and joined back);
+ * the plan replays both forms and keeps the faster, unless a cache line
+ * "key blocks chunk us branches" pins it. Layers of at most 8 input channels, and
  * layers with several 64-row output tiles and at most 256 input channels, run
  * on their own kernels after the shared persistent launch of the others; the
  * schedule concerns the shared launch (a plan of such layers only has nothing
@@ -348,6 +352,10 @@ typedef struct ensei_schedule {
     double homconv_us;
     int shared_layers;   /* layers in the shared persistent launch */
     int own_layers;      /* layers on a HomConv kernel of their own (narrow inputs, deep layers) */
+    int branches;        /* 1: each stage's layers run as concurrent graph branches, 0: in order */
+    int pad;
+    double serial_us;    /* measured replay of the plan with the layers in order (0 if not timed) */
+    double branches_us;  /* the same with concurrent branches (0 if not timed) */
 } ensei_schedule;
 
 /* Creates a plan for nlayers (1..ENSEI_MAX_PLAN_LAYERS) layers. Allocates the

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <utility>
 #include <vector>
@@ -26,6 +27,12 @@ struct ensei_plan {
     // the same work as three graphs, one per stage (ensei_plan_run_stage)
     hipGraph_t stage_graph[3] = {nullptr, nullptr, nullptr};
     hipGraphExec_t stage_exec[3] = {nullptr, nullptr, nullptr};
+    // concurrent branches: within each stage the layers (and in the HomConv
+    // stage the shared launch and each layer of its own) are independent, so
+    // they fork onto side streams and join back; kept when faster
+    bool concurrent = false;
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> joins;  // [0] fork, [1 + i] side stream i's join
     ensei::HcSchedule sched{0, 0};
     ensei_schedule info{};
     // seeded ciphertexts: each layer's ct_in holds only the b words,
@@ -35,6 +42,8 @@ struct ensei_plan {
 
 namespace ensei {
 namespace {
+
+constexpr int kSideStreams = 3;  // with the plan's own stream, the device's four hardware queues
 
 struct DeviceGuard {
     int prev = 0;
@@ -53,6 +62,11 @@ void release(ensei_plan *P) {
         if (P->stage_exec[k]) (void)hipGraphExecDestroy(P->stage_exec[k]);
         if (P->stage_graph[k]) (void)hipGraphDestroy(P->stage_graph[k]);
     }
+    for (hipStream_t q : P->side) {
+        (void)hipStreamSynchronize(q);
+        (void)hipStreamDestroy(q);
+    }
+    for (hipEvent_t e : P->joins) (void)hipEventDestroy(e);
     for (auto *q : P->w_hat) (void)hipFree(q);
     for (auto *q : P->w_pack) (void)hipFree(q);
     if (P->d_table) (void)hipFree(P->d_table);
@@ -60,46 +74,81 @@ void release(ensei_plan *P) {
     delete P;
 }
 
+// Runs nb independent branches fn(i, stream): in order on st, or, with the
+// plan's concurrent branches, dealt round-robin over its side streams, which
+// first wait for the work already queued on st and are joined back into st
+// at the end (during graph capture this forks and joins the graph).
+template <class Fn>
+int fork_join(ensei_plan *P, hipStream_t st, int nb, Fn fn) {
+    const int ns = P->concurrent ? (int)std::min<size_t>(P->side.size(), (size_t)nb) : 0;
+    if (ns < 2) {
+        for (int i = 0; i < nb; ++i) {
+            const int rc = fn(i, st);
+            if (rc) return rc;
+        }
+        return ENSEI_OK;
+    }
+    if (hipEventRecord(P->joins[0], st) != hipSuccess) return ENSEI_ERR_HIP;
+    for (int j = 0; j < ns; ++j)
+        if (hipStreamWaitEvent(P->side[j], P->joins[0], 0) != hipSuccess) return ENSEI_ERR_HIP;
+    int rc = ENSEI_OK;
+    for (int i = 0; i < nb && !rc; ++i) rc = fn(i, P->side[i % ns]);
+    for (int j = 0; j < ns; ++j) {  // always join, so that a capture can end
+        if (hipEventRecord(P->joins[1 + j], P->side[j]) != hipSuccess ||
+            hipStreamWaitEvent(st, P->joins[1 + j], 0) != hipSuccess)
+            rc = rc ? rc : ENSEI_ERR_HIP;
+    }
+    return rc;
+}
+
 // Client side of every layer: x^ = NTT2D(x), ct_in = Enc(x^).
 int run_front(ensei_plan *P, hipStream_t st) {
-    for (const ensei_layer &l : P->layers) {
+    return fork_join(P, st, (int)P->layers.size(), [P](int i, hipStream_t q) {
+        const ensei_layer &l = P->layers[i];
         const int64_t F = (int64_t)l.H * l.W;
-        int rc = ensei_ntt2d(P->ctx, l.x, l.x_hat, l.batch * l.Cin, l.H, l.W, st);
+        int rc = ensei_ntt2d(P->ctx, l.x, l.x_hat, l.batch * l.Cin, l.H, l.W, q);
         if (!rc)
             rc = P->seeded
-                     ? ensei_encrypt_seeded(P->ctx, l.x_hat, l.s, l.e, l.batch, l.Cin, F, l.n, l.seed_a, 0, l.ct_in, st)
-                     : ensei_encrypt(P->ctx, l.x_hat, l.s, l.e, l.batch, l.Cin, F, l.n, l.seed_a, 0, l.ct_in, st);
-        if (rc) return rc;
-    }
-    return ENSEI_OK;
+                     ? ensei_encrypt_seeded(P->ctx, l.x_hat, l.s, l.e, l.batch, l.Cin, F, l.n, l.seed_a, 0, l.ct_in, q)
+                     : ensei_encrypt(P->ctx, l.x_hat, l.s, l.e, l.batch, l.Cin, F, l.n, l.seed_a, 0, l.ct_in, q);
+        return rc;
+    });
 }
 
 // Dec, the client's INTT2D and the server's share of every layer.
 int run_back(ensei_plan *P, hipStream_t st) {
-    for (const ensei_layer &l : P->layers) {
+    return fork_join(P, st, (int)P->layers.size(), [P](int i, hipStream_t q) {
+        const ensei_layer &l = P->layers[i];
         const int64_t F = (int64_t)l.H * l.W;
-        int rc = ensei_decrypt(P->ctx, l.ct_out, l.s, l.batch, l.Cout, F, l.n, l.m, st);
-        if (!rc) rc = ensei_intt2d(P->ctx, l.m, l.s_a, l.batch * l.Cout, l.H, l.W, st);
-        if (!rc) rc = ensei_server_share(P->ctx, l.r, l.s_b, l.batch * l.Cout, l.H, l.W, st);
-        if (rc) return rc;
-    }
-    return ENSEI_OK;
+        int rc = ensei_decrypt(P->ctx, l.ct_out, l.s, l.batch, l.Cout, F, l.n, l.m, q);
+        if (!rc) rc = ensei_intt2d(P->ctx, l.m, l.s_a, l.batch * l.Cout, l.H, l.W, q);
+        if (!rc) rc = ensei_server_share(P->ctx, l.r, l.s_b, l.batch * l.Cout, l.H, l.W, q);
+        return rc;
+    });
 }
 
-// s.chunk = -1: the shared problems each in a launch of their own instead
+// The HomConv stage: branch 0 the shared launch (s.chunk = -1: the shared
+// problems each in a launch of their own instead), then each layer on a
+// kernel of its own.
 int run_homconv(ensei_plan *P, HcSchedule s, hipStream_t st) {
-    int rc = ENSEI_OK;
-    if (s.chunk < 0) {
-        for (HcLayer h : P->problems) {
-            h.tile0 = 0;  // its own tile space
-            if (!rc) rc = homconv_launch(P->ctx, &h, nullptr, 1, true, HcSchedule{0, 0}, st, P->seeded);
+    const int nb = 1 + (int)P->single.size();
+    return fork_join(P, st, nb, [P, s](int i, hipStream_t q) {
+        int rc = ENSEI_OK;
+        if (i == 0) {
+            if (s.chunk < 0) {
+                for (HcLayer h : P->problems) {
+                    h.tile0 = 0;  // its own tile space
+                    if (!rc) rc = homconv_launch(P->ctx, &h, nullptr, 1, true, HcSchedule{0, 0}, q, P->seeded);
+                }
+            } else if (!P->problems.empty()) {
+                rc = homconv_launch(P->ctx, P->problems.data(), P->d_table, (int)P->problems.size(), true, s, q,
+                                    P->seeded);
+            }
+            return rc;
         }
-    } else if (!P->problems.empty()) {
-        rc = homconv_launch(P->ctx, P->problems.data(), P->d_table, (int)P->problems.size(), true, s, st, P->seeded);
-    }
-    for (const auto &hp : P->single)
-        if (!rc) rc = homconv_launch(P->ctx, &hp.first, nullptr, 1, hp.second, HcSchedule{0, 0}, st, P->seeded);
-    return rc;
+        const auto &hp = P->single[i - 1];
+        return homconv_launch(P->ctx, &hp.first, nullptr, 1, hp.second, HcSchedule{0, 0}, q, P->seeded);
+    });
 }
 
 // Cache key: device, modulus and the HomConv shape of every layer in the
@@ -119,18 +168,22 @@ std::string plan_key(const ensei_plan *P) {
     return key;
 }
 
-bool cache_lookup(const char *path, const std::string &key, HcSchedule *s) {
+// A cache line is "key blocks chunk [us [branches]]"; branches (0 or 1), when
+// present, pins the serial or concurrent capture too (else it is timed).
+bool cache_lookup(const char *path, const std::string &key, HcSchedule *s, int *branches) {
     FILE *fh = fopen(path, "r");
     if (!fh) return false;
     char line[4096];
     bool found = false;
     while (fgets(line, sizeof line, fh)) {
         char k[3900];
-        int blocks;
+        int blocks, br = -1;
         long long chunk;
-        if (sscanf(line, "%3899s %d %lld", k, &blocks, &chunk) == 3 && (key == k || strcmp(k, "*") == 0) &&
-            blocks > 0 && chunk >= -1) {
+        double us;
+        const int got = sscanf(line, "%3899s %d %lld %lf %d", k, &blocks, &chunk, &us, &br);
+        if (got >= 3 && (key == k || strcmp(k, "*") == 0) && blocks > 0 && chunk >= -1) {
             *s = HcSchedule{blocks, (int64_t)chunk};
+            *branches = got == 5 && (br == 0 || br == 1) ? br : -1;
             found = true;  // the last entry for a key wins
         }
     }
@@ -157,6 +210,29 @@ int time_schedule(ensei_plan *P, HcSchedule s, double *us) {
     const int reps = 3;
     if (!rc && hipEventRecord(a, P->stream) != hipSuccess) rc = ENSEI_ERR_HIP;
     for (int i = 0; i < reps && !rc; ++i) rc = run_homconv(P, s, P->stream);
+    if (!rc && hipEventRecord(b, P->stream) != hipSuccess) rc = ENSEI_ERR_HIP;
+    float ms = 0;
+    if (!rc && (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess))
+        rc = ENSEI_ERR_HIP;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *us = ms * 1e3 / reps;
+    return rc;
+}
+
+// Mean time of one replay of a captured plan (one warm-up, three timed).
+int time_graph(ensei_plan *P, hipGraphExec_t exec, double *us) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return ENSEI_ERR_HIP;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return ENSEI_ERR_HIP;
+    }
+    int rc = hipGraphLaunch(exec, P->stream) == hipSuccess ? ENSEI_OK : ENSEI_ERR_HIP;
+    const int reps = 3;
+    if (!rc && hipEventRecord(a, P->stream) != hipSuccess) rc = ENSEI_ERR_HIP;
+    for (int i = 0; i < reps && !rc; ++i)
+        if (hipGraphLaunch(exec, P->stream) != hipSuccess) rc = ENSEI_ERR_HIP;
     if (!rc && hipEventRecord(b, P->stream) != hipSuccess) rc = ENSEI_ERR_HIP;
     float ms = 0;
     if (!rc && (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess))
@@ -206,6 +282,22 @@ int plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const ch
         P->stream = nullptr;
         release(P);
         return ENSEI_ERR_HIP;
+    }
+    for (int i = 0; i < kSideStreams; ++i) {  // default priority, like every stream here
+        hipStream_t q;
+        if (hipStreamCreateWithFlags(&q, hipStreamNonBlocking) != hipSuccess) {
+            release(P);
+            return ENSEI_ERR_HIP;
+        }
+        P->side.push_back(q);
+    }
+    for (int i = 0; i <= kSideStreams; ++i) {
+        hipEvent_t e;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            release(P);
+            return ENSEI_ERR_HIP;
+        }
+        P->joins.push_back(e);
     }
     // server setup: transformed and packed filters (paired layout, folded for
     // narrow inputs); narrow and deep layers run on their own kernels, the
@@ -272,6 +364,7 @@ int plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const ch
 
     // the HomConv tile schedule: cached, or the fastest candidate
     const std::string key = plan_key(P);
+    int pin_branches = -1;
     HcSchedule best{ctx->num_cus, 0};
     double best_us = 0;
     if (P->problems.empty()) {
@@ -281,7 +374,7 @@ int plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const ch
             release(P);
             return rc;
         }
-    } else if (tune_cache && cache_lookup(tune_cache, key, &best)) {
+    } else if (tune_cache && cache_lookup(tune_cache, key, &best, &pin_branches)) {
         P->info.from_cache = 1;
     } else {
         // chunk -1: no shared launch, each problem on its own
@@ -310,8 +403,39 @@ int plan_create(ensei_ctx *ctx, const ensei_layer *layers, int nlayers, const ch
     P->info.shared_layers = (int)P->problems.size();
     P->info.own_layers = (int)P->single.size();
 
-    // capture the whole stack as one graph, and each stage as a graph of its own
+    // capture the whole stack as one graph, with the layers of each stage in
+    // order or as concurrent branches: pinned by the cache, else whichever
+    // replays faster; then each stage as a graph of its own in the same form
     rc = capture(P, -1, &P->graph, &P->exec);
+    if (!rc && pin_branches >= 0) {
+        P->concurrent = pin_branches == 1;
+        if (P->concurrent) {
+            (void)hipGraphExecDestroy(P->exec);
+            (void)hipGraphDestroy(P->graph);
+            P->exec = nullptr;
+            P->graph = nullptr;
+            rc = capture(P, -1, &P->graph, &P->exec);
+        }
+    } else if (!rc && P->layers.size() > 1) {
+        double serial_us = 0, conc_us = 0;
+        hipGraph_t g2 = nullptr;
+        hipGraphExec_t e2 = nullptr;
+        rc = time_graph(P, P->exec, &serial_us);
+        P->concurrent = true;
+        if (!rc) rc = capture(P, -1, &g2, &e2);
+        if (!rc) rc = time_graph(P, e2, &conc_us);
+        if (!rc && conc_us < serial_us) {
+            std::swap(g2, P->graph);
+            std::swap(e2, P->exec);
+        } else {
+            P->concurrent = false;
+        }
+        if (e2) (void)hipGraphExecDestroy(e2);
+        if (g2) (void)hipGraphDestroy(g2);
+        P->info.serial_us = serial_us;
+        P->info.branches_us = conc_us;
+    }
+    P->info.branches = P->concurrent ? 1 : 0;
     for (int k = 0; k < 3 && !rc; ++k) rc = capture(P, k, &P->stage_graph[k], &P->stage_exec[k]);
     if (rc) {
         release(P);

@@ -131,7 +131,8 @@ class ScheduleDesc(C.Structure):
     """``ensei_schedule``: the HomConv tile schedule a plan runs."""
 
     _fields_ = [("blocks", _i32), ("from_cache", _i32), ("chunk", _i64), ("homconv_us", C.c_double),
-                ("shared_layers", _i32), ("own_layers", _i32)]
+                ("shared_layers", _i32), ("own_layers", _i32), ("branches", _i32), ("pad", _i32),
+                ("serial_us", C.c_double), ("branches_us", C.c_double)]
 
 
 class EnseiError(RuntimeError):
@@ -527,7 +528,8 @@ class Plan:
         sd = ScheduleDesc()
         _check(lib().ensei_plan_schedule(self._h, C.byref(sd)), "ensei_plan_schedule")
         return {"blocks": sd.blocks, "chunk": sd.chunk, "homconv_us": sd.homconv_us, "from_cache": bool(sd.from_cache),
-                "shared_layers": sd.shared_layers, "own_layers": sd.own_layers}
+                "shared_layers": sd.shared_layers, "own_layers": sd.own_layers, "branches": bool(sd.branches),
+                "serial_us": sd.serial_us, "branches_us": sd.branches_us}
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

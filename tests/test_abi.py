@@ -12,6 +12,7 @@ from paper_2003_05328_amd import ensei
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "ensei.h")
 BENCH_HEADER = os.path.join(ROOT, "include", "ensei_bench.h")
+BFV_HEADER = os.path.join(ROOT, "include", "ensei_bfv.h")
 
 
 def declared_functions(header=HEADER):
@@ -40,6 +41,30 @@ def test_every_declared_symbol_is_exported(lib):
         assert hasattr(lib, name), name
         assert name in ensei.SIGNATURES, f"binding lacks {name}"
     assert set(ensei.SIGNATURES) == set(declared_functions())
+
+
+def test_packed_calls_are_exported(lib):
+    from paper_2003_05328_amd import ensei_bfv
+
+    names = declared_functions(BFV_HEADER)
+    assert set(names) == set(ensei_bfv.SIGNATURES)
+    out = subprocess.run(["nm", "-D", "--defined-only", ensei.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    for name in names:
+        assert name in exported, name
+    l = ensei_bfv._lib()
+    h = ctypes.c_void_p()
+    # host-side refusals need no GPU: bad n, composite or ill-sized moduli, null arguments
+    assert l.ensei_bfv_ctx_create(None, 12289, 8380417, 4005889, 2048, 0) == -1
+    assert l.ensei_bfv_ctx_create(ctypes.byref(h), 12289, 8380417, 4005889, 48, 0) == -1
+    assert l.ensei_bfv_ctx_create(ctypes.byref(h), 12289, 8380417, 4005889, 8192, 0) == -1  # n > 4096
+    assert l.ensei_bfv_ctx_create(ctypes.byref(h), 12289, 8380417, 4005889, 4096, 0) == -3  # 8192 does not divide t - 1
+    assert l.ensei_bfv_ctx_create(ctypes.byref(h), 12291, 8380417, 4005889, 2048, 0) == -3
+    assert l.ensei_bfv_ctx_create(ctypes.byref(h), 12289, 8380417, 8380417, 2048, 0) == -3
+    assert l.ensei_bfv_ctx_destroy(None) == 0
+    assert l.ensei_bfv_vectors(None, 3, 1024) == 0
+    assert l.ensei_bfv_key(None, None, None, None) == -1
 
 
 def test_bench_library_exports_its_header(lib):
@@ -125,7 +150,7 @@ def test_plan_structs_match_the_header():
     # ensei_layer: 7 ints, int64 batch, uint64 seed_a, 11 pointers
     assert ctypes.sizeof(ensei.LayerDesc) == 7 * 4 + 4 + 8 + 8 + 11 * 8
     assert ensei.LayerDesc.batch.offset == 32 and ensei.LayerDesc.w.offset == 48
-    assert ctypes.sizeof(ensei.ScheduleDesc) == 32
+    assert ctypes.sizeof(ensei.ScheduleDesc) == 56
 
 
 def test_modulus_rejected_before_device_use(lib):

@@ -114,14 +114,22 @@ def test_plan_of_narrow_layers_only(ctx, orc, tmp_path):
     plan.close()
 
 
+@pytest.mark.parametrize("branches", [0, 1])  # layers of a stage in order, or as concurrent graph branches
 @pytest.mark.parametrize("chunk", [0, 1, 3, 64, -1])  # -1: a launch per layer
-def test_plan_every_schedule_is_exact(ctx, orc, tmp_path, chunk):
+def test_plan_every_schedule_is_exact(ctx, orc, tmp_path, chunk, branches):
     cache = tmp_path / "pin.txt"
-    cache.write_text(f"* {torch.cuda.get_device_properties(0).multi_processor_count} {chunk}\n")
+    cache.write_text(f"* {torch.cuda.get_device_properties(0).multi_processor_count} {chunk} 0 {branches}\n")
     layers = [_layer(ctx, S, 200 + i) for i, S in enumerate(STACK)]
     plan = Plan(ctx, [l for _, l in layers], tune_cache=str(cache))
     assert plan.schedule()["chunk"] == chunk and plan.schedule()["from_cache"]
-    plan.run()
+    assert plan.schedule()["branches"] == bool(branches)
+    for _ in range(2):
+        plan.run()
+        torch.cuda.synchronize()
+        for S, (inp, l) in zip(STACK, layers):
+            _check_layer(orc, S, inp, l, _single_calls(ctx, S, l))
+    for stage in range(3):
+        plan.run_stage(stage)
     torch.cuda.synchronize()
     for S, (inp, l) in zip(STACK, layers):
         _check_layer(orc, S, inp, l, _single_calls(ctx, S, l))
