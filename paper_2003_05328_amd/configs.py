@@ -54,3 +54,14 @@ for _i, _s in enumerate(stack_shapes()):
     WORKLOADS[f"stack8_L{_i + 1}_{_s.H}x{_s.W}_c{_s.Cin}to{_s.Cout}"] = _s
 for _i, _s in enumerate(stack_shapes(binary=True)):
     WORKLOADS[f"stack8bin_L{_i + 1}_{_s.H}x{_s.W}_c{_s.Cin}to{_s.Cout}"] = _s
+
+
+# The packed (BFV / RLWE) instantiation's parameter sets: t = p_E and
+# ceil(lg q) of Table 2 (ENSEI-NTT), n = 2048; q = q0 q1, two primes
+# = 1 mod 2n, the limbs with the smallest centred q mod t among those of the
+# stated bit length (the same rule the checker's golden file records).
+PACKED_SETS = {
+    "binary": dict(t=12289, q0=8380417, q1=4005889, n=2048),
+    "medium": dict(t=147457, q0=134176769, q1=63062017, n=2048),
+    "high": dict(t=2363393, q0=1073692673, q1=561770497, n=2048),
+}
