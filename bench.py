@@ -64,8 +64,8 @@ def parse():
     ap.add_argument("--serve-rates", default="250,500,1000,1500,2000", help="arrival rates, requests/s")
     ap.add_argument("--serve-requests", type=int, default=1000, help="requests per rate")
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
-    ap.add_argument("--serve-streams", type=int, default=4, help="streams of the continuous-batching server")
-    ap.add_argument("--serve-max-batch", type=int, default=16, help="requests per batch")
+    ap.add_argument("--serve-streams", type=int, default=2, help="streams of the continuous-batching server")
+    ap.add_argument("--serve-max-batch", type=int, default=4, help="requests per batch")
     ap.add_argument("--seeded", action="store_true",
                     help="only the main workload's step with seeded ciphertexts, one JSON line")
     ap.add_argument("--chained", action="store_true",
@@ -517,7 +517,7 @@ def stack_batched(ctx, reps: int, seed: int):
     }
 
 
-def serving(ctx, rates, n_req: int, budget_gb: float, seed: int, nstreams: int = 4, max_batch: int = 16,
+def serving(ctx, rates, n_req: int, budget_gb: float, seed: int, nstreams: int = 2, max_batch: int = 4,
             seeded_rates=None, p99_target_ms: float = 25.0):
     """Secure-convolution requests of mixed shapes (one image each: pick one of
     the four workload families uniformly, then one of its layers) arriving as
@@ -1250,6 +1250,7 @@ def main():
         torch.cuda.empty_cache()
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         result["serving"] = serving(ctx, rates, args.serve_requests, args.serve_budget_gb, args.seed,
+                                    nstreams=args.serve_streams, max_batch=args.serve_max_batch,
                                     seeded_rates=rates[-2:])
         result["verified"] = result["verified"] and result["serving"]["bit_exact"]
     if not args.no_cpu_baseline:

@@ -15,7 +15,6 @@
 
 #include <chrono>
 #include <condition_variable>
-#include <algorithm>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -132,14 +131,12 @@ Parts parts_of(const ensei_shape &d, bool seeded = false) {
 
 // Enqueues one batch. Called WITHOUT the server's lock: it reads only the
 // batch's own jobs, its launch-table slot and the arena memory of its
-// requests. The jobs run smallest first, and each request's completion event
-// follows its own last kernel, so that a small request does not wait for the
-// decryption of a large one. Returns a status; on error nothing of the batch
-// is left running once its stream has been synchronised.
+// requests. The jobs keep their arrival order, and each request's completion
+// event follows its own last kernel, so that a request does not wait for the
+// decryption of the requests after it. Returns a status; on error nothing of
+// the batch is left running once its stream has been synchronised.
 int launch_batch(ensei_server *S, Batch &b) {
     const hipStream_t st = b.stream;
-    std::stable_sort(b.jobs.begin(), b.jobs.end(),
-                     [](const Job &x, const Job &y) { return x.sh.footprint < y.sh.footprint; });
     HcLayer *tab = S->h_tables + (size_t)b.slot * S->max_batch;
     int np = 0;
     int64_t tile0 = 0;

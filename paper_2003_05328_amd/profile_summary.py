@@ -63,6 +63,39 @@ def counter_means(pmc_dir: str, counter: str):
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
+def stage_kib(pmc_dir: str, counter: str, prefix: str, per_step: int, steps: int) -> float:
+    """Counter KiB of one step's dispatches of the kernels whose short name
+    starts with prefix: the last per_step * steps such dispatches (in dispatch
+    order), summed and divided by steps."""
+    rows = []
+    with open(os.path.join(pmc_dir, "run_counter_collection.csv")) as fh:
+        for i, r in enumerate(csv.DictReader(fh)):
+            if r["Counter_Name"] == counter:
+                rows.append((int(r.get("Dispatch_Id") or i), short_name(r["Kernel_Name"]), float(r["Counter_Value"])))
+    rows.sort()
+    vals = [v for _, k, v in rows if k.startswith(prefix)]
+    last = vals[-per_step * steps:]
+    assert len(last) == per_step * steps, "fewer dispatches than requested"
+    return sum(last) / steps
+
+
+def step_kernels(trace_dir: str, per_step: int, steps: int):
+    """The last steps * per_step dispatches of run_kernel_trace.csv (start
+    order): per kernel, calls per step and mean microseconds per call, and the
+    order of one step's kernels."""
+    rows = []
+    with open(os.path.join(trace_dir, "run_kernel_trace.csv")) as fh:
+        for r in csv.DictReader(fh):
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short_name(r["Kernel_Name"])))
+    rows.sort()
+    last = rows[-per_step * steps:]
+    agg = defaultdict(list)
+    for a, b, k in last:
+        agg[k].append((b - a) / 1e3)
+    order = [k for _, _, k in last[-per_step:]]
+    return {k: (len(v) / steps, sum(v) / len(v)) for k, v in agg.items()}, order
+
+
 def copy_factor(pmc_dir: str, counter: str) -> float:
     """True bytes / counted bytes for the copy kernel (largest mean among its dispatches)."""
     means = counter_means(pmc_dir, counter)
@@ -82,6 +115,11 @@ def main():
     ap.add_argument("--kernel", default="homconv_mfma_kernel", help="kernel whose HBM bytes are recorded")
     ap.add_argument("--out", required=True)
     ap.add_argument("--traffic")
+    ap.add_argument("--stage-prefix", help="sum the HBM bytes of one step's dispatches of these kernels")
+    ap.add_argument("--per-step", type=int, default=0, help="dispatches of one step in the trace")
+    ap.add_argument("--steps", type=int, default=1, help="trace steps whose dispatches are averaged (the last ones)")
+    ap.add_argument("--stage-per-step", type=int, default=0, help="dispatches of the prefix kernels per step")
+    ap.add_argument("--pmc-steps", type=int, default=1, help="counter-run steps averaged (the last ones)")
     args = ap.parse_args()
 
     lines = [f"# Kernel times and HBM traffic: {args.workload}", ""]
@@ -94,8 +132,21 @@ def main():
     for name, calls, avg, mn, mx, pct in kernel_stats(args.trace):
         lines.append(f"| {name} | {calls} | {avg:.1f} | {mn:.1f} | {mx:.1f} | {pct:.1f} |")
 
+    if args.per_step:
+        per, order = step_kernels(args.trace, args.per_step, args.steps)
+        lines += ["", f"## One step ({args.per_step} dispatches; the last {args.steps} steps of the trace)", "",
+                  "| kernel | calls per step | avg us | us per step |", "|---|---|---|---|"]
+        tot = 0.0
+        for k, (calls, avg) in sorted(per.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+            lines.append(f"| {k} | {calls:g} | {avg:.1f} | {calls * avg:.1f} |")
+            tot += calls * avg
+        if args.stage_prefix:
+            st = sum(c * a for k, (c, a) in per.items() if k.startswith(args.stage_prefix))
+            lines += ["", f"Kernel time per step: {tot:.1f} us, of which {args.stage_prefix}* {st:.1f} us."]
+        lines += ["", "One step's dispatch order: " + ", ".join(order)]
+
     record = None
-    if args.fetch and args.write and args.copy_fetch and args.copy_write:
+    if args.fetch and args.write and args.copy_fetch and args.copy_write and not args.stage_prefix:
         ff, fw = copy_factor(args.copy_fetch, "FETCH_SIZE"), copy_factor(args.copy_write, "WRITE_SIZE")
         fetch, write = counter_means(args.fetch, "FETCH_SIZE"), counter_means(args.write, "WRITE_SIZE")
         lines += ["", "## HBM counters (rocprofv3 --pmc, one counter per run)", "",
@@ -118,6 +169,18 @@ def main():
                     "write_factor": fw,
                     "code_sha256": code_digest(HOMCONV_SRC),
                 }
+    if args.stage_prefix and args.fetch and args.write and args.copy_fetch and args.copy_write:
+        ff, fw = copy_factor(args.copy_fetch, "FETCH_SIZE"), copy_factor(args.copy_write, "WRITE_SIZE")
+        fk = stage_kib(args.fetch, "FETCH_SIZE", args.stage_prefix, args.stage_per_step, args.pmc_steps)
+        wk = stage_kib(args.write, "WRITE_SIZE", args.stage_prefix, args.stage_per_step, args.pmc_steps)
+        hbm = fk * 1024 * ff + wk * 1024 * fw
+        lines += ["", f"## One step's {args.stage_prefix}* dispatches ({args.stage_per_step} per step, mean of the "
+                      f"last {args.pmc_steps} steps of the counter runs)", "",
+                  f"FETCH_SIZE {fk:.0f} KiB, WRITE_SIZE {wk:.0f} KiB: {hbm / 1e6:.1f} MB of HBM traffic per step "
+                  "(calibrated)."]
+        record = {"kernel": f"{args.stage_prefix}* (one step)", "workload": args.workload,
+                  "hbm_bytes_per_launch": int(round(hbm)), "fetch_kib": fk, "write_kib": wk, "fetch_factor": ff,
+                  "write_factor": fw, "code_sha256": code_digest(HOMCONV_SRC)}
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
