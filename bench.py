@@ -642,8 +642,15 @@ def serving(ctx, rates, n_req: int, budget_gb: float, seed: int, nstreams: int =
                 "submit_lag_p99_ms": float(np.percentile((ts[:, 1] - ts[:, 0]) * 1e3, 99)),
                 "queue_p99_ms": float(np.percentile((ts[:, 2] - ts[:, 1]) * 1e3, 99)), "bit_exact": bool(ok[0])}
 
-    def sweep(server, fams, plan, rs):
-        return [run(server, fams, plan, r) for r in rs]
+    def sweep(server, fams, plan, rs, label):
+        out = []
+        for r in rs:
+            out.append(run(server, fams, plan, r))
+            x = out[-1]
+            # a progress line per rate (a long sweep is otherwise silent for minutes)
+            print(f"serving {label}: {r:g} req/s offered, {x['throughput_req_s']:.0f} served, p50 {x['p50_ms']:.2f} "
+                  f"ms, p99 {x['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+        return out
 
     g = np.random.default_rng(seed)
     plan = draw(g, n_req)
@@ -659,7 +666,7 @@ def serving(ctx, rates, n_req: int, budget_gb: float, seed: int, nstreams: int =
                 server.forget(t)
                 L["ref"][j] = (s_a, s_b)
     torch.cuda.synchronize()
-    batched = sweep(server, fams, plan, rates)
+    batched = sweep(server, fams, plan, rates, "continuous batching")
     st = server.stats()
     server.close()
     refs = [[L["ref"] for L in lst] for lst in fams]
@@ -675,12 +682,12 @@ def serving(ctx, rates, n_req: int, budget_gb: float, seed: int, nstreams: int =
     if seeded_rates:
         # requests keep only the b words of their input ciphertexts
         server = Server(ctx, budget, nstreams=nstreams, max_batch=max_batch, seeded=True)
-        seeded = sweep(server, with_refs(server), plan, seeded_rates)
+        seeded = sweep(server, with_refs(server), plan, seeded_rates, "seeded")
         server.close()
     # sequential plain execution on the same GPU: one stream, one request at a
     # time, first come first served, the same open-loop arrivals
     seq_server = Server(ctx, budget, nstreams=1, max_batch=1)
-    sequential = sweep(seq_server, with_refs(seq_server), plan, rates)
+    sequential = sweep(seq_server, with_refs(seq_server), plan, rates, "sequential")
     seq_server.close()
 
     def best_at(rows):
