@@ -603,39 +603,98 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
 }
 
 // Deep-layer HomConv (paired fragments, Cin <= 64 kDeepMaxKs, several
-// 64-row output tiles): a block is (b, f, 32 columns j). The block's words of
+// 64-row output tiles): a block is (b, f, 32 columns j), and one 12-wave
+// workgroup per CU walks a contiguous range of blocks. The block's words of
 // every input channel are converted to digit planes in LDS once (up to 64 KB),
-// then every (row tile, K step) phase of the block contracts from there with
-// no barrier in between: the conversion is shared by all Cout rows instead of
-// being repeated per row tile, and each phase's fixed cost is a few fragment
-// loads per wave. Four waves hold 16 columns x 32 rows each (as in
-// homconv_mfma_kernel) and load their own weight fragments from the packed
-// layout one phase ahead; every phase issues the same loads and stores
-// (dropped ones where the K step is not the tile's last), so the waits see
-// static counts. Two workgroups share a CU, so one contracts while the other
-// waits for its next block's words; each walks a contiguous range of blocks.
-constexpr int kDeepThreads = 256;
-constexpr int kXcds = 8;                             // accelerator dies (each with its own L2)
-constexpr int kDeepCols = 32;                        // columns per block
-constexpr int kDeepPlane = kDeepCols * 4 * 16;       // one digit plane of a block's K step
+// then every (row-tile pair, K step) phase of the block contracts from there
+// with no barrier in between: the conversion is shared by all Cout rows
+// instead of being repeated per row tile. Eight compute waves hold 16 columns
+// x 32 rows each, 128 rows (two row tiles) per phase. Four loader waves
+// stream the coming blocks' words from HBM straight into a ring of LDS
+// staging buffers (LDS-DMA buffer loads) while the compute waves contract the
+// current one.
+// The weight fragments come one of two ways:
+//   - resident (AL): when the frequency's whole fragment set fits in LDS
+//     beside the planes and the staging buffer (128 input channels, up to 256
+//     outputs), the loader waves copy it there whenever a block of a new
+//     frequency starts (a workgroup's blocks cover one or a few
+//     frequencies), and the compute waves read it with the planes: they
+//     issue no loads at all;
+//   - streamed: each compute wave loads its own fragments from the L2 one
+//     phase ahead (across block boundaries too) into two register sets used
+//     in turn, so that no copy waits for a load in flight.
+// The loader/compute split matters because a wave's memory counter retires
+// in issue order: a compute wave that issued the HBM loads itself would, at
+// its next wait for fragments, wait for those loads as well.
+constexpr int kDeepComputeWaves = 8;
+constexpr int kDeepLoaderWaves = 4;
+constexpr int kDeepThreads = (kDeepComputeWaves + kDeepLoaderWaves) * 64;
+constexpr int kXcds = 8;                        // accelerator dies (each with its own L2)
+constexpr int kDeepCols = 32;                   // columns per block
+constexpr int kDeepPlane = kDeepCols * 4 * 16;  // one digit plane of a block's K step
 constexpr int kDeepMaxKs = 4;
+constexpr int kDmaBytes = 64 * 16;    // one 16-byte LDS-DMA instruction: 16 bytes per lane
+constexpr int kFragBytes = 768 * 16;  // the fragments of one (K step, row tile) unit
+constexpr int kDeepLds = 160 * 1024;  // LDS of one workgroup
 
-// SEEDED: seeded input (ensei_homconv_seeded), as in homconv_mfma_kernel.
-template <bool WIDE_STORE, bool SEEDED>
-__global__ __launch_bounds__(kDeepThreads, 2) void homconv_deep_kernel(HcLayer P, uint64_t delta) {
-    extern __shared__ __attribute__((aligned(16))) uint8_t dlds[];  // [ks][plane 8] planes, then masks [n_ot 64]
-    const int n_ks = P.n_ks, n_ot = P.n_ot, Cin = P.Cin, Cout = P.Cout;
+// Staging order of a block's words (Cin a multiple of 8): the 64-byte run of
+// 8 channels (column col, channel group grp) keeps its place, and its 16-byte
+// chunk q sits at chunk q ^ deep_swz(col, grp). The conversion's 16-byte reads
+// of 16 consecutive lanes (two columns x eight groups, same q) then fall on
+// distinct banks.
+__device__ __forceinline__ uint32_t deep_swz(uint32_t col, uint32_t grp) { return ((grp >> 1) & 3) ^ (col & 1); }
+
+// LDS address of a shared-memory pointer, as the LDS-DMA instructions take it.
+typedef __attribute__((address_space(3))) void *lds_ptr_t;
+
+// The deep kernel's LDS: digit planes [ks][8 planes]; ring staging buffers
+// (a block's words in whole LDS-DMA lines, then, streamed, its masks); then
+// either the masks of the block being contracted (streamed) or the
+// frequency's fragments [ks][row tile][768 items] (resident, whose masks are
+// read from global memory). When Cin is not a multiple of 8, 64 spare bytes at
+// the end take the reads of a channel group straddling Cin past the last
+// column.
+struct DeepLds {
+    int n_dma, n_mask;
+    size_t planes, words, slot, tail, total;
+    __host__ __device__ DeepLds(int Cin, int n_ks, int n_ot, bool seeded, bool resident, int ring) {
+        n_dma = seeded ? 0 : (kDeepCols * Cin * 8 + kDmaBytes - 1) / kDmaBytes;
+        n_mask = 2 * ((n_ot + 1) / 2) * 64;
+        planes = (size_t)n_ks * 8 * kDeepPlane;
+        words = (size_t)n_dma * kDmaBytes;
+        slot = words + (resident ? 0 : (size_t)n_mask * 4);
+        tail = resident ? (size_t)n_ks * n_ot * kFragBytes : (size_t)n_mask * 4;
+        total = planes + (size_t)ring * slot + tail + (Cin % 8 ? 64 : 0);
+    }
+};
+
+// SEEDED: seeded input (ensei_homconv_seeded): words j < n come from the
+// public stream at conversion and only the b words (column n) are loaded.
+// NKS: the layer's K steps of 64 channels (1 to kDeepMaxKs). AL: resident
+// fragments. ring: staging buffers (blocks loaded ahead; 1, 2 or 4).
+template <bool WIDE_STORE, bool SEEDED, int NKS, bool AL>
+__global__ __launch_bounds__(kDeepThreads) void homconv_deep_kernel(HcLayer P, uint64_t delta, int ring) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t dlds[];
+    constexpr int n_ks = NKS;
+    const int n_ot = P.n_ot, Cin = P.Cin, Cout = P.Cout;
+    const int n_otp = (n_ot + 1) / 2;
     const int64_t F = P.F, rowlen = (int64_t)P.n + 1;
     const int n_jt = (int)((rowlen + kDeepCols - 1) / kDeepCols);
-    uint32_t *lds_r = reinterpret_cast<uint32_t *>(dlds + (size_t)n_ks * 8 * kDeepPlane);
+    const DeepLds L(Cin, n_ks, n_ot, SEEDED, AL, ring);
+    const int n_dma = L.n_dma, n_mask = L.n_mask;
+    const bool swz = Cin % 8 == 0;
     auto planes = [&](int ks) { return dlds + ks * 8 * kDeepPlane; };
+    auto slot = [&](int64_t x) { return dlds + L.planes + (size_t)(x % ring) * L.slot; };  // x: block - blo
+    uint8_t *tail = dlds + L.planes + (size_t)ring * L.slot;  // masks in use (streamed) or fragments (resident)
+    uint32_t *lds_r = reinterpret_cast<uint32_t *>(tail);
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int g = lane >> 4, l16 = lane & 15, cg = wave & 1, rg = wave >> 1;
-    const int ld_col = tid >> 3, ld_sc = (tid >> 1) & 3, ld_h = tid & 1;  // load role: 8 channels of a column
-    const int b_col = cg * 16 + l16, out_row = 32 * rg + 8 * g;
+    const bool loader = wave >= kDeepComputeWaves;
+    const int g = lane >> 4, l16 = lane & 15, cg = wave & 1, rg = (wave >> 1) & 3;
+    const int b_col = cg * 16 + l16;
     const int b_base = plane_slot(b_col, g) * 16;  // this lane's 16 channels of a plane
+    const int half = rg & 1, pair_row = rg >> 1;  // 32-row half of row tile 2 otp + pair_row
 
     // Blocks in (f, b, column) order, so that a frequency's weight fragments
     // serve B * n_jt consecutive blocks. Workgroups are dealt to the XCDs
@@ -648,83 +707,162 @@ __global__ __launch_bounds__(kDeepThreads, 2) void homconv_deep_kernel(HcLayer P
     const int64_t per = total / G, extra = total % G;
     const int64_t blo = wg * per + (wg < extra ? wg : extra);
     const int64_t bhi = blo + per + (wg < extra ? 1 : 0);
-    const int n_ph = n_ot * n_ks;
+    if (blo >= bhi) return;
+    const int64_t nblk = bhi - blo;
 
-    // this wave's fragments of unit (f, ks, ot): items [limb][row block][lane]
-    auto load_frags = [&](int64_t f, int ks, int ot, v4i (&A)[3][2]) {
-        const int64_t unit = (f * n_ks + ks) * n_ot + ot;
-        const __amdgpu_buffer_rsrc_t ra =
-            make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(P.w_pack) + unit * 768 * 16), 768u * 16u);
-#pragma unroll
-        for (int l = 0; l < 3; ++l)
-#pragma unroll
-            for (int rb = 0; rb < 2; ++rb) {
-                const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(ra, ((l * 4 + rg * 2 + rb) * 64 + lane) * 16, 0, 0);
-                A[l][rb] = v4i{(int)t.x, (int)t.y, (int)t.z, (int)t.w};
-            }
+    // block blk's image, frequency and column block
+    auto coords = [&](int64_t blk, int64_t &b, int64_t &f, int &jt) {
+        jt = (int)(blk % n_jt);
+        const int64_t fb = blk / n_jt;
+        b = fb % P.B;
+        f = fb / P.B;
     };
+    auto freq = [&](int64_t blk) { return blk / n_jt / P.B; };
 
-    v4i acc[8][2];
-    uint64_t res[2][4] = {};
-    for (int64_t blk = blo; blk < bhi; ++blk) {
-        const int jt = (int)(blk % n_jt);
-        const int64_t fb = blk / n_jt, b = fb % P.B, f = fb / P.B;
+    if (loader) {
+        // Loader waves only issue LDS-DMA loads and wait for their own; their
+        // barriers carry no fence, so no wait is added for loads in flight.
+        // Group k (the loader waves lw with lw % ring == k, as many as divide
+        // evenly) owns the blocks x = k mod ring: it loads block x into slot
+        // x % ring once block x - ring has been converted, and waits for it
+        // just before the barrier after which x is converted. A group has one
+        // block in flight at a time, so that wait is exact.
+        const int lw = wave - kDeepComputeWaves;
+        const int per_group = kDeepLoaderWaves / ring;
+        const int grp = lw % ring, gw = lw / ring;  // group, wave within the group
+        const bool act = gw < per_group;
+        auto load_block = [&](int64_t x) {
+            int64_t b, f;
+            int jt;
+            coords(blo + x, b, f, jt);
+            uint8_t *dst = slot(x);
+            if (!SEEDED) {
+                const __amdgpu_buffer_rsrc_t rs = make_rsrc(
+                    uniform_ptr(reinterpret_cast<const uint8_t *>(P.ct_in + (b * F + f) * rowlen * Cin)),
+                    (uint32_t)(rowlen * Cin * 8));
+                const uint32_t col_off = (uint32_t)((int64_t)jt * kDeepCols * Cin * 8);
+                for (int i = gw; i < n_dma; i += per_group) {
+                    const uint32_t c = (uint32_t)i * 64 + lane;  // 16-byte chunk of the slot
+                    uint32_t gc = c;
+                    if (swz) {
+                        const uint32_t u = c >> 2, gpc = (uint32_t)Cin / 8;  // run u: column u / gpc, group u % gpc
+                        gc = (c & ~3u) | ((c & 3u) ^ deep_swz(u / gpc, (u % gpc) & 7));
+                    }
+                    const uint32_t d = __builtin_amdgcn_readfirstlane(
+                        (uint32_t)(uintptr_t)(lds_ptr_t)(dst + (size_t)i * kDmaBytes));
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (lds_ptr_t)(uintptr_t)d, 16, col_off + gc * 16, 0,
+                                                             0, 0);
+                }
+            }
+            if (!AL && jt == n_jt - 1) {
+                // masks r[b][o][f], o < Cout (zero past it), 4 bytes per lane
+                const __amdgpu_buffer_rsrc_t rr =
+                    make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(P.r + b * Cout * F + f)),
+                              (uint32_t)(((int64_t)(Cout - 1) * F + 1) * 4));
+                for (int i = gw; i * 64 < n_mask; i += per_group) {
+                    const int o = i * 64 + lane;
+                    const uint32_t d = __builtin_amdgcn_readfirstlane(
+                        (uint32_t)(uintptr_t)(lds_ptr_t)(dst + L.words + (size_t)i * 256));
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rr, (lds_ptr_t)(uintptr_t)d, 4,
+                                                             o < Cout ? (uint32_t)((int64_t)o * F * 4) : 0x80000000u,
+                                                             0, 0, 0);
+                }
+            }
+        };
+        // resident: frequency f's fragments, one contiguous run of w_pack
+        // (every loader wave takes a share)
+        auto load_frags_lds = [&](int64_t f) {
+            const uint32_t bytes = (uint32_t)L.tail;
+            const __amdgpu_buffer_rsrc_t ra = make_rsrc(
+                uniform_ptr(reinterpret_cast<const uint8_t *>(P.w_pack) + f * (int64_t)L.tail), bytes);
+            for (int i = lw; i * kDmaBytes < (int)bytes; i += kDeepLoaderWaves) {
+                const uint32_t d =
+                    __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_ptr_t)(tail + (size_t)i * kDmaBytes));
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr_t)(uintptr_t)d, 16,
+                                                         (uint32_t)i * kDmaBytes + lane * 16, 0, 0, 0);
+            }
+        };
+        // prologue: the fragments and block 0 landed before the first
+        // barrier; blocks 1 .. ring - 1 on their way
+        if (AL) load_frags_lds(freq(blo));
+        if (act && grp == 0) load_block(0);
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+        if (act && grp > 0 && grp < nblk) load_block(grp);
+        __builtin_amdgcn_s_barrier();
+        for (int64_t x = 0; x < nblk; ++x) {
+            const int64_t blk = blo + x;
+            if (AL && x > 0 && freq(blk) != freq(blk - 1)) {
+                // the previous block's phases are done: its frequency's
+                // fragments can be replaced while the block is converted
+                // (this also waits for the blocks in flight)
+                load_frags_lds(freq(blk));
+                __builtin_amdgcn_s_waitcnt(0x0F70);
+            }
+            __builtin_amdgcn_s_barrier();  // block x converted: its slot is free
+            if (act && x % ring == grp && x + ring < nblk) load_block(x + ring);
+            if (act && (x + 1) % ring == grp) __builtin_amdgcn_s_waitcnt(0x0F70);  // block x + 1 landed
+            __builtin_amdgcn_s_barrier();  // block x contracted
+        }
+        return;
+    }
 
-        // the block's words of every K step (8 channels of one column per
-        // thread); seeded: only the b words, read by the block holding column n
-        const uint8_t *src = uniform_ptr(
-            SEEDED ? reinterpret_cast<const uint8_t *>(P.b_in + (b * F + f) * Cin)
-                   : reinterpret_cast<const uint8_t *>(P.ct_in + (b * F + f) * rowlen * Cin));
-        const __amdgpu_buffer_rsrc_t rs =
-            make_rsrc(src, SEEDED ? (jt == n_jt - 1 ? (uint32_t)(Cin * 8) : 0u) : (uint32_t)(rowlen * Cin * 8));
-        const int col = jt * kDeepCols + ld_col;
-        u32x4 w[kDeepMaxKs][4];
-#pragma unroll
-        for (int ks = 0; ks < kDeepMaxKs; ++ks) {
-            if (ks >= n_ks) break;
-            // columns past n read zero; 8-channel groups past Cin are not read
-            const bool any = ld_sc * 16 + ld_h * 8 < Cin - ks * 64;
-            const int c0 = ks * 64 + ld_sc * 16 + ld_h * 8;
-            const uint32_t off = SEEDED ? (any && col == P.n ? (uint32_t)(c0 * 8) : 0x80000000u)
-                                        : (any ? (uint32_t)(((int64_t)col * Cin + c0) * 8) : 0x80000000u);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) w[ks][q] = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)(off + 16 * q), 0, 0);
-        }
-        // masks of the block holding the b word (j = n)
-        if (jt == n_jt - 1) {
-            const uint32_t *rsrc = P.r + b * Cout * F + f;
-            for (int o = tid; o < n_ot * 64; o += kDeepThreads) lds_r[o] = o < Cout ? rsrc[(int64_t)o * F] : 0u;
-        }
-        v4i A[3][2];
-        load_frags(f, 0, 0, A);
-#pragma unroll
-        for (int ks = 0; ks < kDeepMaxKs; ++ks) {
-            if (ks >= n_ks) break;
-            // seeded: words j = col < n of the thread's 8 channels from the
-            // public stream (zero where the words were loaded)
-            uint64_t gen[8] = {};
+    // compute waves: block x's words (its ring slot, or the public stream
+    // when seeded) -> digit planes, and (streamed) its masks to the masks in
+    // use; unit u = (K step, column, 8-channel group)
+    auto convert = [&](int64_t x) {
+        int64_t b, f;
+        int jt;
+        coords(blo + x, b, f, jt);
+        const int col0 = jt * kDeepCols;
+        const uint8_t *staging = slot(x);
+        if (!AL && jt == n_jt - 1)
+            for (int o = tid; o < n_mask; o += kDeepComputeWaves * 64)
+                lds_r[o] = reinterpret_cast<const uint32_t *>(staging + L.words)[o];
+        for (int u = tid; u < n_ks * 256; u += kDeepComputeWaves * 64) {
+            const int uks = u >> 8, col = (u >> 3) & 31, sc = (u >> 1) & 3, h = u & 1;
+            const int c0 = uks * 64 + sc * 16 + h * 8;
+            uint64_t wd[8];
             if (SEEDED) {
-                const int c0 = ks * 64 + ld_sc * 16 + ld_h * 8;
-                const bool on = c0 < Cin && col < P.n;
+                // words j < n from the public stream, the b word loaded
+                const bool on = c0 < Cin && col0 + col < P.n;
                 const uint64_t q0 = P.idx0 + (uint64_t)((b * F + f) * Cin + c0);
-                uint64_t z = P.seed_a + (q0 * (uint64_t)P.n + (uint64_t)col + 1) * kGamma;
-                const uint64_t step = (uint64_t)P.n * kGamma;
+                uint64_t z = P.seed_a + (q0 * (uint64_t)P.n + (uint64_t)(col0 + col) + 1) * kGamma;
+                const uint64_t zstep = (uint64_t)P.n * kGamma;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    const uint64_t a = splitmix_mix(z);
-                    gen[i] = on ? a : 0ull;
-                    z += step;
+                    wd[i] = on ? splitmix_mix(z) : 0ull;
+                    z += zstep;
                 }
+                if (col0 + col == P.n) {
+                    const uint64_t *bw = P.b_in + (b * F + f) * Cin;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) wd[i] = c0 + i < Cin ? bw[c0 + i] : 0ull;
+                }
+            } else if (c0 >= Cin) {
+#pragma unroll
+                for (int i = 0; i < 8; ++i) wd[i] = 0;
+            } else if (swz) {
+                const uint32_t run = (uint32_t)(col * (Cin / 8) + c0 / 8), x = deep_swz(col, (c0 / 8) & 7);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const u32x4 t = *reinterpret_cast<const u32x4 *>(staging + (run * 4 + (q ^ x)) * 16);
+                    wd[2 * q] = (uint64_t)t.y << 32 | t.x;
+                    wd[2 * q + 1] = (uint64_t)t.w << 32 | t.z;
+                }
+            } else {
+                // 8-byte aligned words; a group straddling Cin reads the next
+                // column's words (or, past the last column, what follows the
+                // words in LDS), which meet zero weights
+                const uint64_t *sw = reinterpret_cast<const uint64_t *>(staging) + (col * Cin + c0);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) wd[i] = sw[i];
             }
             uint32_t lo[8], hi[8], pl[8][2];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const uint64_t v0 = ((uint64_t)w[ks][q].y << 32 | w[ks][q].x) + gen[2 * q] + 0x8080808080808080ull;
-                const uint64_t v1 = ((uint64_t)w[ks][q].w << 32 | w[ks][q].z) + gen[2 * q + 1] + 0x8080808080808080ull;
-                lo[2 * q] = (uint32_t)v0;
-                hi[2 * q] = (uint32_t)(v0 >> 32);
-                lo[2 * q + 1] = (uint32_t)v1;
-                hi[2 * q + 1] = (uint32_t)(v1 >> 32);
+            for (int i = 0; i < 8; ++i) {
+                const uint64_t v = wd[i] + 0x8080808080808080ull;
+                lo[i] = (uint32_t)v;
+                hi[i] = (uint32_t)(v >> 32);
             }
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
@@ -733,82 +871,170 @@ __global__ __launch_bounds__(kDeepThreads, 2) void homconv_deep_kernel(HcLayer P
                 transpose4(hi[4 * d], hi[4 * d + 1], hi[4 * d + 2], hi[4 * d + 3], pl[4][d], pl[5][d], pl[6][d],
                            pl[7][d]);
             }
-            const int pslot = plane_slot(ld_col, ld_sc) * 16 + ld_h * 8;
+            const int pslot = plane_slot(col, sc) * 16 + h * 8;
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-                *reinterpret_cast<u32x2 *>(planes(ks) + k * kDeepPlane + pslot) =
+                *reinterpret_cast<u32x2 *>(planes(uks) + k * kDeepPlane + pslot) =
                     u32x2{pl[k][0] ^ 0x80808080u, pl[k][1] ^ 0x80808080u};
         }
-        __syncthreads();
+    };
 
-        const uint64_t *oblk = P.ct_out + ((b * F + f) * rowlen + jt * kDeepCols) * Cout;
-        const uint32_t obytes = (uint32_t)((rowlen - jt * kDeepCols) * Cout * 8);
-        const bool b_lane = jt * kDeepCols + b_col == P.n;
-        int ot = 0, ks = 0;
-        for (int ph = 0; ph < n_ph; ++ph) {
-            // the next phase's fragments (past the block's end: this phase's again)
-            const int ks2 = ks + 1 < n_ks ? ks + 1 : 0;
-            const int ot2 = ks + 1 < n_ks ? ot : (ot + 1 < n_ot ? ot + 1 : ot);
-            v4i An[3][2];
-            load_frags(f, ph + 1 < n_ph ? ks2 : ks, ph + 1 < n_ph ? ot2 : ot, An);
-
-            auto contract = [&](auto fresh_tag) {
-                constexpr bool FRESH = decltype(fresh_tag)::value;
-                const v4i zero = {0, 0, 0, 0};
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const v4i B = *reinterpret_cast<const v4i *>(planes(ks) + b_base + k * kDeepPlane);
-#pragma unroll
-                    for (int l = 0; l < 3; ++l) {
-                        if (k + l >= 8) break;
-                        const bool first = FRESH && (k == 0 || l == 2);
-#pragma unroll
-                        for (int rb = 0; rb < 2; ++rb)
-                            acc[k + l][rb] =
-                                __builtin_amdgcn_mfma_i32_16x16x64_i8(A[l][rb], B, first ? zero : acc[k + l][rb], 0, 0, 0);
-                    }
-                }
-            };
-            if (ks == 0)
-                contract(std::true_type{});
-            else
-                contract(std::false_type{});
-
-            // the tile's last K step: recombine, HomShare on the b word, store
-            // (other phases issue the same stores, dropped)
-            const bool last = ks == n_ks - 1;
-            if (last) {
-                auto recombine_all = [&](auto small_tag) {
-                    constexpr bool SMALL = decltype(small_tag)::value;
-#pragma unroll
-                    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            res[rb][i] = recombine<SMALL>(acc[0][rb][i], acc[1][rb][i], acc[2][rb][i], acc[3][rb][i],
-                                                          acc[4][rb][i], acc[5][rb][i], acc[6][rb][i], acc[7][rb][i]);
-                };
-                if (Cin <= kSmallCin)
-                    recombine_all(std::true_type{});
-                else
-                    recombine_all(std::false_type{});
-                if (b_lane) {
-#pragma unroll
-                    for (int rb = 0; rb < 2; ++rb)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) res[rb][i] += delta * (uint64_t)lds_r[ot * 64 + out_row + 4 * rb + i];
-                }
-            }
-            const __amdgpu_buffer_rsrc_t rso = make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(oblk)),
-                                                         __builtin_amdgcn_readfirstlane(last ? obytes : 0u));
-            store_lane_words<WIDE_STORE, false, 0>(res, rso, b_col, ot * 64 + 32 * rg, g, Cout, last);
+    // streamed: this wave's fragments of unit (f, ks, ot) from the L2, items
+    // [limb][row block][lane] (none past the last row tile: the loads return
+    // zero); resident: the same items from LDS
+    auto load_frags = [&](int64_t f, int ks, int ot, v4i (&A)[3][2]) {
+        if (AL) {
+            const uint8_t *u = tail + (size_t)(ks * n_ot + (ot < n_ot ? ot : 0)) * kFragBytes;
 #pragma unroll
             for (int l = 0; l < 3; ++l)
 #pragma unroll
-                for (int rb = 0; rb < 2; ++rb) A[l][rb] = An[l][rb];
-            ks = ks2;
-            ot = ot2;
+                for (int rb = 0; rb < 2; ++rb)
+                    A[l][rb] = *reinterpret_cast<const v4i *>(u + ((l * 4 + half * 2 + rb) * 64 + lane) * 16);
+            return;
         }
-        __syncthreads();  // planes and masks are rewritten by the next block
+        const int64_t unit = (f * n_ks + ks) * n_ot + (ot < n_ot ? ot : 0);
+        const __amdgpu_buffer_rsrc_t ra =
+            make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(P.w_pack) + unit * kFragBytes),
+                      __builtin_amdgcn_readfirstlane(ot < n_ot ? (uint32_t)kFragBytes : 0u));
+#pragma unroll
+        for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb) {
+                const u32x4 t =
+                    __builtin_amdgcn_raw_buffer_load_b128(ra, ((l * 4 + half * 2 + rb) * 64 + lane) * 16, 0, 0);
+                A[l][rb] = v4i{(int)t.x, (int)t.y, (int)t.z, (int)t.w};
+            }
+    };
+
+    v4i A0[3][2], A1[3][2];
+    if (!AL) load_frags(freq(blo), 0, pair_row, A0);
+    __syncthreads();
+
+    v4i acc[8][2];
+    uint64_t res[2][4];
+    int64_t f = 0, f_next = 0, b = 0;
+    int col0 = 0;
+    const uint64_t *oblk = nullptr;
+    uint32_t obytes = 0;
+
+    // one phase (row-tile pair otp, K step KS) of the current block. Streamed,
+    // it contracts with the fragments in A while those of the next phase load
+    // into An; the K step is a compile-time index, so the phases that store
+    // are known statically and every wait counts exactly the operations
+    // issued after the awaited loads. Resident, A is read from LDS here.
+    auto step = [&](auto ks_tag, v4i (&A)[3][2], v4i (&An)[3][2], int otp) {
+        constexpr int KS = decltype(ks_tag)::value;
+        const int ot = 2 * otp + pair_row;
+        if (AL) {
+            load_frags(f, KS, ot, A);
+        } else {
+            // the next phase's fragments (past the block's end: the next block's first)
+            if (KS + 1 < NKS)
+                load_frags(f, KS + 1, ot, An);
+            else if (otp + 1 < n_otp)
+                load_frags(f, 0, ot + 2, An);
+            else
+                load_frags(f_next, 0, pair_row, An);
+        }
+
+        const v4i zero = {0, 0, 0, 0};
+        if (ot < n_ot) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const v4i Bk = *reinterpret_cast<const v4i *>(planes(KS) + b_base + k * kDeepPlane);
+#pragma unroll
+                for (int l = 0; l < 3; ++l) {
+                    if (k + l >= 8) break;
+                    const bool first = KS == 0 && (k == 0 || l == 2);
+#pragma unroll
+                    for (int rb = 0; rb < 2; ++rb)
+                        acc[k + l][rb] =
+                            __builtin_amdgcn_mfma_i32_16x16x64_i8(A[l][rb], Bk, first ? zero : acc[k + l][rb], 0, 0, 0);
+                }
+            }
+        }
+        if constexpr (KS == NKS - 1) {
+            // the tile's last K step: recombine, HomShare on the b word,
+            // store (dropped past the last row tile, so that every such
+            // phase issues the same stores)
+            if (Cin <= kSmallCin) {
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        res[rb][i] = recombine<true>(acc[0][rb][i], acc[1][rb][i], acc[2][rb][i], acc[3][rb][i],
+                                                     acc[4][rb][i], acc[5][rb][i], acc[6][rb][i], acc[7][rb][i]);
+            } else {
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        res[rb][i] = recombine<false>(acc[0][rb][i], acc[1][rb][i], acc[2][rb][i], acc[3][rb][i],
+                                                      acc[4][rb][i], acc[5][rb][i], acc[6][rb][i], acc[7][rb][i]);
+            }
+            if (col0 + b_col == P.n && ot < n_ot) {
+                const int o0 = ot * 64 + 32 * half + 8 * g;
+                const uint32_t *rsrc = P.r + b * Cout * F + f;
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int o = o0 + 4 * rb + i;
+                        const uint32_t r = AL ? (o < Cout ? rsrc[(int64_t)o * F] : 0u) : lds_r[o];
+                        res[rb][i] += delta * (uint64_t)r;
+                    }
+            }
+            const __amdgpu_buffer_rsrc_t rso = make_rsrc(uniform_ptr(reinterpret_cast<const uint8_t *>(oblk)),
+                                                         __builtin_amdgcn_readfirstlane(ot < n_ot ? obytes : 0u));
+            store_lane_words<WIDE_STORE, false, 0>(res, rso, b_col, ot * 64 + 32 * half, g, Cout, ot < n_ot);
+        }
+    };
+    // the K steps of one row-tile pair; PAR: which register set holds the
+    // first step's fragments
+    auto pair = [&](auto par_tag, int otp) {
+        constexpr int PAR = decltype(par_tag)::value;
+        auto S = [&](auto ks_tag) {
+            constexpr int KS = decltype(ks_tag)::value;
+            if constexpr (((KS + PAR) & 1) == 0)
+                step(ks_tag, A0, A1, otp);
+            else
+                step(ks_tag, A1, A0, otp);
+        };
+        S(std::integral_constant<int, 0>{});
+        if constexpr (NKS > 1) S(std::integral_constant<int, 1>{});
+        if constexpr (NKS > 2) S(std::integral_constant<int, 2>{});
+        if constexpr (NKS > 3) S(std::integral_constant<int, 3>{});
+    };
+
+    for (int64_t x = 0; x < nblk; ++x) {
+        const int64_t blk = blo + x;
+        convert(x);
+        __syncthreads();  // planes and masks written, the slot free
+        int jt;
+        coords(blk, b, f, jt);
+        f_next = freq(x + 1 < nblk ? blk + 1 : blk);
+        col0 = jt * kDeepCols;
+        oblk = P.ct_out + ((b * F + f) * rowlen + col0) * Cout;
+        obytes = (uint32_t)((rowlen - col0) * Cout * 8);
+        if constexpr (AL || NKS % 2 == 0) {
+            for (int otp = 0; otp < n_otp; ++otp) pair(std::integral_constant<int, 0>{}, otp);
+        } else {
+            int otp = 0;
+            for (; otp + 1 < n_otp; otp += 2) {
+                pair(std::integral_constant<int, 0>{}, otp);
+                pair(std::integral_constant<int, 1>{}, otp + 1);
+            }
+            if (otp < n_otp) {
+                // an odd number of phases: the next block's fragments are in
+                // A1; move them to A0 (this waits for them)
+                pair(std::integral_constant<int, 0>{}, otp);
+#pragma unroll
+                for (int l = 0; l < 3; ++l)
+#pragma unroll
+                    for (int rb = 0; rb < 2; ++rb) A0[l][rb] = A1[l][rb];
+            }
+        }
+        __syncthreads();  // planes read by every compute wave; the next block's words landed
     }
 }
 
@@ -1234,42 +1460,56 @@ static int launch_narrow(const ensei_ctx *ctx, const HcLayer &P, HcSchedule sche
 
 // Deep kernel launch, if the layer suits it (homconv_deep_fits). Returns
 // ENSEI_ERR_LIMIT (nothing launched) otherwise.
-constexpr int kLdsBytes = 160 * 1024;
-static size_t deep_lds_bytes(const HcLayer &P) { return (size_t)P.n_ks * 8 * kDeepPlane + (size_t)P.n_ot * 64 * 4; }
-
-// Seeded input: the deep kernel generates a block's words once for all of its
-// row tiles (the streaming kernel once per row tile), so it takes every layer
-// with two or more row tiles.
-static bool deep_fits_seeded(const HcLayer &P) {
-    return P.Cin >= kPairedCin && P.n_ks <= kDeepMaxKs && P.n_ot >= 2 && deep_lds_bytes(P) <= (size_t)kLdsBytes / 2;
-}
-
 bool homconv_deep_fits(const HcLayer &P, bool seeded) {
-    if (seeded) return deep_fits_seeded(P);
-    // all K steps of a block in half the LDS, several row tiles, and at least
-    // four (row tile, K step) phases per block to share the conversion
-    return P.Cin >= kPairedCin && P.n_ks <= kDeepMaxKs && P.n_ot >= 2 && P.n_ot * P.n_ks >= 4 &&
-           deep_lds_bytes(P) <= (size_t)kLdsBytes / 2;
+    // all K steps of a block in LDS beside a staging buffer, several row
+    // tiles and (plain input) at least four (row tile, K step) pairs per block
+    // to share the conversion; seeded input takes every layer with two or more
+    // row tiles (the stream is generated once per block, not per row tile)
+    return P.Cin >= kPairedCin && P.n_ks <= kDeepMaxKs && P.n_ot >= 2 && (seeded || P.n_ot * P.n_ks >= 4) &&
+           DeepLds(P.Cin, P.n_ks, P.n_ot, seeded, false, 1).total <= (size_t)kDeepLds;
 }
 
 template <bool SEEDED>
 static int launch_deep(const ensei_ctx *ctx, const HcLayer &P, hipStream_t stream) {
     if (!homconv_deep_fits(P, SEEDED)) return ENSEI_ERR_LIMIT;
-    const size_t lds = deep_lds_bytes(P);
+    // resident fragments when the frequency's set fits beside the rest; then
+    // as many staging buffers as fit (1, 2 or 4). With streamed fragments
+    // one: more blocks in flight lengthen the fragment loads' round trips
+    // more than they gain.
+    const bool al = DeepLds(P.Cin, P.n_ks, P.n_ot, SEEDED, true, 1).total <= (size_t)kDeepLds;
+    int ring = 1;
+    if (al)
+        for (int r : {4, 2})
+            if (DeepLds(P.Cin, P.n_ks, P.n_ot, SEEDED, true, r).total <= (size_t)kDeepLds) {
+                ring = r;
+                break;
+            }
+    const size_t lds = DeepLds(P.Cin, P.n_ks, P.n_ot, SEEDED, al, ring).total;
     const bool wide = P.Cout % 2 == 0;
-    auto kernel = wide ? homconv_deep_kernel<true, SEEDED> : homconv_deep_kernel<false, SEEDED>;
-    static std::atomic<bool> attr[kMaxDevices][2];  // dynamic-LDS limit raised, by device and store width
+    using Kern = void (*)(HcLayer, uint64_t, int);
+    static const Kern kernels[2][2][kDeepMaxKs] = {
+        {{homconv_deep_kernel<false, SEEDED, 1, false>, homconv_deep_kernel<false, SEEDED, 2, false>,
+          homconv_deep_kernel<false, SEEDED, 3, false>, homconv_deep_kernel<false, SEEDED, 4, false>},
+         {homconv_deep_kernel<false, SEEDED, 1, true>, homconv_deep_kernel<false, SEEDED, 2, true>,
+          homconv_deep_kernel<false, SEEDED, 3, true>, homconv_deep_kernel<false, SEEDED, 4, true>}},
+        {{homconv_deep_kernel<true, SEEDED, 1, false>, homconv_deep_kernel<true, SEEDED, 2, false>,
+          homconv_deep_kernel<true, SEEDED, 3, false>, homconv_deep_kernel<true, SEEDED, 4, false>},
+         {homconv_deep_kernel<true, SEEDED, 1, true>, homconv_deep_kernel<true, SEEDED, 2, true>,
+          homconv_deep_kernel<true, SEEDED, 3, true>, homconv_deep_kernel<true, SEEDED, 4, true>}}};
+    const Kern kernel = kernels[wide][al][P.n_ks - 1];
+    // dynamic-LDS limit raised, by device, store width, fragments and K steps
+    static std::atomic<bool> attr[kMaxDevices][2][2][kDeepMaxKs];
     const bool cached = ctx->device < kMaxDevices;
-    if (!cached || !attr[ctx->device][wide].load(std::memory_order_acquire)) {
-        if (hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes / 2) !=
+    if (!cached || !attr[ctx->device][wide][al][P.n_ks - 1].load(std::memory_order_acquire)) {
+        if (hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, kDeepLds) !=
             hipSuccess)
             return ENSEI_ERR_HIP;
-        if (cached) attr[ctx->device][wide].store(true, std::memory_order_release);
+        if (cached) attr[ctx->device][wide][al][P.n_ks - 1].store(true, std::memory_order_release);
     }
-    // two resident workgroups per CU
+    // one resident workgroup per CU
     const int64_t blocks_total = P.B * P.F * ((P.n + 1 + kDeepCols - 1) / kDeepCols);
-    const int64_t grid = blocks_total < 2 * (int64_t)ctx->num_cus ? blocks_total : 2 * (int64_t)ctx->num_cus;
-    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(kDeepThreads), lds, stream, P, ctx->delta);
+    const int64_t grid = blocks_total < (int64_t)ctx->num_cus ? blocks_total : (int64_t)ctx->num_cus;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(kDeepThreads), lds, stream, P, ctx->delta, ring);
     return launch_status();
 }
 

@@ -63,20 +63,37 @@ def counter_means(pmc_dir: str, counter: str):
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
-def stage_kib(pmc_dir: str, counter: str, prefix: str, per_step: int, steps: int) -> float:
-    """Counter KiB of one step's dispatches of the kernels whose short name
-    starts with prefix: the last per_step * steps such dispatches (in dispatch
-    order), summed and divided by steps."""
+def stage_runs(pmc_dir: str, counter: str, prefix: str):
+    """The dispatches of kernels whose short name starts with prefix, in
+    dispatch order, grouped into runs of consecutive such dispatches (one
+    run per step's stage: the stages are separated by other kernels, and the
+    number of launches in a stage may differ between runs of the plan's
+    tuner). Each run is a list of (kernel, counter KiB)."""
     rows = []
     with open(os.path.join(pmc_dir, "run_counter_collection.csv")) as fh:
         for i, r in enumerate(csv.DictReader(fh)):
             if r["Counter_Name"] == counter:
                 rows.append((int(r.get("Dispatch_Id") or i), short_name(r["Kernel_Name"]), float(r["Counter_Value"])))
     rows.sort()
-    vals = [v for _, k, v in rows if k.startswith(prefix)]
-    last = vals[-per_step * steps:]
-    assert len(last) == per_step * steps, "fewer dispatches than requested"
-    return sum(last) / steps
+    runs, cur = [], []
+    for _, k, v in rows:
+        if k.startswith(prefix):
+            cur.append((k, v))
+        elif cur:
+            runs.append(cur)
+            cur = []
+    if cur:
+        runs.append(cur)
+    return runs
+
+
+def stage_kib(pmc_dir: str, counter: str, prefix: str, steps: int):
+    """Counter KiB of one step's stage (mean over the last `steps` runs of
+    stage_runs) and the last run's dispatches."""
+    runs = stage_runs(pmc_dir, counter, prefix)
+    assert len(runs) >= steps, "fewer stage runs than requested"
+    last = runs[-steps:]
+    return sum(sum(v for _, v in r) for r in last) / steps, last[-1]
 
 
 def step_kernels(trace_dir: str, per_step: int, steps: int):
@@ -118,7 +135,6 @@ def main():
     ap.add_argument("--stage-prefix", help="sum the HBM bytes of one step's dispatches of these kernels")
     ap.add_argument("--per-step", type=int, default=0, help="dispatches of one step in the trace")
     ap.add_argument("--steps", type=int, default=1, help="trace steps whose dispatches are averaged (the last ones)")
-    ap.add_argument("--stage-per-step", type=int, default=0, help="dispatches of the prefix kernels per step")
     ap.add_argument("--pmc-steps", type=int, default=1, help="counter-run steps averaged (the last ones)")
     args = ap.parse_args()
 
@@ -171,13 +187,18 @@ def main():
                 }
     if args.stage_prefix and args.fetch and args.write and args.copy_fetch and args.copy_write:
         ff, fw = copy_factor(args.copy_fetch, "FETCH_SIZE"), copy_factor(args.copy_write, "WRITE_SIZE")
-        fk = stage_kib(args.fetch, "FETCH_SIZE", args.stage_prefix, args.stage_per_step, args.pmc_steps)
-        wk = stage_kib(args.write, "WRITE_SIZE", args.stage_prefix, args.stage_per_step, args.pmc_steps)
+        fk, flast = stage_kib(args.fetch, "FETCH_SIZE", args.stage_prefix, args.pmc_steps)
+        wk, wlast = stage_kib(args.write, "WRITE_SIZE", args.stage_prefix, args.pmc_steps)
         hbm = fk * 1024 * ff + wk * 1024 * fw
-        lines += ["", f"## One step's {args.stage_prefix}* dispatches ({args.stage_per_step} per step, mean of the "
-                      f"last {args.pmc_steps} steps of the counter runs)", "",
+        lines += ["", f"## One step's {args.stage_prefix}* dispatches (mean of the last {args.pmc_steps} steps of the "
+                      "counter runs)", "",
                   f"FETCH_SIZE {fk:.0f} KiB, WRITE_SIZE {wk:.0f} KiB: {hbm / 1e6:.1f} MB of HBM traffic per step "
                   "(calibrated)."]
+        if [k for k, _ in flast] == [k for k, _ in wlast]:
+            lines += ["", "The last step's dispatches (calibrated MB):", "",
+                      "| dispatch | kernel | fetched | written |", "|---|---|---|---|"]
+            for i, ((k, fv), (_, wv)) in enumerate(zip(flast, wlast)):
+                lines.append(f"| {i + 1} | {k} | {fv * 1024 * ff / 1e6:.1f} | {wv * 1024 * fw / 1e6:.1f} |")
         record = {"kernel": f"{args.stage_prefix}* (one step)", "workload": args.workload,
                   "hbm_bytes_per_launch": int(round(hbm)), "fetch_kib": fk, "write_kib": wk, "fetch_factor": ff,
                   "write_factor": fw, "code_sha256": code_digest(HOMCONV_SRC)}
