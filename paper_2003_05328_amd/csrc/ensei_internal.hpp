@@ -66,6 +66,30 @@ __device__ __forceinline__ uint32_t mulmod_lazy(uint32_t a, uint32_t w, uint32_t
     return mul24(a, w) - mul24_pinned(q, p);
 }
 
+// mulmod_lazy for a twiddle in scalar registers (w, wq wave-uniform), every
+// multiply pinned to the full-rate 24-bit instructions: where the compiler
+// cannot bound a below 2^24 it would otherwise keep the masks and fall back
+// to the quarter-rate 32-bit multiply.
+__device__ __forceinline__ uint32_t mulmod_lazy_su(uint32_t a, uint32_t w, uint32_t wq, uint32_t p) {
+    uint32_t lo, hi, aw, qp;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(lo) : "s"(wq), "v"(a));
+    asm("v_mul_hi_u32_u24 %0, %1, %2" : "=v"(hi) : "s"(wq), "v"(a));
+    const uint32_t q = __builtin_amdgcn_alignbit(hi, lo, 24);
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(aw) : "s"(w), "v"(a));
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(qp) : "s"(p), "v"(q));
+    return aw - qp;
+}
+
+// x mod p up to one p, for x < 2^24 and 256 < p: with m = floor(2^32 / p),
+// q = floor(x m / 2^32) is floor(x / p) or one less, so x - q p lies in
+// [0, 2p). Three full-rate ops.
+__device__ __forceinline__ uint32_t reduce_2p(uint32_t x, uint32_t m, uint32_t p) {
+    uint32_t q, qp;
+    asm("v_mul_hi_u32_u24 %0, %1, %2" : "=v"(q) : "s"(m), "v"(x));
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(qp) : "s"(p), "v"(q));
+    return x - qp;
+}
+
 // x in [0, 2m) -> [0, m): unsigned min picks x when x < m (x - m wraps high).
 __device__ __forceinline__ uint32_t reduce_once(uint32_t x, uint32_t m) {
     uint32_t y = x - m;

@@ -57,6 +57,34 @@ __device__ __forceinline__ void dif_line(uint32_t (&v)[L], const uint2 *__restri
     }
 }
 
+// The same transform for p < 2^17 without the per-stage reductions: the
+// sums are kept as they are and the differences are offset by the stage's
+// input bound B (inputs < B give sums and offset differences < 2 B); a
+// twiddle multiplication brings its value back below 2p. From inputs < 2p
+// the outputs stay below 2p L <= 128 p < 2^24, the range of the 24-bit
+// multiplies, for L <= 64.
+template <int L>
+__device__ __forceinline__ void dif_line_lazy(uint32_t (&v)[L], const uint2 *__restrict__ tw, uint32_t p) {
+    uint32_t B = 2 * p;  // bound of this stage's inputs
+#pragma unroll
+    for (int m = L; m >= 2; m >>= 1) {
+        const int h = m >> 1;
+#pragma unroll
+        for (int j = 0; j < h; ++j) {
+            uint2 w = make_uint2(1, 0);
+            if (j > 0) w = tw[h - 1 + j];
+#pragma unroll
+            for (int b = 0; b < L; b += m) {
+                const uint32_t u = v[b + j], t = v[b + j + h];
+                const uint32_t d = u - t + B;
+                v[b + j] = u + t;
+                v[b + j + h] = (j == 0) ? d : mulmod_lazy_su(d, w.x, w.y, p);
+            }
+        }
+        B *= 2;
+    }
+}
+
 // Half h of a length-L DIF transform of the line x[0], x[st], ..., x[(L-1) st]
 // (residues < 2p): the first stage's sums (h = 0) or twiddled differences
 // (h = 1), then the length-L/2 transform. out[k] is output 2k + h in
@@ -181,9 +209,156 @@ __global__ __launch_bounds__((NttShape<LOGH, LOGW>::NT)) void ntt2d_kernel(const
     }
 }
 
+// Square grids up to 64 x 64 (the image and filter transforms of every
+// workload here): one wave transforms G = 64 / L grids at a time with no
+// workgroup barrier at all. Lane (g, r) holds row r of grid g in registers
+// (16-byte loads straight from HBM), transforms it there (length-L DIF,
+// outputs in bit-reversed register order) and writes it to the wave's own LDS
+// tile (rows padded to L + 1 words: conflict-free both ways); lane (g, c) then
+// reads column c, transforms it in registers, and stores output row k of all
+// the wave's columns with one coalesced store per k. Per point this is one
+// LDS write and one read, and every butterfly is in registers. The waves are
+// persistent: while a wave works on one group of grids, the rows of its next
+// group are already on their way into registers, so the HBM latency hides
+// behind the butterflies (the LDS tiles, not the registers, bound the waves
+// per CU, so the prefetch costs no occupancy).
+// MODE as for ntt2d_kernel; wsrc/kh/kw for MODE 2. LAZY (p < 2^17): the
+// line transforms skip their per-stage reductions (dif_line_lazy); one
+// Barrett step (reduce_2p, pm = floor(2^32 / p)) brings the rows back below
+// 2p before the columns, and the outputs before the final reduction.
+constexpr int kNttWaves = 4;  // waves per workgroup
+
+template <int LOGL, int MODE, bool LAZY>
+__global__ __launch_bounds__(kNttWaves * 64) void ntt2d_wave_kernel(const uint32_t *in, uint32_t *out, int64_t batch,
+                                                                   const uint2 *__restrict__ tw, uint32_t p,
+                                                                   uint32_t scale, uint32_t scale_q,
+                                                                   const int32_t *__restrict__ wsrc, int kh, int kw,
+                                                                   uint32_t pm) {
+    constexpr int L = 1 << LOGL, F = L * L, G = 64 / L, STR = L + 1;
+    extern __shared__ uint32_t lds[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t *tile = lds + wave * (G * L * STR);
+    const int g = lane / L, i = lane % L;  // rows phase: row i of grid g; columns phase: column i
+    const uint2 *twd = tw + (MODE == 1 ? kTwPerDir : 0);
+    const int64_t units = (batch + G - 1) / G, stride = (int64_t)gridDim.x * kNttWaves;
+
+    // row i of grid g of unit u into nxt (zero past the batch)
+    uint32_t nxt[L];
+    auto load_rows = [&](int64_t u) {
+        const int64_t grid = u * G + g;
+        const bool live = grid < batch;
+        if (MODE == 2) {
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                uint32_t x = 0;
+                if (live && i < kh && k < kw) {
+                    const int32_t t = wsrc[(grid * kh + i) * kw + k] % (int32_t)p;
+                    x = (uint32_t)(t < 0 ? t + (int32_t)p : t);
+                }
+                nxt[k] = x;
+            }
+        } else if constexpr (L >= 4) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(in + grid * F + i * L);
+#pragma unroll
+            for (int q = 0; q < L / 4; ++q) {
+                const uint4 x = live ? src[q] : make_uint4(0, 0, 0, 0);
+                nxt[4 * q] = x.x;
+                nxt[4 * q + 1] = x.y;
+                nxt[4 * q + 2] = x.z;
+                nxt[4 * q + 3] = x.w;
+            }
+        } else {
+            const uint2 x = live ? *reinterpret_cast<const uint2 *>(in + grid * F + i * L) : make_uint2(0, 0);
+            nxt[0] = x.x;
+            nxt[1] = x.y;
+        }
+    };
+
+    int64_t u = (int64_t)blockIdx.x * kNttWaves + wave;
+    if (u < units) load_rows(u);
+    for (; u < units; u += stride) {
+        uint32_t v[L];
+#pragma unroll
+        for (int k = 0; k < L; ++k) v[k] = nxt[k];
+        // the next group's rows, in flight during this group's transforms
+        if (u + stride < units) load_rows(u + stride);
+        // rows
+        if (LAZY) {
+            dif_line_lazy<L>(v, twd, p);
+#pragma unroll
+            for (int k = 0; k < L; ++k) v[k] = reduce_2p(v[k], pm, p);
+        } else {
+            dif_line<L>(v, twd, p);
+        }
+        uint32_t *row = tile + (g * L + i) * STR;
+#pragma unroll
+        for (int k = 0; k < L; ++k) row[k] = v[BitRev<L>::apply(k)];
+        // the tile is the wave's own: lanes only need each other's writes
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // columns
+        const uint32_t *col = tile + g * L * STR + i;
+#pragma unroll
+        for (int r = 0; r < L; ++r) v[r] = col[r * STR];
+        // every lane has read its column before the next group's rows are written
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (LAZY)
+            dif_line_lazy<L>(v, twd, p);
+        else
+            dif_line<L>(v, twd, p);
+        const int64_t grid = u * G + g;
+        if (grid < batch) {
+            uint32_t *dst = out + grid * F + i;
+#pragma unroll
+            for (int k = 0; k < L; ++k) {
+                uint32_t x = v[BitRev<L>::apply(k)];
+                if (MODE == 1)
+                    x = mulmod_lazy(x, scale, scale_q, p);
+                else if (LAZY)
+                    x = reduce_2p(x, pm, p);
+                dst[k * L] = reduce_once(x, p);
+            }
+        }
+    }
+}
+
 template <int LOGH, int LOGW, int MODE>
 static int launch_ntt(const uint32_t *in, uint32_t *out, int64_t batch, const ensei_ctx *ctx, uint32_t scale,
                       hipStream_t st, const int32_t *w, int kh, int kw) {
+    const uint32_t scale_q = (uint32_t)(((uint64_t)scale << 24) / ctx->p);
+    if constexpr (LOGH == LOGW && LOGH <= 6) {
+        constexpr int L = 1 << LOGH, G = 64 / L;
+        const size_t lds = (size_t)kNttWaves * G * L * (L + 1) * 4;
+        const bool lazy = ctx->p < (1u << 17);
+        auto kern = lazy ? ntt2d_wave_kernel<LOGH, MODE, true> : ntt2d_wave_kernel<LOGH, MODE, false>;
+        static std::atomic<bool> wave_attr[kMaxDevices][2];  // dynamic-LDS limit raised, by device and form
+        const bool cached = ctx->device < kMaxDevices;
+        if (lds > 48 * 1024 && (!cached || !wave_attr[ctx->device][lazy].load(std::memory_order_acquire))) {
+            if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+                hipSuccess)
+                return ENSEI_ERR_HIP;
+            if (cached) wave_attr[ctx->device][lazy].store(true, std::memory_order_release);
+        }
+        // persistent: as many workgroups as are resident at once, none idle
+        static std::atomic<int> resident[kMaxDevices][2];  // workgroups per CU (0: not yet known), by device and form
+        int per_cu = cached ? resident[ctx->device][lazy].load(std::memory_order_relaxed) : 0;
+        if (per_cu == 0) {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kNttWaves * 64, lds) != hipSuccess ||
+                per_cu < 1)
+                per_cu = 1;
+            if (cached) resident[ctx->device][lazy].store(per_cu, std::memory_order_relaxed);
+        }
+        const int64_t needed = (batch + kNttWaves * G - 1) / (kNttWaves * G);
+        const int64_t full = (int64_t)ctx->num_cus * per_cu;
+        const int64_t blocks = needed < full ? needed : full;
+        const uint32_t pm = (uint32_t)((1ull << 32) / ctx->p);
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kNttWaves * 64), lds, st, in, out, batch, ctx->d_tw,
+                           ctx->p, scale, scale_q, w, kh, kw, pm);
+        return launch_status();
+    }
     using S = NttShape<LOGH, LOGW>;
     const size_t lds = (size_t)S::LDS_WORDS * 4;
     auto kern = ntt2d_kernel<LOGH, LOGW, MODE>;
@@ -196,7 +371,6 @@ static int launch_ntt(const uint32_t *in, uint32_t *out, int64_t batch, const en
     }
     const int64_t blocks = (batch + S::T - 1) / S::T;
     if (blocks > 0x7fffffff) return ENSEI_ERR_LIMIT;
-    const uint32_t scale_q = (uint32_t)(((uint64_t)scale << 24) / ctx->p);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(S::NT), lds, st, in, out, batch, ctx->d_tw, ctx->p, scale,
                        scale_q, w, kh, kw);
     return launch_status();
