@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--packed", action="store_true",
                     help="only the packed (BFV) instantiation on Table 4's benchmarks, one JSON line")
     ap.add_argument("--packed-batch", type=int, default=64)
+    ap.add_argument("--ntt", action="store_true",
+                    help="only the NTT2D weight-batch measurements (the ntt2d entry of the default line)")
     ap.add_argument("--probe-copy", action="store_true",
                     help="run only a plain 1 GiB read + 1 GiB write elementwise kernel (counter calibration)")
     return ap.parse_args()
@@ -190,7 +192,7 @@ def ntt_throughput(ctx, batches, reps: int = 5):
     import torch
 
     dv = "cuda:0"
-    flush = torch.ones(1 << 28, dtype=torch.int32, device=dv)
+    flush = torch.ones(1 << 27, dtype=torch.int64, device=dv)  # summed in its own type: no converted copy
     sink = torch.zeros((), dtype=torch.int64, device=dv)
     bufs = []
     for grids, H, W in batches:
@@ -1180,6 +1182,17 @@ def main():
                           "warmup": args.warmup, "higher_is_better": True, "dtype": "u64", "data": "synthetic",
                           "config": {"workload": LAYER_WORKLOAD}, "seeded": res}), flush=True)
         sys.exit(0 if res["verified"] else 3)
+    if args.ntt:
+        stack = configs.stack_shapes(B=8)
+        big = configs.WORKLOADS["conv64x64(56)_c64to64_k3_n1024"]
+        res = {"stack8_weight_prep": ntt_throughput(ctx, [(S.Cout * S.Cin, S.H, S.W) for S in stack]),
+               "conv64x64_weight_prep": ntt_throughput(ctx, [(big.Cout * big.Cin, big.H, big.W)])}
+        main_row = res["conv64x64_weight_prep"]
+        print(json.dumps({"metric": "NTT2D points/s (64x64 weight batch, caches flushed before each launch)",
+                          "value": main_row["points_per_s"], "unit": "points/s", "n_gpus": 1,
+                          "higher_is_better": True, "dtype": "u32", "data": "synthetic",
+                          "config": {"workload": "conv64x64_weight_prep"}, "ntt2d": res}), flush=True)
+        return
     if args.chained:
         res = chained(ctx, args.steps, args.seed)
         print(json.dumps({"metric": "chained secure-conv rounds: ciphertext-MACs/s over both rounds",

@@ -1463,8 +1463,10 @@ static int launch_narrow(const ensei_ctx *ctx, const HcLayer &P, HcSchedule sche
 bool homconv_deep_fits(const HcLayer &P, bool seeded) {
     // all K steps of a block in LDS beside a staging buffer, several row
     // tiles and (plain input) at least four (row tile, K step) pairs per block
-    // to share the conversion; seeded input takes every layer with two or more
-    // row tiles (the stream is generated once per block, not per row tile)
+    // to share the conversion (the 64 -> 128 layer, two pairs, is faster on
+    // the streaming kernel: 700-750 against 930 us); seeded input takes every
+    // layer with two or more row tiles (the stream is generated once per
+    // block, not per row tile)
     return P.Cin >= kPairedCin && P.n_ks <= kDeepMaxKs && P.n_ot >= 2 && (seeded || P.n_ot * P.n_ks >= 4) &&
            DeepLds(P.Cin, P.n_ks, P.n_ot, seeded, false, 1).total <= (size_t)kDeepLds;
 }

@@ -136,6 +136,9 @@ def main():
     ap.add_argument("--per-step", type=int, default=0, help="dispatches of one step in the trace")
     ap.add_argument("--steps", type=int, default=1, help="trace steps whose dispatches are averaged (the last ones)")
     ap.add_argument("--pmc-steps", type=int, default=1, help="counter-run steps averaged (the last ones)")
+    ap.add_argument("--sq", action="append", default=[],
+                    help="a --pmc run directory whose counters are listed per kernel (mean per dispatch)")
+    ap.add_argument("--sq-prefix", default="", help="only kernels whose short name starts with this")
     args = ap.parse_args()
 
     lines = [f"# Kernel times and HBM traffic: {args.workload}", ""]
@@ -202,6 +205,30 @@ def main():
         record = {"kernel": f"{args.stage_prefix}* (one step)", "workload": args.workload,
                   "hbm_bytes_per_launch": int(round(hbm)), "fetch_kib": fk, "write_kib": wk, "fetch_factor": ff,
                   "write_factor": fw, "code_sha256": code_digest(HOMCONV_SRC)}
+    for sq_dir in args.sq:
+        per = defaultdict(lambda: defaultdict(list))
+        with open(os.path.join(sq_dir, "run_counter_collection.csv")) as fh:
+            disp = defaultdict(lambda: defaultdict(float))
+            names = {}
+            for r in csv.DictReader(fh):
+                k = short_name(r["Kernel_Name"])
+                if not k.startswith(args.sq_prefix):
+                    continue
+                d = int(r["Dispatch_Id"])
+                names[d] = k
+                disp[d][r["Counter_Name"]] += float(r["Counter_Value"])
+        for d, cs in disp.items():
+            for c, v in cs.items():
+                per[names[d]][c].append(v)
+        counters = sorted({c for cs in per.values() for c in cs})
+        lines += ["", f"## Counters of `{os.path.basename(os.path.normpath(sq_dir))}` (mean per dispatch, summed "
+                      "over the device's instances)", "",
+                  "| kernel | dispatches | " + " | ".join(counters) + " |",
+                  "|---|---|" + "---|" * len(counters)]
+        for k in sorted(per):
+            n = max(len(v) for v in per[k].values())
+            vals = [sum(per[k][c]) / len(per[k][c]) if per[k].get(c) else 0.0 for c in counters]
+            lines.append(f"| {k} | {n} | " + " | ".join(f"{v:.0f}" for v in vals) + " |")
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
