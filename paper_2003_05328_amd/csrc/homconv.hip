@@ -710,14 +710,30 @@ __global__ __launch_bounds__(kDeepThreads) void homconv_deep_kernel(HcLayer P, u
     if (blo >= bhi) return;
     const int64_t nblk = bhi - blo;
 
-    // block blk's image, frequency and column block
-    auto coords = [&](int64_t blk, int64_t &b, int64_t &f, int &jt) {
-        jt = (int)(blk % n_jt);
-        const int64_t fb = blk / n_jt;
-        b = fb % P.B;
-        f = fb / P.B;
+    // a block's column block, image and frequency: found by division once
+    // per walk, then stepped (the 64-bit divisions are long scalar sequences)
+    struct Pos {
+        int jt;
+        int64_t b, f;
     };
-    auto freq = [&](int64_t blk) { return blk / n_jt / P.B; };
+    auto locate = [&](int64_t blk) {
+        Pos q;
+        q.jt = (int)(blk % n_jt);
+        const int64_t fb = blk / n_jt;
+        q.b = fb % P.B;
+        q.f = fb / P.B;
+        return q;
+    };
+    auto advance = [&](Pos &q, int by) {
+        for (int s = 0; s < by; ++s)
+            if (++q.jt == n_jt) {
+                q.jt = 0;
+                if (++q.b == P.B) {
+                    q.b = 0;
+                    ++q.f;
+                }
+            }
+    };
 
     if (loader) {
         // Loader waves only issue LDS-DMA loads and wait for their own; their
@@ -731,10 +747,12 @@ __global__ __launch_bounds__(kDeepThreads) void homconv_deep_kernel(HcLayer P, u
         const int per_group = kDeepLoaderWaves / ring;
         const int grp = lw % ring, gw = lw / ring;  // group, wave within the group
         const bool act = gw < per_group;
-        auto load_block = [&](int64_t x) {
-            int64_t b, f;
-            int jt;
-            coords(blo + x, b, f, jt);
+        // 64-byte runs per column; a power of two for 64, 128 and 256 channels
+        const uint32_t gpc = (uint32_t)Cin / 8;
+        const int gpc_log2 = (gpc & (gpc - 1)) == 0 ? __builtin_ctz(gpc) : -1;
+        auto load_block = [&](int64_t x, const Pos &q) {
+            const int64_t b = q.b, f = q.f;
+            const int jt = q.jt;
             uint8_t *dst = slot(x);
             if (!SEEDED) {
                 const __amdgpu_buffer_rsrc_t rs = make_rsrc(
@@ -745,8 +763,9 @@ __global__ __launch_bounds__(kDeepThreads) void homconv_deep_kernel(HcLayer P, u
                     const uint32_t c = (uint32_t)i * 64 + lane;  // 16-byte chunk of the slot
                     uint32_t gc = c;
                     if (swz) {
-                        const uint32_t u = c >> 2, gpc = (uint32_t)Cin / 8;  // run u: column u / gpc, group u % gpc
-                        gc = (c & ~3u) | ((c & 3u) ^ deep_swz(u / gpc, (u % gpc) & 7));
+                        // run u: column u / gpc, group u % gpc
+                        const uint32_t u = c >> 2, col = gpc_log2 >= 0 ? u >> gpc_log2 : u / gpc;
+                        gc = (c & ~3u) | ((c & 3u) ^ deep_swz(col, (u - col * gpc) & 7));
                     }
                     const uint32_t d = __builtin_amdgcn_readfirstlane(
                         (uint32_t)(uintptr_t)(lds_ptr_t)(dst + (size_t)i * kDmaBytes));
@@ -784,24 +803,33 @@ __global__ __launch_bounds__(kDeepThreads) void homconv_deep_kernel(HcLayer P, u
         };
         // prologue: the fragments and block 0 landed before the first
         // barrier; blocks 1 .. ring - 1 on their way
-        if (AL) load_frags_lds(freq(blo));
-        if (act && grp == 0) load_block(0);
+        Pos cur = locate(blo);     // block x
+        Pos mine = cur;            // the next block this group loads
+        advance(mine, grp);
+        if (AL) load_frags_lds(cur.f);
+        if (act && grp == 0) load_block(0, mine);
         __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-        if (act && grp > 0 && grp < nblk) load_block(grp);
+        if (act && grp > 0 && grp < nblk) load_block(grp, mine);
+        advance(mine, ring);
         __builtin_amdgcn_s_barrier();
+        int64_t fprev = cur.f;
         for (int64_t x = 0; x < nblk; ++x) {
-            const int64_t blk = blo + x;
-            if (AL && x > 0 && freq(blk) != freq(blk - 1)) {
+            if (AL && cur.f != fprev) {
                 // the previous block's phases are done: its frequency's
                 // fragments can be replaced while the block is converted
                 // (this also waits for the blocks in flight)
-                load_frags_lds(freq(blk));
+                load_frags_lds(cur.f);
                 __builtin_amdgcn_s_waitcnt(0x0F70);
             }
+            fprev = cur.f;
             __builtin_amdgcn_s_barrier();  // block x converted: its slot is free
-            if (act && x % ring == grp && x + ring < nblk) load_block(x + ring);
+            if (x % ring == grp && x + ring < nblk) {
+                if (act) load_block(x + ring, mine);
+                advance(mine, ring);
+            }
             if (act && (x + 1) % ring == grp) __builtin_amdgcn_s_waitcnt(0x0F70);  // block x + 1 landed
             __builtin_amdgcn_s_barrier();  // block x contracted
+            advance(cur, 1);
         }
         return;
     }
@@ -809,10 +837,9 @@ __global__ __launch_bounds__(kDeepThreads) void homconv_deep_kernel(HcLayer P, u
     // compute waves: block x's words (its ring slot, or the public stream
     // when seeded) -> digit planes, and (streamed) its masks to the masks in
     // use; unit u = (K step, column, 8-channel group)
-    auto convert = [&](int64_t x) {
-        int64_t b, f;
-        int jt;
-        coords(blo + x, b, f, jt);
+    auto convert = [&](int64_t x, const Pos &q) {
+        const int64_t b = q.b, f = q.f;
+        const int jt = q.jt;
         const int col0 = jt * kDeepCols;
         const uint8_t *staging = slot(x);
         if (!AL && jt == n_jt - 1)
@@ -906,8 +933,10 @@ __global__ __launch_bounds__(kDeepThreads) void homconv_deep_kernel(HcLayer P, u
             }
     };
 
+    Pos cur = locate(blo), nxt = cur;  // block x and block x + 1
+    advance(nxt, 1);
     v4i A0[3][2], A1[3][2];
-    if (!AL) load_frags(freq(blo), 0, pair_row, A0);
+    if (!AL) load_frags(cur.f, 0, pair_row, A0);
     __syncthreads();
 
     v4i acc[8][2];
@@ -1007,13 +1036,12 @@ __global__ __launch_bounds__(kDeepThreads) void homconv_deep_kernel(HcLayer P, u
     };
 
     for (int64_t x = 0; x < nblk; ++x) {
-        const int64_t blk = blo + x;
-        convert(x);
+        convert(x, cur);
         __syncthreads();  // planes and masks written, the slot free
-        int jt;
-        coords(blk, b, f, jt);
-        f_next = freq(x + 1 < nblk ? blk + 1 : blk);
-        col0 = jt * kDeepCols;
+        b = cur.b;
+        f = cur.f;
+        f_next = x + 1 < nblk ? nxt.f : cur.f;
+        col0 = cur.jt * kDeepCols;
         oblk = P.ct_out + ((b * F + f) * rowlen + col0) * Cout;
         obytes = (uint32_t)((rowlen - col0) * Cout * 8);
         if constexpr (AL || NKS % 2 == 0) {
@@ -1035,6 +1063,8 @@ __global__ __launch_bounds__(kDeepThreads) void homconv_deep_kernel(HcLayer P, u
             }
         }
         __syncthreads();  // planes read by every compute wave; the next block's words landed
+        cur = nxt;
+        advance(nxt, 1);
     }
 }
 
