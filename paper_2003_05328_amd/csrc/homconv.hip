@@ -413,13 +413,87 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
         c.b = 0;
         if (c.L + 1 < nlayers) ++c.L;
     };
-    HcCoord cur, nx;
+    // cur: the unit being contracted; cv: the next one, being converted;
+    // nx: the last one issued
+    HcCoord cur, cv, nx;
     seek(cur, chunk == 0 ? t_lo : (int64_t)blockIdx.x * chunk);
     v4i acc[8][2];
 
+    // digit planes of one unit's 8 words per thread: 8 bytes of each plane,
+    // in pl (u: the unit, whose position the seeded form needs to generate
+    // its words)
+    auto convert = [&](const HcCoord &u, const HcBuf &buf, uint32_t (&pl)[8][2]) {
+        // seeded input: this thread's words j = col < n of its 8 channels,
+        // from the public stream (zero where the words were loaded)
+        uint64_t gen[8];
+        if (SEEDED) {
+            const HcLayer P = layer(u.L);
+            const int col = u.jt * 64 + ld_col, c0 = u.ks * 64 + ld_sc * 16 + ld_h * 8;
+            const bool on = c0 < P.Cin && col < P.n;
+            const uint64_t q0 = P.idx0 + (uint64_t)((u.b * P.F + u.f) * P.Cin + c0);
+            uint64_t z = P.seed_a + (q0 * (uint64_t)P.n + (uint64_t)col + 1) * kGamma;
+            const uint64_t step = (uint64_t)P.n * kGamma;  // next channel, same word
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const uint64_t a = splitmix_mix(z);
+                gen[i] = on ? a : 0ull;
+                z += step;
+            }
+        }
+        {
+            uint32_t lo[8], hi[8];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint64_t v0 = (uint64_t)buf.w[q].y << 32 | buf.w[q].x;
+                uint64_t v1 = (uint64_t)buf.w[q].w << 32 | buf.w[q].z;
+                if (SEEDED) {  // a thread's words are either loaded or generated; the other part is zero
+                    v0 += gen[2 * q];
+                    v1 += gen[2 * q + 1];
+                }
+                v0 += 0x8080808080808080ull;
+                v1 += 0x8080808080808080ull;
+                lo[2 * q] = (uint32_t)v0;
+                hi[2 * q] = (uint32_t)(v0 >> 32);
+                lo[2 * q + 1] = (uint32_t)v1;
+                hi[2 * q + 1] = (uint32_t)(v1 >> 32);
+            }
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                transpose4(lo[4 * d], lo[4 * d + 1], lo[4 * d + 2], lo[4 * d + 3], pl[0][d], pl[1][d], pl[2][d],
+                           pl[3][d]);
+                transpose4(hi[4 * d], hi[4 * d + 1], hi[4 * d + 2], hi[4 * d + 3], pl[4][d], pl[5][d], pl[6][d],
+                           pl[7][d]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            pl[k][0] ^= 0x80808080u;
+            pl[k][1] ^= 0x80808080u;
+        }
+    };
+    // a unit's digit planes, its weight fragments (when loaded for it) and its
+    // masks into LDS buffer lb
+    auto store_unit = [&](const uint32_t (&pl)[8][2], const HcBuf &buf, int lb) {
+        const int pslot = plane_slot(ld_col, ld_sc) * 16 + ld_h * 8;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            *reinterpret_cast<u32x2 *>(planes(lb) + k * kPlaneBytes + pslot) = u32x2{pl[k][0], pl[k][1]};
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            if (buf.afresh && tid + kHcThreads * j < kAItems)
+                reinterpret_cast<v4i *>(lds_a(lb))[tid + kHcThreads * j] = buf.a[j];
+        if (tid < 64) lds_r(lb)[tid] = buf.r;
+    };
+
     // MFMA phase of one unit; FRESH: the first product into each shift
-    // accumulator starts from zero (the unit is the tile's first K step)
-    auto contract = [&](auto fresh_tag, int lb, int sc_here) {
+    // accumulator starts from zero (the unit is the tile's first K step).
+    // Interleaved (paired, words loaded), mid() runs in the same
+    // straight-line code, so that its vector work (the next unit's
+    // conversion) issues while the matrix cores run. The folded form (more
+    // operand registers) and the seeded one (a generator whose long chains
+    // leave the MFMAs bunched) convert before contracting instead.
+    constexpr bool kInterleave = PAIRED && !SEEDED;
+    auto contract = [&](auto fresh_tag, int lb, int sc_here, auto &&mid) {
         constexpr bool FRESH = decltype(fresh_tag)::value;
         const v4i zero = {0, 0, 0, 0};
         if (PAIRED) {
@@ -431,6 +505,9 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
                     A[l][rb] = reinterpret_cast<const v4i *>(lds_a(lb))[(l * 4 + rg * 2 + rb) * 64 + lane];
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
+                // (between instructions that differ with FRESH, so that it
+                // is not moved out ahead of the caller's branch on it)
+                if (kInterleave && k == 4) mid();
                 const v4i B = *reinterpret_cast<const v4i *>(planes(lb) + b_base + k * b_step);
 #pragma unroll
                 for (int l = 0; l < 3; ++l) {
@@ -441,6 +518,14 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
                     for (int rb = 0; rb < 2; ++rb)
                         acc[k + l][rb] =
                             __builtin_amdgcn_mfma_i32_16x16x64_i8(A[l][rb], B, first ? zero : acc[k + l][rb], 0, 0, 0);
+                }
+            }
+            // schedule: each MFMA followed by two of mid()'s vector instructions
+            if (kInterleave) {
+#pragma unroll
+                for (int i = 0; i < 42; ++i) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 2, 0);
                 }
             }
         } else {
@@ -476,9 +561,11 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
         store_lane_words<WIDE_STORE, false, 0>(res, rs, b_col, cur.ot * 64 + 32 * rg, g, P.Cout, valid);
     };
 
-    // two units in flight from the start; the entry issues the same load and
-    // store sequence as every iteration (stores fully out of bounds) so the
-    // waits at the loop head see one static count on both incoming paths
+    // Two units' words in flight from the start; the entry issues the same
+    // load and store sequence as every iteration (stores fully out of bounds)
+    // so the waits see one static count on every incoming path. The first
+    // unit is converted here; from then on each unit's conversion runs during
+    // the previous unit's MFMAs.
     HcBuf buf0, buf1;
     buf0.akey = buf1.akey = 0;  // no fragments in either LDS buffer yet
     const uint64_t none[2][4] = {};
@@ -489,81 +576,47 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
     issue(nx, buf1);
     store_out(none, false);
     int64_t issued = n_units > 1 ? 2 : 1;
+    cv = cur;
+    {
+        uint32_t pl[8][2];
+        convert(cv, buf0, pl);
+        store_unit(pl, buf0, 0);
+    }
+    advance(cv);
+    __syncthreads();
 
     uint64_t res[2][4] = {};  // the last finished tile's words (kept across units)
-    auto body = [&](HcBuf &buf, int lb) {
+    // one unit: its operands are in LDS buffer lb, its words were in bcur
+    // (free again); the next unit's words are in bnxt and go to buffer lb ^ 1
+    auto body = [&](HcBuf &bcur, HcBuf &bnxt, int lb) {
         const HcLayer P = layer(cur.L);
         const bool last_ks = cur.ks == P.n_ks - 1;
 
-        // seeded input: this thread's words j = col < n of its 8 channels,
-        // from the public stream (zero where the words were loaded)
-        uint64_t gen[8];
-        if (SEEDED) {
-            const int col = cur.jt * 64 + ld_col, c0 = cur.ks * 64 + ld_sc * 16 + ld_h * 8;
-            const bool on = c0 < P.Cin && col < P.n;
-            const uint64_t q0 = P.idx0 + (uint64_t)((cur.b * P.F + cur.f) * P.Cin + c0);
-            uint64_t z = P.seed_a + (q0 * (uint64_t)P.n + (uint64_t)col + 1) * kGamma;
-            const uint64_t step = (uint64_t)P.n * kGamma;  // next channel, same word
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const uint64_t a = splitmix_mix(z);
-                gen[i] = on ? a : 0ull;
-                z += step;
-            }
-        }
-        // digit planes of this unit's 8 words: 8 bytes of each plane
-        uint32_t pl[8][2];
-        {
-            uint32_t lo[8], hi[8];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                uint64_t v0 = (uint64_t)buf.w[q].y << 32 | buf.w[q].x;
-                uint64_t v1 = (uint64_t)buf.w[q].w << 32 | buf.w[q].z;
-                if (SEEDED) {  // a thread's words are either loaded or generated; the other part is zero
-                    v0 += gen[2 * q];
-                    v1 += gen[2 * q + 1];
-                }
-                v0 += 0x8080808080808080ull;
-                v1 += 0x8080808080808080ull;
-                lo[2 * q] = (uint32_t)v0;
-                hi[2 * q] = (uint32_t)(v0 >> 32);
-                lo[2 * q + 1] = (uint32_t)v1;
-                hi[2 * q + 1] = (uint32_t)(v1 >> 32);
-            }
-#pragma unroll
-            for (int d = 0; d < 2; ++d) {
-                transpose4(lo[4 * d], lo[4 * d + 1], lo[4 * d + 2], lo[4 * d + 3], pl[0][d], pl[1][d], pl[2][d],
-                           pl[3][d]);
-                transpose4(hi[4 * d], hi[4 * d + 1], hi[4 * d + 2], hi[4 * d + 3], pl[4][d], pl[5][d], pl[6][d],
-                           pl[7][d]);
-            }
-        }
-        const int pslot = plane_slot(ld_col, ld_sc) * 16 + ld_h * 8;
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            *reinterpret_cast<u32x2 *>(planes(lb) + k * kPlaneBytes + pslot) =
-                u32x2{pl[k][0] ^ 0x80808080u, pl[k][1] ^ 0x80808080u};
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-            if (buf.afresh && tid + kHcThreads * j < kAItems)
-                reinterpret_cast<v4i *>(lds_a(lb))[tid + kHcThreads * j] = buf.a[j];
-        if (tid < 64) lds_r(lb)[tid] = buf.r;
-        __syncthreads();
-
-        // the unit two ahead reuses this buffer (past the end: reissue the
-        // last one, keeping the load count static)
+        // the unit two ahead reuses bcur (past the end: reissue the last
+        // one, keeping the load count static)
         if (issued < n_units) {
             advance(nx);
             ++issued;
         }
-        issue(nx, buf);
+        issue(nx, bcur);
 
+        // this unit's MFMAs and the next unit's conversion (past the last
+        // unit it converts words that are never read). Interleaved, the
+        // conversion runs among the MFMAs and its LDS writes follow the
+        // MFMAs' LDS reads; otherwise it comes first.
+        uint32_t pl[8][2];
+        auto conv = [&] { convert(cv, bnxt, pl); };
+        if (!kInterleave) {
+            conv();
+            store_unit(pl, bnxt, lb ^ 1);
+        }
         // 16-channel groups holding channels in this K step (folded scheme)
         const int sc_here = last_ks ? (P.Cin - 64 * (P.n_ks - 1) + 15) / 16 : 4;
         if (cur.ks == 0)
-            contract(std::true_type{}, lb, sc_here);
+            contract(std::true_type{}, lb, sc_here, conv);
         else
-            contract(std::false_type{}, lb, sc_here);
+            contract(std::false_type{}, lb, sc_here, conv);
+        if (kInterleave) store_unit(pl, bnxt, lb ^ 1);
 
         // epilogue: recombine the shift accumulators (in every unit, so the
         // store count stays static; only the tile's last K step stores)
@@ -593,13 +646,16 @@ __global__ __launch_bounds__(kHcThreads) void homconv_mfma_kernel(HcLayer one, c
         }
         store_out(res, last_ks);
         advance(cur);
+        advance(cv);
+        // buffer lb ^ 1 is complete and every wave is done with buffer lb
+        __syncthreads();
     };
 
     for (int64_t it = 0; it < n_units / 2; ++it) {
-        body(buf0, 0);
-        body(buf1, 1);
+        body(buf0, buf1, 0);
+        body(buf1, buf0, 1);
     }
-    if (n_units & 1) body(buf0, 0);
+    if (n_units & 1) body(buf0, buf1, 0);
 }
 
 // Deep-layer HomConv (paired fragments, Cin <= 64 kDeepMaxKs, several
