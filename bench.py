@@ -100,9 +100,10 @@ def homconv_bytes(S, pack_bytes: int) -> int:
     return 8 * (S.n + 1) * S.F * S.B * (S.Cin + S.Cout) + pack_bytes + 4 * S.B * S.Cout * S.F
 
 
-def traffic_entry(path: str = TRAFFIC_FILE):
+def traffic_entry(path: str = TRAFFIC_FILE, workload: str = None, kernel: str = None):
     """Measured HBM bytes per launch (or per plan stage) from rocprofv3
-    counters, if they were taken on the current HomConv source; else None."""
+    counters, if they were taken on the current HomConv source (and, when
+    given, on this workload and kernel); else None."""
     from paper_2003_05328_amd.profile_summary import code_digest
 
     try:
@@ -110,9 +111,31 @@ def traffic_entry(path: str = TRAFFIC_FILE):
             rec = json.load(fh)
         if rec.get("code_sha256") != code_digest(HOMCONV_SRC):
             return None
+        if workload is not None and rec.get("workload") != workload:
+            return None
+        if kernel is not None and not rec.get("kernel", "").startswith(kernel):
+            return None
         return int(rec["hbm_bytes_per_launch"])
     except (OSError, ValueError, KeyError):
         return None
+
+
+def homconv_kernel_name(S, seeded: bool = False) -> str:
+    """The kernel ensei_homconv launches for one layer, by the library's
+    launch rule (homconv.hip): the deep kernel for Cin >= 48 when its LDS
+    layout fits (Cin <= 256, two or more row tiles and, for plain input, at
+    least four (row tile, K step) pairs per block); else the narrow kernel
+    for Cin <= 8; else the streaming kernel."""
+    n_ks, n_ot = -(-S.Cin // 64), -(-S.Cout // 64)
+    if S.Cin >= 48 and n_ks <= 4 and n_ot >= 2 and (seeded or n_ot * n_ks >= 4):
+        n_dma = 0 if seeded else -(-(32 * S.Cin * 8) // 1024)
+        n_mask = 2 * ((n_ot + 1) // 2) * 64
+        lds = n_ks * 8 * 2048 + n_dma * 1024 + 2 * n_mask * 4 + (64 if S.Cin % 8 else 0)
+        if lds <= 160 * 1024:
+            return "homconv_deep_kernel"
+    if S.Cin <= 8:
+        return "homconv_narrow_kernel"
+    return "homconv_mfma_kernel"
 
 
 MFMA_I8_PEAK_MACS = 2.5e15  # dense i8 multiply-accumulates per second (5.0 POP/s)
@@ -1063,7 +1086,7 @@ def stack_main(ctx, args):
     }
 
 
-def layer_main(ctx, S, inp, steps: int, warmup: int, homconv: str = "mfma"):
+def layer_main(ctx, S, inp, steps: int, warmup: int, homconv: str = "mfma", workload: str = None):
     """One layer's whole step through the single calls (filters prepared in
     every step), each kernel timed with HIP events on its stream."""
     import numpy as np
@@ -1135,6 +1158,7 @@ def layer_main(ctx, S, inp, steps: int, warmup: int, homconv: str = "mfma"):
     macs = S.B * S.Cout * S.Cin * S.F
     hc_bytes = homconv_bytes(S, pack_bytes)
     achieved = hc_bytes / (hc_ms * 1e-3) / 1e9
+    kname = homconv_kernel_name(S) if homconv == "mfma" else "homconv_valu_kernel"
     return {
         "value": macs / (ms_per_step * 1e-3),
         "unit": "ct-MAC/s",
@@ -1142,10 +1166,10 @@ def layer_main(ctx, S, inp, steps: int, warmup: int, homconv: str = "mfma"):
         "config": {"workload": None, "grid": f"{S.H}x{S.W}", "cin": S.Cin, "cout": S.Cout, "kernel": f"{S.kh}x{S.kw}",
                    "lwe_n": S.n, "batch": S.B, "p": P, "q": "2^64", "homconv": homconv},
         "roofline": {
-            "kernel": "homconv_mfma_kernel" if homconv == "mfma" else "homconv_valu_kernel",
+            "kernel": kname,
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": traffic_entry() if homconv == "mfma" else None,
+            "traffic": traffic_entry(workload=workload, kernel=kname) if homconv == "mfma" else None,
             "algorithmic_bytes": hc_bytes, "avg_us": hc_ms * 1e3,
         },
         "kernels_us": {k: v * 1e3 for k, v in per_kernel_ms.items()},
@@ -1225,7 +1249,7 @@ def main():
         # one layer's step through the single calls
         S = configs.WORKLOADS[args.workload]
         inp = synth.generate(S, configs.P, args.seed)
-        res = layer_main(ctx, S, inp, args.steps, args.warmup, args.homconv)
+        res = layer_main(ctx, S, inp, args.steps, args.warmup, args.homconv, workload=args.workload)
         res["config"]["workload"] = args.workload
         result = {"metric": "HomConv ciphertext-MACs/s (whole secure-conv step of one layer: NTT2D, weight prep, "
                             "Enc, HomConv, Dec, INTT2D, server share)",
@@ -1245,7 +1269,7 @@ def main():
     if not args.no_extras:
         S = configs.WORKLOADS[LAYER_WORKLOAD]
         inp = synth.generate(S, configs.P, args.seed)
-        layer = layer_main(ctx, S, inp, max(args.steps, 20), max(args.warmup, 10))
+        layer = layer_main(ctx, S, inp, max(args.steps, 20), max(args.warmup, 10), workload=LAYER_WORKLOAD)
         layer["config"]["workload"] = LAYER_WORKLOAD
         result["layer_conv32x32"] = layer
         result["verified"] = result["verified"] and layer["verified"]

@@ -202,6 +202,14 @@ def main():
                       "| dispatch | kernel | fetched | written |", "|---|---|---|---|"]
             for i, ((k, fv), (_, wv)) in enumerate(zip(flast, wlast)):
                 lines.append(f"| {i + 1} | {k} | {fv * 1024 * ff / 1e6:.1f} | {wv * 1024 * fw / 1e6:.1f} |")
+        else:
+            # the two counter runs' plans chose different launches (the
+            # tuner times its candidates in each run): each run's own list
+            for title, last, factor in (("fetched, FETCH_SIZE run", flast, ff), ("written, WRITE_SIZE run", wlast, fw)):
+                lines += ["", f"The last step's dispatches, {title} (calibrated MB):", "",
+                          "| dispatch | kernel | MB |", "|---|---|---|"]
+                for i, (k, v) in enumerate(last):
+                    lines.append(f"| {i + 1} | {k} | {v * 1024 * factor / 1e6:.1f} |")
         record = {"kernel": f"{args.stage_prefix}* (one step)", "workload": args.workload,
                   "hbm_bytes_per_launch": int(round(hbm)), "fetch_kib": fk, "write_kib": wk, "fetch_factor": ff,
                   "write_factor": fw, "code_sha256": code_digest(HOMCONV_SRC)}
