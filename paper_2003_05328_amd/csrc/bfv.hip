@@ -78,38 +78,69 @@ __device__ __forceinline__ int brev(int x, int logn) { return (int)(__brev((uint
 // In-place transform of a[0..n) in LDS mod md.m; modulus index mi selects
 // the twiddles. Forward: natural in, out[i] = u(psi^(2 brev(i) + 1)).
 // Inverse: in[i] = slot brev(i), natural coefficients out, times n^-1.
+// Forward stage s (0 <= s < logn) pairs j and j + t, t = n >> (s + 1), with
+// twiddle 2^s + j / 2t; inverse stage s pairs j and j + t, t = 2^s, with
+// twiddle (n >> (s + 1)) + j / 2t. The stages are taken up to three at a
+// time: a thread loads the 2^R elements j0 + k stride of one unit (one
+// radix-2^R sub-transform) into registers, applies the R stages there and
+// writes them back, so a transform needs ceil(logn / 3) barriers, not logn.
+// na arrays a + v kMaxN (v < na) are transformed together, sharing them.
 template <bool INV>
-__device__ void ntt_lds(uint32_t *a, const BfvK &K, int mi) {
-    const int n = K.n, half = n >> 1, tid = threadIdx.x;
+__device__ void ntt_lds(uint32_t *a, const BfvK &K, int mi, int na = 1) {
+    const int n = K.n, logn = K.logn, tid = threadIdx.x;
     const uint32_t m = K.md[mi].m;
     const uint32_t *tw = K.tw + (size_t)mi * 4 * n + (INV ? 2 * n : 0);
     const uint32_t *tws = tw + n;
-    if (!INV) {
-        for (int mm = 1, t = half; mm < n; mm <<= 1, t >>= 1) {
-            for (int b = tid; b < half; b += kNT) {
-                const int i = b / t, j = 2 * i * t + (b - i * t);
-                const uint32_t S = __ldg(tw + mm + i), Ssh = __ldg(tws + mm + i);
-                const uint32_t U = a[j], V = mulsh(a[j + t], S, Ssh, m);
-                a[j] = addm(U, V, m);
-                a[j + t] = subm(U, V, m);
+    // stages s0 .. s0 + R - 1; SCALE: multiply by n^-1 afterwards
+    auto group = [&](auto r_tag, int s0, bool scale) {
+        constexpr int R = decltype(r_tag)::value, E = 1 << R;
+        // log2 of the unit's stride: the group's smallest t
+        const int ls = INV ? s0 : logn - s0 - R;
+        for (int w = tid; w < (na << (logn - R)); w += kNT) {
+            uint32_t *const av = a + (w >> (logn - R)) * kMaxN;  // array w / (n >> R), unit u of it
+            const int u = w & ((n >> R) - 1);
+            const int j0 = ((u >> ls) << (ls + R)) + (u & ((1 << ls) - 1));
+            uint32_t x[E];
+#pragma unroll
+            for (int k = 0; k < E; ++k) x[k] = av[j0 + (k << ls)];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int st = s0 + r;
+                const int lt = INV ? st : logn - 1 - st;     // log2 t
+                const int d = INV ? 1 << r : 1 << (R - 1 - r);  // t / stride
+                const int base = INV ? n >> (st + 1) : 1 << st;
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    if (k & d) continue;
+                    const int i = (j0 + (k << ls)) >> (lt + 1);
+                    const uint32_t S = __ldg(tw + base + i), Ssh = __ldg(tws + base + i);
+                    const uint32_t U = x[k];
+                    if (!INV) {
+                        const uint32_t V = mulsh(x[k + d], S, Ssh, m);
+                        x[k] = addm(U, V, m);
+                        x[k + d] = subm(U, V, m);
+                    } else {
+                        const uint32_t V = x[k + d];
+                        x[k] = addm(U, V, m);
+                        x[k + d] = mulsh(U + m - V, S, Ssh, m);
+                    }
+                }
             }
-            __syncthreads();
-        }
-    } else {
-        for (int mm = n, t = 1; mm > 1; mm >>= 1, t <<= 1) {
-            const int h = mm >> 1;
-            for (int b = tid; b < half; b += kNT) {
-                const int i = b / t, j = 2 * i * t + (b - i * t);
-                const uint32_t S = __ldg(tw + h + i), Ssh = __ldg(tws + h + i);
-                const uint32_t U = a[j], V = a[j + t];
-                a[j] = addm(U, V, m);
-                a[j + t] = mulsh(U + m - V, S, Ssh, m);
+            if (scale) {
+#pragma unroll
+                for (int k = 0; k < E; ++k) x[k] = mulsh(x[k], K.md[mi].ninv, K.md[mi].ninv_sh, m);
             }
-            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < E; ++k) av[j0 + (k << ls)] = x[k];
         }
-        for (int j = tid; j < n; j += kNT) a[j] = mulsh(a[j], K.md[mi].ninv, K.md[mi].ninv_sh, m);
         __syncthreads();
-    }
+    };
+    int s = 0;
+    for (; s + 3 <= logn; s += 3) group(std::integral_constant<int, 3>{}, s, INV && s + 3 == logn);
+    if (logn - s == 2)
+        group(std::integral_constant<int, 2>{}, s, INV);
+    else if (logn - s == 1)
+        group(std::integral_constant<int, 1>{}, s, INV);
 }
 
 // Slot s of packed vector (b, g, k) of a [B][C][F] spectrum array: channel
@@ -416,9 +447,7 @@ __global__ __launch_bounds__(kNT) void bfv_rerandomize_kernel(BfvK K, uint32_t *
                 }
             }
         __syncthreads();
-        ntt_lds<false>(a[0], K, 1 + l);
-        ntt_lds<false>(a[1], K, 1 + l);
-        ntt_lds<false>(a[2], K, 1 + l);
+        ntt_lds<false>(a[0], K, 1 + l, 3);  // the three draws together
         uint32_t *wa = ct + ((ci * 2 + l) * 2) * (int64_t)n, *wb = wa + n;
         const uint32_t *pa = pk + (size_t)l * 2 * n, *pb = pa + n;
         for (int s = tid; s < n; s += kNT) {
