@@ -84,21 +84,24 @@ __device__ __forceinline__ int brev(int x, int logn) { return (int)(__brev((uint
 // time: a thread loads the 2^R elements j0 + k stride of one unit (one
 // radix-2^R sub-transform) into registers, applies the R stages there and
 // writes them back, so a transform needs ceil(logn / 3) barriers, not logn.
-// na arrays a + v kMaxN (v < na) are transformed together, sharing them.
+// na arrays a + v kMaxN (v < na) are transformed together, sharing them;
+// array v under modulus index mi + v mstep (the same modulus, or one limb
+// per array).
 template <bool INV>
-__device__ void ntt_lds(uint32_t *a, const BfvK &K, int mi, int na = 1) {
+__device__ void ntt_lds(uint32_t *a, const BfvK &K, int mi, int na = 1, int mstep = 0) {
     const int n = K.n, logn = K.logn, tid = threadIdx.x;
-    const uint32_t m = K.md[mi].m;
-    const uint32_t *tw = K.tw + (size_t)mi * 4 * n + (INV ? 2 * n : 0);
-    const uint32_t *tws = tw + n;
     // stages s0 .. s0 + R - 1; SCALE: multiply by n^-1 afterwards
     auto group = [&](auto r_tag, int s0, bool scale) {
         constexpr int R = decltype(r_tag)::value, E = 1 << R;
         // log2 of the unit's stride: the group's smallest t
         const int ls = INV ? s0 : logn - s0 - R;
         for (int w = tid; w < (na << (logn - R)); w += kNT) {
-            uint32_t *const av = a + (w >> (logn - R)) * kMaxN;  // array w / (n >> R), unit u of it
+            const int v = w >> (logn - R), mv = mi + v * mstep;  // array w / (n >> R), unit u of it
+            uint32_t *const av = a + v * kMaxN;
             const int u = w & ((n >> R) - 1);
+            const uint32_t m = K.md[mv].m;
+            const uint32_t *tw = K.tw + (size_t)mv * 4 * n + (INV ? 2 * n : 0);
+            const uint32_t *tws = tw + n;
             const int j0 = ((u >> ls) << (ls + R)) + (u & ((1 << ls) - 1));
             uint32_t x[E];
 #pragma unroll
@@ -128,7 +131,7 @@ __device__ void ntt_lds(uint32_t *a, const BfvK &K, int mi, int na = 1) {
             }
             if (scale) {
 #pragma unroll
-                for (int k = 0; k < E; ++k) x[k] = mulsh(x[k], K.md[mi].ninv, K.md[mi].ninv_sh, m);
+                for (int k = 0; k < E; ++k) x[k] = mulsh(x[k], K.md[mv].ninv, K.md[mv].ninv_sh, m);
             }
 #pragma unroll
             for (int k = 0; k < E; ++k) av[j0 + (k << ls)] = x[k];
@@ -159,38 +162,41 @@ __global__ __launch_bounds__(kNT) void bfv_encrypt_kernel(BfvK K, const uint32_t
                                                           const uint32_t *__restrict__ s_hat,
                                                           const int32_t *__restrict__ e, uint64_t seed_a,
                                                           uint64_t ct_index0, uint32_t *__restrict__ ct) {
-    __shared__ uint32_t a[kMaxN];
+    __shared__ uint32_t a[2][kMaxN];  // one array per limb
     const int n = K.n, tid = threadIdx.x;
     const int64_t ci = blockIdx.x;
     const int64_t b = ci / ((int64_t)G * KC);
     const int rest = (int)(ci - b * G * KC), g = rest / KC, k = rest - g * KC;
-    for (int s = tid; s < n; s += kNT) a[brev(s, K.logn)] = packed_slot(x, b, C, F, P, Fp, g, k, s);
+    for (int s = tid; s < n; s += kNT) a[0][brev(s, K.logn)] = packed_slot(x, b, C, F, P, Fp, g, k, s);
     __syncthreads();
-    ntt_lds<true>(a, K, 0);  // u = INTT_t(slots), natural order
+    ntt_lds<true>(a[0], K, 0);  // u = INTT_t(slots), natural order
     uint32_t u[kPer];
     int32_t ev[kPer];
 #pragma unroll
     for (int r = 0; r < kPer; ++r) {
         const int s = tid + r * kNT;
         if (s < n) {
-            u[r] = a[s];
+            u[r] = a[0][s];
             ev[r] = e[ci * n + s];
         }
     }
+    __syncthreads();
     for (int l = 0; l < 2; ++l) {
         const uint32_t m = K.md[1 + l].m;
-        __syncthreads();
 #pragma unroll
         for (int r = 0; r < kPer; ++r) {
             const int s = tid + r * kNT;
             if (s < n) {
                 const uint32_t em = ev[r] < 0 ? m - mulsh((uint32_t)(-ev[r]), 1u, K.one_sh[1 + l], m)
                                               : mulsh((uint32_t)ev[r], 1u, K.one_sh[1 + l], m);
-                a[s] = red1(mulsh(u[r], K.delta[l], K.delta_sh[l], m) + red1(em, m), m);
+                a[l][s] = red1(mulsh(u[r], K.delta[l], K.delta_sh[l], m) + red1(em, m), m);
             }
         }
-        __syncthreads();
-        ntt_lds<false>(a, K, 1 + l);
+    }
+    __syncthreads();
+    ntt_lds<false>(a[0], K, 1, 2, 1);  // both limbs
+    for (int l = 0; l < 2; ++l) {
+        const uint32_t m = K.md[1 + l].m;
         uint32_t *wa = ct + ((ci * 2 + l) * 2) * (int64_t)n, *wb = wa + n;
         const uint32_t *sh = s_hat + (size_t)l * 2 * n;
         for (int s = tid; s < n; s += kNT) {
@@ -198,7 +204,7 @@ __global__ __launch_bounds__(kNT) void bfv_encrypt_kernel(BfvK K, const uint32_t
                                                       (uint64_t)s + 1);
             const uint32_t av = mod64(z, m, K.r32[l], K.r32_sh[l], K.one_sh[1 + l]);
             wa[s] = av;
-            wb[s] = addm(mulsh(av, sh[s], sh[n + s], m), a[brev(s, K.logn)], m);
+            wb[s] = addm(mulsh(av, sh[s], sh[n + s], m), a[l][brev(s, K.logn)], m);
         }
     }
 }
@@ -211,7 +217,7 @@ __global__ __launch_bounds__(kNT) void bfv_encrypt_kernel(BfvK K, const uint32_t
 template <int MODE>
 __global__ __launch_bounds__(kNT) void bfv_encode_kernel(BfvK K, const void *__restrict__ src, int C, int64_t F, int P,
                                                          int Fp, int G, int KC, uint32_t *__restrict__ out) {
-    __shared__ uint32_t a[kMaxN];
+    __shared__ uint32_t a[2][kMaxN];  // one array per limb
     const int n = K.n, tid = threadIdx.x;
     const int64_t vi = blockIdx.x;
     uint32_t u[kPer];
@@ -228,21 +234,21 @@ __global__ __launch_bounds__(kNT) void bfv_encode_kernel(BfvK K, const void *__r
         if (MODE == 0) {
             const int64_t o = vi / ((int64_t)G * KC);
             const int rest = (int)(vi - o * G * KC), g = rest / KC, k = rest - g * KC;
-            for (int s = tid; s < n; s += kNT) a[brev(s, K.logn)] = packed_slot(x, o, C, F, P, Fp, g, k, s);
+            for (int s = tid; s < n; s += kNT) a[0][brev(s, K.logn)] = packed_slot(x, o, C, F, P, Fp, g, k, s);
         } else {
-            for (int s = tid; s < n; s += kNT) a[brev(s, K.logn)] = x[vi * n + s];
+            for (int s = tid; s < n; s += kNT) a[0][brev(s, K.logn)] = x[vi * n + s];
         }
         __syncthreads();
-        ntt_lds<true>(a, K, 0);
+        ntt_lds<true>(a[0], K, 0);
 #pragma unroll
         for (int r = 0; r < kPer; ++r) {
             const int s = tid + r * kNT;
-            if (s < n) u[r] = a[s];
+            if (s < n) u[r] = a[0][s];
         }
     }
+    __syncthreads();
     for (int l = 0; l < 2; ++l) {
         const uint32_t m = K.md[1 + l].m;
-        __syncthreads();
 #pragma unroll
         for (int r = 0; r < kPer; ++r) {
             const int s = tid + r * kNT;
@@ -254,17 +260,20 @@ __global__ __launch_bounds__(kNT) void bfv_encode_kernel(BfvK K, const void *__r
                 v = mulsh(u[r], K.delta[l], K.delta_sh[l], m);
             else
                 v = sgn[r] < 0 ? m - 1 : (uint32_t)sgn[r];
-            a[s] = v;
+            a[l][s] = v;
         }
-        __syncthreads();
-        ntt_lds<false>(a, K, 1 + l);
+    }
+    __syncthreads();
+    ntt_lds<false>(a[0], K, 1, 2, 1);  // both limbs
+    for (int l = 0; l < 2; ++l) {
+        const uint32_t m = K.md[1 + l].m;
         if (MODE == 1) {
             uint32_t *o = out + (vi * 2 + l) * (int64_t)n;
-            for (int s = tid; s < n; s += kNT) o[s] = a[brev(s, K.logn)];
+            for (int s = tid; s < n; s += kNT) o[s] = a[l][brev(s, K.logn)];
         } else {
             uint32_t *o = out + (vi * 2 + l) * 2 * (int64_t)n;
             for (int s = tid; s < n; s += kNT) {
-                const uint32_t w = a[brev(s, K.logn)];
+                const uint32_t w = a[l][brev(s, K.logn)];
                 o[s] = w;
                 o[n + s] = (uint32_t)(((uint64_t)w << 32) / m);
             }
