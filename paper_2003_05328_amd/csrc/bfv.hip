@@ -102,20 +102,21 @@ __device__ void ntt_lds(uint32_t *a, const BfvK &K, int mi, int na = 1, int mste
             const uint32_t m = K.md[mv].m;
             const uint32_t *tw = K.tw + (size_t)mv * 4 * n + (INV ? 2 * n : 0);
             const uint32_t *tws = tw + n;
-            const int j0 = ((u >> ls) << (ls + R)) + (u & ((1 << ls) - 1));
+            const int blk = u >> ls, j0 = (blk << (ls + R)) + (u & ((1 << ls) - 1));
             uint32_t x[E];
 #pragma unroll
             for (int k = 0; k < E; ++k) x[k] = av[j0 + (k << ls)];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int st = s0 + r;
-                const int lt = INV ? st : logn - 1 - st;     // log2 t
                 const int d = INV ? 1 << r : 1 << (R - 1 - r);  // t / stride
                 const int base = INV ? n >> (st + 1) : 1 << st;
 #pragma unroll
                 for (int k = 0; k < E; ++k) {
                     if (k & d) continue;
-                    const int i = (j0 + (k << ls)) >> (lt + 1);
+                    // (j0 + k stride) / 2t: the butterflies of a unit share
+                    // one twiddle in the group's first stage, 2^R / 2 in its last
+                    const int i = INV ? (blk << (R - 1 - r)) + (k >> (r + 1)) : (blk << r) + (k >> (R - r));
                     const uint32_t S = __ldg(tw + base + i), Ssh = __ldg(tws + base + i);
                     const uint32_t U = x[k];
                     if (!INV) {
