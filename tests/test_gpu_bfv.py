@@ -1,6 +1,6 @@
 """GPU parity of the packed (BFV / RLWE) instantiation against its oracle
 (oracle/bfv.py): every call bit for bit under Table 2's three parameter sets
-(n = 2048) and a toy set (n = 64), packings with several channels per
+(n = 2048) and toy sets (n = 64, 128, 1024, 4096), packings with several channels per
 vector (and a partial last one), one channel per vector and channels
 spanning two vectors; the whole packed secure convolution, whose shares add
 up to the cyclic convolution mod t; and argument errors."""
@@ -18,6 +18,12 @@ pytestmark = pytest.mark.gpu
 
 SETS = dict(obfv.table2_params())
 SETS["toy"] = obfv.Params("toy", 257, 1073692673, 561770497, 64)
+# ring degrees whose transforms end in a one-stage pass (n = 128, 1024: the
+# stages go three at a time) and that give a thread two units per pass
+# (n = 4096); primes below 2^30, each 1 mod 2n
+SETS["toy128"] = obfv.Params("toy128", 257, 1073692673, 561770497, 128)
+SETS["toy1024"] = obfv.Params("toy1024", 12289, 1073692673, 561770497, 1024)
+SETS["toy4096"] = obfv.Params("toy4096", 40961, 1073692673, 536813569, 4096)
 
 
 @pytest.fixture(scope="module")
