@@ -284,8 +284,14 @@ __global__ __launch_bounds__(kNT) void bfv_encode_kernel(BfvK K, const void *__r
 
 // SIMDScMult, the sum over input vectors and the masks. One thread per slot
 // s of one (chunk k, limb l), kOB outputs x kBB images of both words in
-// registers; the filters and inputs of a g are read once per thread.
+// registers; the filters and inputs of a g are read once per thread. From
+// three input vectors on, the products w x < 2^60 are summed exactly in 64
+// bits (one multiply-add each), 16 at a time, and reduced mod m once per 16
+// input vectors; with one or two, each product is reduced by Shoup's method
+// (the 64-bit reduction costs more than two of those).
 constexpr int kOB = 4, kBB = 4;
+constexpr int kLazyTerms = 16;  // 16 (2^30 - 1)^2 < 2^64
+constexpr int kLazyMinG = 3;
 
 __global__ __launch_bounds__(kNT) void bfv_homconv_kernel(BfvK K, const uint32_t *__restrict__ ct_in,
                                                           const uint32_t *__restrict__ w_enc,
@@ -305,12 +311,12 @@ __global__ __launch_bounds__(kNT) void bfv_homconv_kernel(BfvK K, const uint32_t
     const int64_t b0 = (t / nob) * kBB;
     const uint32_t m = K.md[1 + l].m;
     if (s >= n) return;
-    uint32_t acc[kOB][kBB][2];
+    uint32_t acc[kOB][kBB][2];  // reduced sums
 #pragma unroll
     for (int i = 0; i < kOB; ++i)
 #pragma unroll
         for (int j = 0; j < kBB; ++j) acc[i][j][0] = acc[i][j][1] = 0;
-    for (int g = 0; g < G; ++g) {
+    for (int g = 0; G < kLazyMinG && g < G; ++g) {
         uint32_t w[kOB], wsh[kOB], x[kBB][2];
 #pragma unroll
         for (int i = 0; i < kOB; ++i) {
@@ -333,6 +339,43 @@ __global__ __launch_bounds__(kNT) void bfv_homconv_kernel(BfvK K, const uint32_t
                 acc[i][j][0] = addm(acc[i][j][0], mulsh(x[j][0], w[i], wsh[i], m), m);
                 acc[i][j][1] = addm(acc[i][j][1], mulsh(x[j][1], w[i], wsh[i], m), m);
             }
+    }
+    for (int g0 = 0; G >= kLazyMinG && g0 < G; g0 += kLazyTerms) {
+        const int g1 = G - g0 < kLazyTerms ? G : g0 + kLazyTerms;
+        uint64_t sum[kOB][kBB][2];  // exact sums of at most kLazyTerms products
+#pragma unroll
+        for (int i = 0; i < kOB; ++i)
+#pragma unroll
+            for (int j = 0; j < kBB; ++j) sum[i][j][0] = sum[i][j][1] = 0;
+        for (int g = g0; g < g1; ++g) {
+            uint32_t w[kOB], x[kBB][2];
+#pragma unroll
+            for (int i = 0; i < kOB; ++i) {
+                const int o = o0 + i < Cout ? o0 + i : Cout - 1;
+                w[i] = w_enc[((((int64_t)o * G + g) * KC + k) * 2 + l) * 2 * (int64_t)n + s];
+            }
+#pragma unroll
+            for (int j = 0; j < kBB; ++j) {
+                const int64_t b = b0 + j < B ? b0 + j : B - 1;
+                const uint32_t *p = ct_in + ((((b * G + g) * KC + k) * 2 + l) * 2) * (int64_t)n;
+                x[j][0] = p[s];
+                x[j][1] = p[n + s];
+            }
+#pragma unroll
+            for (int i = 0; i < kOB; ++i)
+#pragma unroll
+                for (int j = 0; j < kBB; ++j) {
+                    sum[i][j][0] += (uint64_t)x[j][0] * w[i];
+                    sum[i][j][1] += (uint64_t)x[j][1] * w[i];
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < kOB; ++i)
+#pragma unroll
+            for (int j = 0; j < kBB; ++j)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    acc[i][j][h] = addm(acc[i][j][h], mod64(sum[i][j][h], m, K.r32[l], K.r32_sh[l], K.one_sh[1 + l]), m);
     }
 #pragma unroll
     for (int i = 0; i < kOB; ++i) {

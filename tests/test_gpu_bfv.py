@@ -96,7 +96,9 @@ def test_encode_filters_and_masks(orc, pr_ctx):
 
 def test_homconv(orc, pr_ctx):
     pr, c = pr_ctx
-    for k, (B, Cin, Cout, F) in enumerate([(2, 5, 6, pr.n // 4), (1, 3, 2, pr.n), (1, 2, 5, 2 * pr.n)]):
+    # G = 2 and 3 input vectors, and 20 (exact 64-bit sums of 16 products, then of 4)
+    for k, (B, Cin, Cout, F) in enumerate([(2, 5, 6, pr.n // 4), (1, 3, 2, pr.n), (1, 2, 5, 2 * pr.n),
+                                           (1, 20, 3, pr.n)]):
         g = np.random.default_rng(30 + k)
         P, K, G = geometry(Cin, F, pr.n)
         ct = np.stack([g.integers(0, m, size=(B * G * K, 2, pr.n)) for m in (pr.q0, pr.q1)], axis=1).astype(np.uint32)
