@@ -95,13 +95,15 @@ __global__ __launch_bounds__(256) void encrypt_kernel(const uint32_t *__restrict
     uint64_t acc_p = 0, acc_n = 0;
     if (L.ok) {
         int j = j0;
+        uint64_t *wj = w + (int64_t)j0 * C;  // word j (stepped: no per-word 64-bit multiply)
         for (; j + 4 <= j1; j += 4) {
             const uint32_t k4 = key4(key, j);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const uint64_t a = splitmix_mix(z);
                 z += kGamma;
-                if (STORE_A) w[(int64_t)(j + k) * C] = a;
+                if (STORE_A) *wj = a;
+                wj += C;
                 acc_p += a & key_mask(k4, k, 1);
                 acc_n += a & key_mask(k4, k, -1);
             }
@@ -109,7 +111,8 @@ __global__ __launch_bounds__(256) void encrypt_kernel(const uint32_t *__restrict
         for (; j < j1; ++j) {
             const uint64_t a = splitmix_mix(z);
             z += kGamma;
-            if (STORE_A) w[(int64_t)j * C] = a;
+            if (STORE_A) *wj = a;
+            wj += C;
             const uint32_t k1 = __builtin_amdgcn_readfirstlane((uint32_t)(uint8_t)key[j]);
             acc_p += a & key_mask(k1, 0, 1);
             acc_n += a & key_mask(k1, 0, -1);
