@@ -56,6 +56,12 @@ __device__ __forceinline__ uint32_t mulsh(uint32_t x, uint32_t w, uint32_t wsh, 
     return red1(x * w - qt * m, m);
 }
 
+// Shoup's product without its final correction: x w mod m + {0, m}, in
+// [0, 2m), for any 32-bit x
+__device__ __forceinline__ uint32_t mulsh_lazy(uint32_t x, uint32_t w, uint32_t wsh, uint32_t m) {
+    return x * w - __umulhi(x, wsh) * m;
+}
+
 __device__ __forceinline__ uint32_t addm(uint32_t a, uint32_t b, uint32_t m) { return red1(a + b, m); }
 __device__ __forceinline__ uint32_t subm(uint32_t a, uint32_t b, uint32_t m) { return red1(a + m - b, m); }
 
@@ -84,14 +90,18 @@ __device__ __forceinline__ int brev(int x, int logn) { return (int)(__brev((uint
 // time: a thread loads the 2^R elements j0 + k stride of one unit (one
 // radix-2^R sub-transform) into registers, applies the R stages there and
 // writes them back, so a transform needs ceil(logn / 3) barriers, not logn.
+// The butterflies are Harvey's lazy ones (m < 2^30, so 4m fits 32 bits):
+// forward values stay in [0, 4m), inverse ones in [0, 2m), and the last
+// pass reduces them to [0, m).
 // na arrays a + v kMaxN (v < na) are transformed together, sharing them;
 // array v under modulus index mi + v mstep (the same modulus, or one limb
 // per array).
 template <bool INV>
 __device__ void ntt_lds(uint32_t *a, const BfvK &K, int mi, int na = 1, int mstep = 0) {
     const int n = K.n, logn = K.logn, tid = threadIdx.x;
-    // stages s0 .. s0 + R - 1; SCALE: multiply by n^-1 afterwards
-    auto group = [&](auto r_tag, int s0, bool scale) {
+    // stages s0 .. s0 + R - 1; LAST: the transform's last pass (forward:
+    // reduce to [0, m); inverse: multiply by n^-1, which also reduces)
+    auto group = [&](auto r_tag, int s0, bool last) {
         constexpr int R = decltype(r_tag)::value, E = 1 << R;
         // log2 of the unit's stride: the group's smallest t
         const int ls = INV ? s0 : logn - s0 - R;
@@ -118,21 +128,24 @@ __device__ void ntt_lds(uint32_t *a, const BfvK &K, int mi, int na = 1, int mste
                     // one twiddle in the group's first stage, 2^R / 2 in its last
                     const int i = INV ? (blk << (R - 1 - r)) + (k >> (r + 1)) : (blk << r) + (k >> (R - r));
                     const uint32_t S = __ldg(tw + base + i), Ssh = __ldg(tws + base + i);
-                    const uint32_t U = x[k];
                     if (!INV) {
-                        const uint32_t V = mulsh(x[k + d], S, Ssh, m);
-                        x[k] = addm(U, V, m);
-                        x[k + d] = subm(U, V, m);
+                        // inputs in [0, 4m)
+                        const uint32_t U = red1(x[k], 2 * m);                // [0, 2m)
+                        const uint32_t V = mulsh_lazy(x[k + d], S, Ssh, m);  // [0, 2m)
+                        x[k] = U + V;                                        // [0, 4m)
+                        x[k + d] = U - V + 2 * m;                            // (0, 4m)
                     } else {
-                        const uint32_t V = x[k + d];
-                        x[k] = addm(U, V, m);
-                        x[k + d] = mulsh(U + m - V, S, Ssh, m);
+                        // inputs in [0, 2m)
+                        const uint32_t U = x[k], V = x[k + d];
+                        x[k] = red1(U + V, 2 * m);                           // [0, 2m)
+                        x[k + d] = mulsh_lazy(U - V + 2 * m, S, Ssh, m);     // [0, 2m)
                     }
                 }
             }
-            if (scale) {
+            if (last) {
 #pragma unroll
-                for (int k = 0; k < E; ++k) x[k] = mulsh(x[k], K.md[mv].ninv, K.md[mv].ninv_sh, m);
+                for (int k = 0; k < E; ++k)
+                    x[k] = INV ? mulsh(x[k], K.md[mv].ninv, K.md[mv].ninv_sh, m) : red1(red1(x[k], 2 * m), m);
             }
 #pragma unroll
             for (int k = 0; k < E; ++k) av[j0 + (k << ls)] = x[k];
@@ -140,11 +153,11 @@ __device__ void ntt_lds(uint32_t *a, const BfvK &K, int mi, int na = 1, int mste
         __syncthreads();
     };
     int s = 0;
-    for (; s + 3 <= logn; s += 3) group(std::integral_constant<int, 3>{}, s, INV && s + 3 == logn);
+    for (; s + 3 <= logn; s += 3) group(std::integral_constant<int, 3>{}, s, s + 3 == logn);
     if (logn - s == 2)
-        group(std::integral_constant<int, 2>{}, s, INV);
+        group(std::integral_constant<int, 2>{}, s, true);
     else if (logn - s == 1)
-        group(std::integral_constant<int, 1>{}, s, INV);
+        group(std::integral_constant<int, 1>{}, s, true);
 }
 
 // Slot s of packed vector (b, g, k) of a [B][C][F] spectrum array: channel
