@@ -34,6 +34,7 @@ struct BfvK {
     Mod md[kMods];
     uint32_t delta[2], delta_sh[2];   // Delta = round(q / t), mod q_l, and companion
     uint32_t r32[2], r32_sh[2];       // 2^32 mod q_l and companion (64-bit reduction)
+    uint32_t mont[2];                 // -q_l^-1 mod 2^32 (Montgomery reduction)
     uint32_t one_sh[3];               // floor(2^32 / m): reduces a 32-bit word mod m
     uint32_t q0inv, q0inv_sh;         // q0^-1 mod q1 and companion
     uint32_t t;
@@ -72,8 +73,18 @@ __device__ __forceinline__ uint32_t mod64(uint64_t x, uint32_t m, uint32_t r32, 
     return addm(h, l, m);
 }
 
+constexpr uint64_t kSplitGamma = 0x9e3779b97f4a7c15ULL;
+
+// SplitMix64's output for the state z = seed + k gamma (the generator's
+// finaliser; splitmix64(seed, k) below)
+__device__ __forceinline__ uint64_t splitmix_out(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
-    uint64_t z = seed + k * 0x9e3779b97f4a7c15ULL;
+    uint64_t z = seed + k * kSplitGamma;
     z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
     z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
     return z ^ (z >> 31);
@@ -475,9 +486,17 @@ __global__ __launch_bounds__(kNT) void bfv_decrypt_kernel(BfvK K, const uint32_t
 // from the generator by multiply-shift and are transformed per limb.
 constexpr uint32_t kE1Bound = 16;
 
-__device__ __forceinline__ int32_t draw(uint64_t seed, uint64_t k, uint32_t bound) {
-    const uint64_t z = splitmix64(seed, k);
-    return (int32_t)((int64_t)(((z >> 32) * (2 * (uint64_t)bound + 1)) >> 32) - (int64_t)bound);
+// draw number k in [-bound, bound] from the generator's state z = seed + k gamma
+__device__ __forceinline__ int32_t draw_at(uint64_t z, uint32_t bound) {
+    const uint64_t x = splitmix_out(z);
+    return (int32_t)((int64_t)(((x >> 32) * (2 * (uint64_t)bound + 1)) >> 32) - (int64_t)bound);
+}
+
+// x R^-1 mod m (R = 2^32) for x < m 2^32, with mont = -m^-1 mod 2^32
+// (Montgomery's reduction: x + (x mont mod R) m is divisible by R)
+__device__ __forceinline__ uint32_t redc(uint64_t x, uint32_t m, uint32_t mont) {
+    const uint32_t t = (uint32_t)x * mont;
+    return red1((uint32_t)((x + (uint64_t)t * m) >> 32), m);
 }
 
 __global__ __launch_bounds__(kNT) void bfv_rerandomize_kernel(BfvK K, uint32_t *__restrict__ ct,
@@ -486,16 +505,20 @@ __global__ __launch_bounds__(kNT) void bfv_rerandomize_kernel(BfvK K, uint32_t *
     __shared__ uint32_t a[3][kMaxN];
     const int n = K.n, tid = threadIdx.x;
     const int64_t ci = blockIdx.x;
+    // draw k = ((ct_index0 + ci) 3 + w) n + s + 1 of the generator seeded with
+    // seed_r: its state seed_r + k gamma stepped by n gamma per w and kNT gamma
+    // per r
     int32_t d[3][kPer];
+    const uint64_t z0 = seed_r + (((ct_index0 + (uint64_t)ci) * 3) * (uint64_t)n + (uint64_t)tid + 1) * kSplitGamma;
 #pragma unroll
     for (int w = 0; w < 3; ++w) {
         const uint32_t bound = w == 0 ? 1u : w == 1 ? kE1Bound : flood;
+        uint64_t z = z0 + (uint64_t)w * (uint64_t)n * kSplitGamma;
 #pragma unroll
         for (int r = 0; r < kPer; ++r) {
             const int s = tid + r * kNT;
-            if (s < n)
-                d[w][r] = draw(seed_r, ((ct_index0 + (uint64_t)ci) * 3 + (uint64_t)w) * (uint64_t)n + (uint64_t)s + 1,
-                               bound);
+            if (s < n) d[w][r] = draw_at(z, bound);
+            z += (uint64_t)kNT * kSplitGamma;
         }
     }
     for (int l = 0; l < 2; ++l) {
@@ -508,8 +531,14 @@ __global__ __launch_bounds__(kNT) void bfv_rerandomize_kernel(BfvK K, uint32_t *
                 const int s = tid + r * kNT;
                 if (s < n) {
                     const int32_t v = d[w][r];
-                    const uint32_t mag = mulsh((uint32_t)(v < 0 ? -v : v), 1u, K.one_sh[1 + l], m);
-                    a[w][s] = v < 0 ? red1(m - mag, m) : mag;
+                    if (w == 0) {
+                        // rho in {-1, 0, 1}, times R = 2^32 (Montgomery form for
+                        // the products below)
+                        a[w][s] = v == 0 ? 0u : v > 0 ? K.r32[l] : m - K.r32[l];
+                    } else {
+                        const uint32_t mag = mulsh((uint32_t)(v < 0 ? -v : v), 1u, K.one_sh[1 + l], m);
+                        a[w][s] = v < 0 ? red1(m - mag, m) : mag;
+                    }
                 }
             }
         __syncthreads();
@@ -518,9 +547,9 @@ __global__ __launch_bounds__(kNT) void bfv_rerandomize_kernel(BfvK K, uint32_t *
         const uint32_t *pa = pk + (size_t)l * 2 * n, *pb = pa + n;
         for (int s = tid; s < n; s += kNT) {
             const int i = brev(s, K.logn);
-            const uint32_t rho = a[0][i];
-            const uint32_t ta = mod64((uint64_t)pa[s] * rho, m, K.r32[l], K.r32_sh[l], K.one_sh[1 + l]);
-            const uint32_t tb = mod64((uint64_t)pb[s] * rho, m, K.r32[l], K.r32_sh[l], K.one_sh[1 + l]);
+            const uint32_t rho = a[0][i];  // NTT(rho) R mod m
+            const uint32_t ta = redc((uint64_t)pa[s] * rho, m, K.mont[l]);
+            const uint32_t tb = redc((uint64_t)pb[s] * rho, m, K.mont[l]);
             wa[s] = addm(addm(wa[s], ta, m), a[1][i], m);
             wb[s] = addm(addm(wb[s], tb, m), a[2][i], m);
         }
@@ -674,6 +703,9 @@ int ensei_bfv_ctx_create(ensei_bfv_ctx **out, uint32_t t, uint32_t q0, uint32_t 
         K.delta_sh[l] = companion(K.delta[l], m);
         K.r32[l] = (uint32_t)((((uint64_t)1) << 32) % m);
         K.r32_sh[l] = companion(K.r32[l], m);
+        uint32_t inv = m;  // m^-1 mod 2^32 by Newton's iteration (m odd: correct to 3 bits, doubling)
+        for (int it = 0; it < 5; ++it) inv *= 2u - m * inv;
+        K.mont[l] = 0u - inv;
     }
     K.q0inv = (uint32_t)h_powmod(q0 % q1, q1 - 2, q1);
     K.q0inv_sh = companion(K.q0inv, q1);
