@@ -90,6 +90,15 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
     return z ^ (z >> 31);
 }
 
+// A kernel's LDS (dynamic, sized at launch for the context's n): arrays of
+// n words one after another, a[w] the w-th
+extern __shared__ __attribute__((aligned(16))) uint32_t bfv_lds[];
+struct LdsArrays {
+    uint32_t *p;
+    int n;
+    __device__ uint32_t *operator[](int w) const { return p + w * n; }
+};
+
 __device__ __forceinline__ int brev(int x, int logn) { return (int)(__brev((uint32_t)x) >> (32 - logn)); }
 
 // In-place transform of a[0..n) in LDS mod md.m; modulus index mi selects
@@ -104,7 +113,7 @@ __device__ __forceinline__ int brev(int x, int logn) { return (int)(__brev((uint
 // The butterflies are Harvey's lazy ones (m < 2^30, so 4m fits 32 bits):
 // forward values stay in [0, 4m), inverse ones in [0, 2m), and the last
 // pass reduces them to [0, m).
-// na arrays a + v kMaxN (v < na) are transformed together, sharing them;
+// na arrays a + v n (v < na) are transformed together, sharing them;
 // array v under modulus index mi + v mstep (the same modulus, or one limb
 // per array).
 template <bool INV>
@@ -118,7 +127,7 @@ __device__ void ntt_lds(uint32_t *a, const BfvK &K, int mi, int na = 1, int mste
         const int ls = INV ? s0 : logn - s0 - R;
         for (int w = tid; w < (na << (logn - R)); w += kNT) {
             const int v = w >> (logn - R), mv = mi + v * mstep;  // array w / (n >> R), unit u of it
-            uint32_t *const av = a + v * kMaxN;
+            uint32_t *const av = a + v * n;
             const int u = w & ((n >> R) - 1);
             const uint32_t m = K.md[mv].m;
             const uint32_t *tw = K.tw + (size_t)mv * 4 * n + (INV ? 2 * n : 0);
@@ -187,8 +196,8 @@ __global__ __launch_bounds__(kNT) void bfv_encrypt_kernel(BfvK K, const uint32_t
                                                           const uint32_t *__restrict__ s_hat,
                                                           const int32_t *__restrict__ e, uint64_t seed_a,
                                                           uint64_t ct_index0, uint32_t *__restrict__ ct) {
-    __shared__ uint32_t a[2][kMaxN];  // one array per limb
     const int n = K.n, tid = threadIdx.x;
+    const LdsArrays a{bfv_lds, n};  // one array per limb
     const int64_t ci = blockIdx.x;
     const int64_t b = ci / ((int64_t)G * KC);
     const int rest = (int)(ci - b * G * KC), g = rest / KC, k = rest - g * KC;
@@ -242,8 +251,8 @@ __global__ __launch_bounds__(kNT) void bfv_encrypt_kernel(BfvK K, const uint32_t
 template <int MODE>
 __global__ __launch_bounds__(kNT) void bfv_encode_kernel(BfvK K, const void *__restrict__ src, int C, int64_t F, int P,
                                                          int Fp, int G, int KC, uint32_t *__restrict__ out) {
-    __shared__ uint32_t a[2][kMaxN];  // one array per limb
     const int n = K.n, tid = threadIdx.x;
+    const LdsArrays a{bfv_lds, n};  // one array per limb
     const int64_t vi = blockIdx.x;
     uint32_t u[kPer];
     int sgn[kPer];
@@ -444,8 +453,8 @@ __device__ __forceinline__ uint32_t round_tq(uint64_t phi, const BfvK &K) {
 __global__ __launch_bounds__(kNT) void bfv_decrypt_kernel(BfvK K, const uint32_t *__restrict__ ct,
                                                           const uint32_t *__restrict__ s_hat,
                                                           uint32_t *__restrict__ v) {
-    __shared__ uint32_t a[kMaxN];
     const int n = K.n, tid = threadIdx.x;
+    uint32_t *const a = bfv_lds;
     const int64_t ci = blockIdx.x;
     uint32_t r0[kPer];
     for (int l = 0; l < 2; ++l) {
@@ -502,8 +511,8 @@ __device__ __forceinline__ uint32_t redc(uint64_t x, uint32_t m, uint32_t mont) 
 __global__ __launch_bounds__(kNT) void bfv_rerandomize_kernel(BfvK K, uint32_t *__restrict__ ct,
                                                               const uint32_t *__restrict__ pk, uint64_t seed_r,
                                                               uint64_t ct_index0, uint32_t flood) {
-    __shared__ uint32_t a[3][kMaxN];
     const int n = K.n, tid = threadIdx.x;
+    const LdsArrays a{bfv_lds, n};  // the three draws
     const int64_t ci = blockIdx.x;
     // draw k = ((ct_index0 + ci) 3 + w) n + s + 1 of the generator seeded with
     // seed_r: its state seed_r + k gamma stepped by n gamma per w and kNT gamma
@@ -641,6 +650,9 @@ struct ensei_bfv_ctx {
 
 namespace {
 
+// dynamic LDS of a kernel holding `arrays` polynomials of the context's n words
+size_t lds_bytes(const ensei_bfv_ctx *ctx, int arrays) { return (size_t)arrays * ctx->K.n * sizeof(uint32_t); }
+
 int check_bfv(const ensei_bfv_ctx *ctx) {
     if (!ctx) return ENSEI_ERR_ARG;
     int dev = -1;
@@ -750,7 +762,7 @@ int ensei_bfv_key(ensei_bfv_ctx *ctx, const int8_t *s, uint32_t *s_hat, void *st
     if (!aligned4(s_hat)) return ENSEI_ERR_ALIGN;
     const int n = ctx->K.n;
     if (ensei::overlaps(s_hat, (size_t)4 * n * 4, s, n)) return ENSEI_ERR_OVERLAP;
-    hipLaunchKernelGGL(bfv_encode_kernel<2>, dim3(1), dim3(kNT), 0, (hipStream_t)stream, ctx->K, s, 1, (int64_t)1, 1,
+    hipLaunchKernelGGL(bfv_encode_kernel<2>, dim3(1), dim3(kNT), lds_bytes(ctx, 2), (hipStream_t)stream, ctx->K, s, 1, (int64_t)1, 1,
                        1, 1, 1, s_hat);
     return ensei::launch_status();
 }
@@ -770,7 +782,7 @@ int ensei_bfv_encrypt(ensei_bfv_ctx *ctx, const uint32_t *x_hat, int64_t B, int 
     if (ensei::overlaps(ct, ctb, x_hat, (size_t)B * C * F * 4) || ensei::overlaps(ct, ctb, s_hat, (size_t)4 * n * 4) ||
         ensei::overlaps(ct, ctb, e, (size_t)count * n * 4))
         return ENSEI_ERR_OVERLAP;
-    hipLaunchKernelGGL(bfv_encrypt_kernel, dim3((unsigned)count), dim3(kNT), 0, (hipStream_t)stream, ctx->K, x_hat, C,
+    hipLaunchKernelGGL(bfv_encrypt_kernel, dim3((unsigned)count), dim3(kNT), lds_bytes(ctx, 2), (hipStream_t)stream, ctx->K, x_hat, C,
                        F, gm.P, gm.Fp, gm.G, gm.KC, s_hat, e, seed_a, ct_index0, ct);
     return ensei::launch_status();
 }
@@ -786,7 +798,7 @@ int ensei_bfv_encode_filters(ensei_bfv_ctx *ctx, const uint32_t *w_hat, int Cout
     const int64_t count = (int64_t)Cout * gm.G * gm.KC, n = ctx->K.n;
     if (count > 0x7fffffff) return ENSEI_ERR_LIMIT;
     if (ensei::overlaps(w_enc, (size_t)count * 4 * n * 4, w_hat, (size_t)Cout * Cin * F * 4)) return ENSEI_ERR_OVERLAP;
-    hipLaunchKernelGGL(bfv_encode_kernel<0>, dim3((unsigned)count), dim3(kNT), 0, (hipStream_t)stream, ctx->K, w_hat,
+    hipLaunchKernelGGL(bfv_encode_kernel<0>, dim3((unsigned)count), dim3(kNT), lds_bytes(ctx, 2), (hipStream_t)stream, ctx->K, w_hat,
                        Cin, F, gm.P, gm.Fp, gm.G, gm.KC, w_enc);
     return ensei::launch_status();
 }
@@ -799,7 +811,7 @@ int ensei_bfv_encode_masks(ensei_bfv_ctx *ctx, const uint32_t *r, int64_t count,
     if (!aligned4(r) || !aligned4(mask_enc)) return ENSEI_ERR_ALIGN;
     const int64_t n = ctx->K.n;
     if (ensei::overlaps(mask_enc, (size_t)count * 2 * n * 4, r, (size_t)count * n * 4)) return ENSEI_ERR_OVERLAP;
-    hipLaunchKernelGGL(bfv_encode_kernel<1>, dim3((unsigned)count), dim3(kNT), 0, (hipStream_t)stream, ctx->K, r, 1,
+    hipLaunchKernelGGL(bfv_encode_kernel<1>, dim3((unsigned)count), dim3(kNT), lds_bytes(ctx, 2), (hipStream_t)stream, ctx->K, r, 1,
                        (int64_t)1, 1, 1, 1, 1, mask_enc);
     return ensei::launch_status();
 }
@@ -836,7 +848,7 @@ int ensei_bfv_decrypt(ensei_bfv_ctx *ctx, const uint32_t *ct, const uint32_t *s_
     if (ensei::overlaps(v, (size_t)count * n * 4, ct, (size_t)count * 4 * n * 4) ||
         ensei::overlaps(v, (size_t)count * n * 4, s_hat, (size_t)4 * n * 4))
         return ENSEI_ERR_OVERLAP;
-    hipLaunchKernelGGL(bfv_decrypt_kernel, dim3((unsigned)count), dim3(kNT), 0, (hipStream_t)stream, ctx->K, ct, s_hat,
+    hipLaunchKernelGGL(bfv_decrypt_kernel, dim3((unsigned)count), dim3(kNT), lds_bytes(ctx, 1), (hipStream_t)stream, ctx->K, ct, s_hat,
                        v);
     return ensei::launch_status();
 }
@@ -850,7 +862,7 @@ int ensei_bfv_rerandomize(ensei_bfv_ctx *ctx, uint32_t *ct, int64_t count, const
     if (!aligned4(ct) || !aligned4(pk)) return ENSEI_ERR_ALIGN;
     const int64_t n = ctx->K.n;
     if (ensei::overlaps(ct, (size_t)count * 4 * n * 4, pk, (size_t)4 * n * 4)) return ENSEI_ERR_OVERLAP;
-    hipLaunchKernelGGL(bfv_rerandomize_kernel, dim3((unsigned)count), dim3(kNT), 0, (hipStream_t)stream, ctx->K, ct, pk,
+    hipLaunchKernelGGL(bfv_rerandomize_kernel, dim3((unsigned)count), dim3(kNT), lds_bytes(ctx, 3), (hipStream_t)stream, ctx->K, ct, pk,
                        seed_r, ct_index0, flood);
     return ensei::launch_status();
 }
