@@ -7,8 +7,9 @@
 // LDS array: Cooley-Tukey (forward, natural in, bit-reversed out) and
 // Gentleman-Sande (inverse, bit-reversed in, natural out) butterflies with
 // the merged psi powers in bit-reversed order, Shoup multiplications by
-// precomputed companions, residues kept in [0, m). The layouts at the ABI
-// are natural slot order; the bit reversal happens on the LDS reads.
+// precomputed companions; residues enter and leave a transform in [0, m)
+// (inside it they stay lazily reduced). The layouts at the ABI are natural
+// slot order; the bit reversal happens on the LDS reads.
 #include <stdio.h>
 #include <string.h>
 
@@ -20,7 +21,7 @@
 namespace {
 
 constexpr int kNT = 256;          // threads per polynomial
-constexpr int kMaxN = 4096;       // ring degree limit (16 KB of LDS per polynomial)
+constexpr int kMaxN = 4096;       // ring degree limit (a polynomial's LDS array: 4 n bytes)
 constexpr int kPer = kMaxN / kNT; // coefficients per thread at most
 constexpr int kMods = 3;          // t, q0, q1
 
