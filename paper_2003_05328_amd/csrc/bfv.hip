@@ -116,9 +116,10 @@ __device__ __forceinline__ int brev(int x, int logn) { return (int)(__brev((uint
 // pass reduces them to [0, m).
 // na arrays a + v n (v < na) are transformed together, sharing them;
 // array v under modulus index mi + v mstep (the same modulus, or one limb
-// per array).
-template <bool INV>
-__device__ void ntt_lds(uint32_t *a, const BfvK &K, int mi, int na = 1, int mstep = 0) {
+// per array). JA > 1: groups of JA arrays of one modulus (mstep = 0) go
+// through a thread together, which reads each twiddle once for all of them.
+template <bool INV, int JA = 1>
+__device__ void ntt_lds(uint32_t *a, const BfvK &K, int mi, int na = JA, int mstep = 0) {
     const int n = K.n, logn = K.logn, tid = threadIdx.x;
     // stages s0 .. s0 + R - 1; LAST: the transform's last pass (forward:
     // reduce to [0, m); inverse: multiply by n^-1, which also reduces)
@@ -126,17 +127,21 @@ __device__ void ntt_lds(uint32_t *a, const BfvK &K, int mi, int na = 1, int mste
         constexpr int R = decltype(r_tag)::value, E = 1 << R;
         // log2 of the unit's stride: the group's smallest t
         const int ls = INV ? s0 : logn - s0 - R;
-        for (int w = tid; w < (na << (logn - R)); w += kNT) {
-            const int v = w >> (logn - R), mv = mi + v * mstep;  // array w / (n >> R), unit u of it
-            uint32_t *const av = a + v * n;
+        // item w: unit u of arrays v0 .. v0 + JA - 1 (JA > 1: one modulus,
+        // each twiddle read once for all of them)
+        for (int w = tid; w < ((na / JA) << (logn - R)); w += kNT) {
+            const int v0 = (w >> (logn - R)) * JA, mv = mi + v0 * mstep;
+            uint32_t *const av = a + v0 * n;
             const int u = w & ((n >> R) - 1);
             const uint32_t m = K.md[mv].m;
             const uint32_t *tw = K.tw + (size_t)mv * 4 * n + (INV ? 2 * n : 0);
             const uint32_t *tws = tw + n;
             const int blk = u >> ls, j0 = (blk << (ls + R)) + (u & ((1 << ls) - 1));
-            uint32_t x[E];
+            uint32_t x[JA][E];
 #pragma unroll
-            for (int k = 0; k < E; ++k) x[k] = av[j0 + (k << ls)];
+            for (int q = 0; q < JA; ++q)
+#pragma unroll
+                for (int k = 0; k < E; ++k) x[q][k] = av[q * n + j0 + (k << ls)];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int st = s0 + r;
@@ -149,27 +154,35 @@ __device__ void ntt_lds(uint32_t *a, const BfvK &K, int mi, int na = 1, int mste
                     // one twiddle in the group's first stage, 2^R / 2 in its last
                     const int i = INV ? (blk << (R - 1 - r)) + (k >> (r + 1)) : (blk << r) + (k >> (R - r));
                     const uint32_t S = __ldg(tw + base + i), Ssh = __ldg(tws + base + i);
-                    if (!INV) {
-                        // inputs in [0, 4m)
-                        const uint32_t U = red1(x[k], 2 * m);                // [0, 2m)
-                        const uint32_t V = mulsh_lazy(x[k + d], S, Ssh, m);  // [0, 2m)
-                        x[k] = U + V;                                        // [0, 4m)
-                        x[k + d] = U - V + 2 * m;                            // (0, 4m)
-                    } else {
-                        // inputs in [0, 2m)
-                        const uint32_t U = x[k], V = x[k + d];
-                        x[k] = red1(U + V, 2 * m);                           // [0, 2m)
-                        x[k + d] = mulsh_lazy(U - V + 2 * m, S, Ssh, m);     // [0, 2m)
+#pragma unroll
+                    for (int q = 0; q < JA; ++q) {
+                        if (!INV) {
+                            // inputs in [0, 4m)
+                            const uint32_t U = red1(x[q][k], 2 * m);                // [0, 2m)
+                            const uint32_t V = mulsh_lazy(x[q][k + d], S, Ssh, m);  // [0, 2m)
+                            x[q][k] = U + V;                                        // [0, 4m)
+                            x[q][k + d] = U - V + 2 * m;                            // (0, 4m)
+                        } else {
+                            // inputs in [0, 2m)
+                            const uint32_t U = x[q][k], V = x[q][k + d];
+                            x[q][k] = red1(U + V, 2 * m);                           // [0, 2m)
+                            x[q][k + d] = mulsh_lazy(U - V + 2 * m, S, Ssh, m);     // [0, 2m)
+                        }
                     }
                 }
             }
             if (last) {
 #pragma unroll
-                for (int k = 0; k < E; ++k)
-                    x[k] = INV ? mulsh(x[k], K.md[mv].ninv, K.md[mv].ninv_sh, m) : red1(red1(x[k], 2 * m), m);
+                for (int q = 0; q < JA; ++q)
+#pragma unroll
+                    for (int k = 0; k < E; ++k)
+                        x[q][k] = INV ? mulsh(x[q][k], K.md[mv].ninv, K.md[mv].ninv_sh, m)
+                                      : red1(red1(x[q][k], 2 * m), m);
             }
 #pragma unroll
-            for (int k = 0; k < E; ++k) av[j0 + (k << ls)] = x[k];
+            for (int q = 0; q < JA; ++q)
+#pragma unroll
+                for (int k = 0; k < E; ++k) av[q * n + j0 + (k << ls)] = x[q][k];
         }
         __syncthreads();
     };
@@ -552,7 +565,7 @@ __global__ __launch_bounds__(kNT) void bfv_rerandomize_kernel(BfvK K, uint32_t *
                 }
             }
         __syncthreads();
-        ntt_lds<false>(a[0], K, 1 + l, 3);  // the three draws together
+        ntt_lds<false, 3>(a[0], K, 1 + l);  // the three draws together, one twiddle read for the three
         uint32_t *wa = ct + ((ci * 2 + l) * 2) * (int64_t)n, *wb = wa + n;
         const uint32_t *pa = pk + (size_t)l * 2 * n, *pb = pa + n;
         for (int s = tid; s < n; s += kNT) {
